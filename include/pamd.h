@@ -1,0 +1,215 @@
+/*
+ * pamd.h -- C ABI of the MI355X (gfx950) population-annealing MD library (libpamd.so).
+ *
+ * The calls follow the numbered population-annealing MD (PAMD) scheme of
+ * Christiansen, Weigel & Janke, "Accelerating molecular dynamics simulations
+ * with population annealing" (arXiv:1806.06016):
+ *
+ *   step 1  set up R independent copies at a high temperature T0  -> pamd_init
+ *                                                                     (+ pamd_md_steps at T0)
+ *   step 2  resample to T_i < T_{i-1} with weights
+ *           tau_j = exp(-(1/kB T_i - 1/kB T_{i-1}) E_j) / Q,
+ *           Q = (1/R) sum_j exp(-(1/kB T_i - 1/kB T_{i-1}) E_j),
+ *           velocities rescaled by sqrt(T_i / T_{i-1})             -> pamd_resample
+ *   step 3  theta MD steps per copy                                 -> pamd_md_steps
+ *   step 4  observables as population averages                     -> pamd_observables
+ *   step 5  loop until T_i <= T_N                                    (the caller)
+ *
+ * The free energy follows from the recorded normalisers: ln Q_i estimates
+ * ln Z(T_i) - ln Z(T_{i-1}) (the paragraph on the recorded Q values); the
+ * library accumulates sum_i ln Q_i in FP64 on the device.
+ *
+ * Conventions for every call
+ *  - Returns a pamd_status; PAMD_OK == 0.  Nothing aborts or prints.  After an
+ *    error the context's message is available from pamd_last_error(); device
+ *    detected errors (non-finite energies, population over capacity) are
+ *    sticky in device memory and surface at the next synchronising call
+ *    (pamd_observables, pamd_get_*), after which the context refuses further
+ *    work until pamd_destroy().
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    pamd_md_steps and pamd_resample only enqueue work (asynchronous, no host
+ *    synchronisation, capturable into a HIP graph); pamd_init, pamd_observables
+ *    and the pamd_get_* / pamd_set_* calls synchronise `stream`.
+ *  - Host arrays passed in are only read during the call (copied).
+ *  - Device memory: the caller allocates `d_state` and `d_work` (sizes from
+ *    pamd_query_sizes, 256-byte aligned) and keeps them alive until
+ *    pamd_destroy(); the library allocates no device memory.
+ */
+#ifndef PAMD_H
+#define PAMD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t pamd_status;
+enum {
+    PAMD_OK = 0,
+    PAMD_ERR_ARG = 1,        /* null pointer, size mismatch, index out of range, unsupported size */
+    PAMD_ERR_HIP = 2,        /* a HIP runtime call failed; message holds hipGetErrorString */
+    PAMD_ERR_CAPACITY = 3,   /* resampled population larger than R_cap (or extinct) */
+    PAMD_ERR_NONFINITE = 4,  /* NaN / Inf potential energy */
+    PAMD_ERR_STATE = 5       /* call-order violation or context already failed */
+};
+
+enum { PAMD_FP64 = 0, PAMD_FP32 = 1 };
+enum { PAMD_DIELECTRIC_VACUUM = 0, PAMD_DIELECTRIC_4R = 1 };
+
+#define PAMD_MAX_ATOMS 80    /* 16-lane tiles of atoms held in registers: N <= 5 x 16 */
+#define PAMD_FORCE_CHUNK 256 /* replicas per pamd_get_forces call */
+
+/*
+ * One molecule (host pointers; all arrays row-major).  Functional form:
+ *   bonds      U = 1/2 k (r - r0)^2
+ *   angles     U = 1/2 k (theta - theta0)^2                        (theta0 in radians)
+ *   dihedrals  U = k (1 + cos(n phi - delta)), delta in {0, pi} (within 1e-9 rad)
+ *   LJ         U = s 4 eps_ij ((sigma_ij / r)^12 - (sigma_ij / r)^6),
+ *              sigma_ij = (sigma_i + sigma_j) / 2, eps_ij = sqrt(eps_i eps_j)
+ *   Coulomb    U = s k_e q_i q_j / r          (dielectric PAMD_DIELECTRIC_VACUUM)
+ *              U = s k_e q_i q_j / (4 r^2)    (PAMD_DIELECTRIC_4R: eps(r) = 4 r)
+ * Nonbonded pairs: every i < j except 1-2 and 1-3 pairs of the bond graph;
+ * 1-4 pairs (three bonds apart) take s = scale14_lj / scale14_coul, others s = 1.
+ * Units are the caller's (kB and coulomb_k set them).
+ */
+typedef struct pamd_system {
+    int32_t n_atoms;               /* 1 .. PAMD_MAX_ATOMS */
+    int32_t n_bonds, n_angles, n_dihedrals;
+    const double* mass;            /* [n_atoms] > 0 */
+    const double* charge;          /* [n_atoms] */
+    const double* sigma;           /* [n_atoms] */
+    const double* epsilon;         /* [n_atoms] >= 0 */
+    const int32_t* bond_idx;       /* [n_bonds][2] */
+    const double* bond_k;          /* [n_bonds] */
+    const double* bond_r0;         /* [n_bonds] */
+    const int32_t* angle_idx;      /* [n_angles][3]  (i, centre, k) */
+    const double* angle_k;
+    const double* angle_theta0;
+    const int32_t* dih_idx;        /* [n_dihedrals][4] */
+    const double* dih_k;
+    const int32_t* dih_n;          /* multiplicity 1..6 */
+    const double* dih_delta;
+    double scale14_lj, scale14_coul;
+    double coulomb_k;
+    int32_t dielectric;            /* PAMD_DIELECTRIC_* */
+    int32_t reserved;
+    double kB;                     /* Boltzmann constant in the caller's units */
+    const double* x_init;          /* [n_atoms][3] start configuration of every copy */
+} pamd_system;
+
+/* Run parameters. */
+typedef struct pamd_params {
+    int64_t R_target;              /* population size R (expected copies sum to it) */
+    int64_t R_cap;                 /* slots per buffer, >= R_target (fluctuation headroom) */
+    double T0;                     /* initial temperature */
+    double dt;                     /* MD time step */
+    double nu;                     /* Andersen collision frequency (0: NVE) */
+    uint64_t seed;                 /* Philox key = (seed_lo, seed_hi + run) */
+    int32_t precision;             /* PAMD_FP32 (positions, velocities, forces FP32) or PAMD_FP64 */
+    int32_t waves_per_block;       /* 0: automatic; else 1..16 (autotuner override) */
+    double V_target;               /* adaptive schedule: normalised weight variance per step */
+    double T_final;                /* adaptive schedule: lowest temperature T_N */
+} pamd_params;
+
+/* Population observables of one run (PAMD step 4), all FP64. */
+typedef struct pamd_obs {
+    double T;                      /* current bath temperature T_i */
+    double T_prev;                 /* previous temperature T_{i-1} */
+    double lnQ_last;               /* ln Q_i of the last resampling */
+    double sum_lnQ;                /* sum_i ln Q_i = estimate of ln Z(T_i) - ln Z(T_0) */
+    double V_last;                 /* normalised weight variance R sum p_j^2 - 1 of the last step */
+    double E_mean;                 /* <E_pot> */
+    double E2_mean;                /* <E_pot^2> */
+    double K_mean;                 /* <E_kin> */
+    double T_measured;             /* 2 <E_kin> / (3 N kB) */
+    double Cv;                     /* (<E^2> - <E>^2) / (kB T^2)  (heat capacity / kB ... in kB units) */
+    int64_t R;                     /* current population size R_i */
+    int64_t families;              /* distinct ancestors among the R_i copies */
+    int64_t temp_index;            /* i */
+    int64_t step;                  /* MD steps done since pamd_init */
+    int32_t error;                 /* sticky device error code (PAMD_ERR_*) or 0 */
+    int32_t reserved;
+} pamd_obs;
+
+typedef struct pamd_ctx pamd_ctx;
+
+/* Device bytes needed for `n_runs` independent runs (sys[n_runs], p[n_runs]).
+ * Pure host function. */
+pamd_status pamd_query_sizes(const pamd_system* sys, int32_t n_runs, const pamd_params* p,
+                             size_t* state_bytes, size_t* work_bytes);
+
+/* PAMD step 1.  Copies topology and parameters to the device, derives the
+ * exclusion / 1-4 lists from the bonds, builds the pair-parameter tables,
+ * fills R_target slots per run with x_init and Maxwell-Boltzmann(T0)
+ * velocities (Philox stream 3), ancestor = slot.  Equilibration at T0 is the
+ * caller's pamd_md_steps.  Synchronises `stream`. */
+pamd_status pamd_init(const pamd_system* sys, int32_t n_runs, const pamd_params* p,
+                      void* d_state, size_t state_bytes, void* d_work, size_t work_bytes,
+                      void* stream, pamd_ctx** out);
+
+/* PAMD step 3.  n_steps >= 0 NVT velocity-Verlet steps (Andersen collisions
+ * after each step) of every copy of every run at the run's current T; leaves
+ * E_pot and E_kin of the final configurations (n_steps = 0 only evaluates
+ * them).  Asynchronous. */
+pamd_status pamd_md_steps(pamd_ctx* ctx, int32_t n_steps, void* stream);
+
+/* PAMD step 2.  T_next: host [n_runs]; T_next[r] > 0 is the next temperature
+ * of run r, T_next[r] <= 0 (or T_next == NULL) chooses it adaptively (largest
+ * step with normalised weight variance <= V_target, not below T_final).
+ * d_uniforms: device [n_runs][R_cap] doubles in [0,1) for the rounding draws,
+ * or NULL to draw them from Philox stream 2.  Copy numbers are
+ * c_j = floor(tau_j) + [u_j < frac(tau_j)] with tau_j = R_target w_j / sum w;
+ * copies of source j take consecutive new slots in increasing j; velocities
+ * are scaled by sqrt(T_i / T_{i-1}) and each copy is translated so its centre
+ * of mass sits at the origin.  Asynchronous; an over-capacity population
+ * leaves the state unchanged and raises PAMD_ERR_CAPACITY at the next sync. */
+pamd_status pamd_resample(pamd_ctx* ctx, const double* T_next, const double* d_uniforms,
+                          void* stream);
+
+/* PAMD step 4.  out: host [n_runs].  Synchronises `stream`. */
+pamd_status pamd_observables(pamd_ctx* ctx, pamd_obs* out, void* stream);
+
+/* ---- inspection / checkpoint calls (synchronising) ---------------------- */
+
+/* Forces and potential energies at the current positions of replicas
+ * [r0, r0 + count) of `run`, count <= PAMD_FORCE_CHUNK.
+ * host_F: [count][n_atoms][3], host_E: [count] (either may be NULL). */
+pamd_status pamd_get_forces(pamd_ctx* ctx, int32_t run, int64_t r0, int32_t count,
+                            double* host_F, double* host_E, void* stream);
+
+/* Per-run scalars that travel with a checkpoint. */
+typedef struct pamd_run_scalars {
+    double T, T_prev, sum_lnQ, lnQ_last;
+    int64_t R;
+    uint32_t step, temp_index;
+} pamd_run_scalars;
+
+/* Copy the current population of `run` to the host.  Arrays have room for
+ * R_cap replicas; x, v: [R][n_atoms][3]; E_pot, E_kin: [R]; ancestor: [R].
+ * Any pointer may be NULL. */
+pamd_status pamd_get_state(pamd_ctx* ctx, int32_t run, double* x, double* v, double* E_pot,
+                           double* E_kin, int32_t* ancestor, pamd_run_scalars* scalars,
+                           void* stream);
+
+/* Replace the population of `run` (R = scalars->R <= R_cap copies).  x, v
+ * required; E_pot and ancestor optional (NULL: zeros / slot index). */
+pamd_status pamd_set_state(pamd_ctx* ctx, int32_t run, const double* x, const double* v,
+                           const double* E_pot, const int32_t* ancestor,
+                           const pamd_run_scalars* scalars, void* stream);
+
+/* Copy numbers c_j of the last resampling of `run` (host [R_{i-1}]). */
+pamd_status pamd_get_counts(pamd_ctx* ctx, int32_t run, int32_t* host_c, int64_t* n, void* stream);
+
+/* Launch shape chosen at init: waves per workgroup and workgroups (informational). */
+pamd_status pamd_launch_info(const pamd_ctx* ctx, int32_t* waves_per_block, int32_t* blocks,
+                             int32_t* lds_bytes);
+
+void pamd_destroy(pamd_ctx* ctx);
+const char* pamd_last_error(const pamd_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PAMD_H */

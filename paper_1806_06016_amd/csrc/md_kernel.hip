@@ -1,0 +1,772 @@
+// PAMD step 3 on gfx950: theta NVT velocity-Verlet steps (Andersen
+// collisions) for every replica of a run, in one persistent launch.
+//
+// Mapping (CDNA wave64):
+//   * one replica per 16-lane DPP row, four replicas per wavefront; lane l of a
+//     row owns atoms a = 16 s + l (s < NS) and keeps their positions,
+//     velocities and forces in VGPRs for all theta steps (HBM is touched once
+//     per replica per call);
+//   * all-pairs nonbonded forces as 16 x 16 tiles: in tile (I, J) step k lane
+//     l pairs atom 16 I + l with atom 16 J + ((l - k) mod 16), read from the
+//     neighbour lane with a DPP row rotation folded into the VALU operand;
+//     the reaction force returns by the opposite rotation (Newton's third
+//     law, every unordered pair evaluated once);
+//   * per-(tile, step, lane) pair coefficients (LJ 12 c12, -6 c6 and the
+//     Coulomb factor with exclusions / 1-4 scaling folded in) sit in LDS,
+//     shared by every replica of the workgroup;
+//   * bonded terms: positions are staged in a per-replica LDS slice, each
+//     lane evaluates one term per pass and scatters its forces with LDS
+//     float atomics;
+//   * persistent workgroups pull groups of four replicas from a device work
+//     counter, so the launch needs no host-side knowledge of R.
+//
+// Functional form (the paper uses AMBER ff94): harmonic bonds and angles,
+// Fourier dihedrals with delta in {0, pi} evaluated through Chebyshev
+// polynomials of cos(phi), LJ + Coulomb (1/r or eps(r) = 4 r).
+#include <type_traits>
+#include <utility>
+
+#include "pamd_internal.h"
+#include "philox.h"
+
+namespace pamd {
+
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f)
+{
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
+// lane l of a 16-lane row receives the value of lane (l - K) mod 16
+template <int K>
+__device__ __forceinline__ float rowrot(float v)
+{
+    if constexpr (K == 0) {
+        return v;
+    } else {
+        // bound_ctrl set: no lane of a rotation is out of bounds, and it lets the
+        // compiler fold the move into the consuming VALU instruction (DPP operand)
+        return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x120 + K,
+                                                                  0xF, 0xF, true));
+    }
+}
+template <int K>
+__device__ __forceinline__ double rowrot(double v)
+{
+    if constexpr (K == 0) {
+        return v;
+    } else {
+        const uint64_t u = __builtin_bit_cast(uint64_t, v);
+        const int lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)u, 0x120 + K, 0xF, 0xF, true);
+        const int hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), 0x120 + K, 0xF, 0xF, true);
+        return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+    }
+}
+
+__device__ __forceinline__ float rcp_(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp_(double x) { return 1.0 / x; }
+__device__ __forceinline__ float rsq_(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsq_(double x) { return 1.0 / sqrt(x); }
+__device__ __forceinline__ float sqrt_(float x) { return __builtin_sqrtf(x); }
+__device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
+__device__ __forceinline__ float atan2_(float y, float x) { return atan2f(y, x); }
+__device__ __forceinline__ double atan2_(double y, double x) { return atan2(y, x); }
+__device__ __forceinline__ float log_(float x) { return logf(x); }
+__device__ __forceinline__ double log_(double x) { return log(x); }
+__device__ __forceinline__ void sincos_(float a, float* s, float* c) { sincosf(a, s, c); }
+__device__ __forceinline__ void sincos_(double a, double* s, double* c) { sincos(a, s, c); }
+
+// LDS ordering between lanes of one wavefront (no workgroup barrier: waves
+// of a block run independent work items)
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename real>
+__device__ __forceinline__ void lds_add(real* p, real v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Tile schedule, column-major over blocks: for block J, first its diagonal
+// block (rotations k = 1..8), then for every rotation k = 0..15 the blocks
+// I < J (so the rotated copy of block J is formed once per (J, k)).
+__host__ __device__ constexpr int col_base(int J)
+{
+    int b = 0;
+    for (int q = 0; q < J; ++q)
+        b += 8 + 16 * q;
+    return b;
+}
+
+template <typename real, int NS>
+struct Regs {
+    real x[NS], y[NS], z[NS];
+    real vx[NS], vy[NS], vz[NS];
+    real fx[NS], fy[NS], fz[NS];
+};
+
+// ---------------------------------------------------------------------------
+// nonbonded pair step: pair (atom of lane l in block I, atom of lane l-K in block J)
+// ---------------------------------------------------------------------------
+template <typename real, int DIEL, int KBACK, bool ENERGY>
+__device__ __forceinline__ void pair_step(real xi, real yi, real zi, real xjr, real yjr, real zjr,
+                                          real& fxi, real& fyi, real& fzi, real& fxj, real& fyj,
+                                          real& fzj, const real* ab, const real* cc, double& eacc)
+{
+    // (xjr, yjr, zjr): position of the partner atom, already rotated to this lane
+    const real A = ab[0];    // 12 c12 s
+    const real nB = ab[1];   // -6 c6 s
+    const real C = cc[0];    // Coulomb factor (2 k q q s / 4 for eps = 4r; k q q s for 1/r)
+    const real dx = xjr - xi;
+    const real dy = yjr - yi;
+    const real dz = zjr - zi;
+    const real r2 = dx * dx + dy * dy + dz * dz;
+    if constexpr (ENERGY) {
+        const real ir2 = rcp_(r2);
+        const real ir6 = ir2 * ir2 * ir2;
+        const real ulj = ir6 * (A * (real)(1.0 / 12.0) * ir6 + nB * (real)(1.0 / 6.0));
+        real uc;
+        if constexpr (DIEL == 1)
+            uc = (real)0.5 * C * ir2;
+        else
+            uc = C * rsq_(r2);
+        eacc += (double)ulj + (double)uc;
+    } else {
+        real fs;
+        if constexpr (DIEL == 1) {
+            const real ir2 = rcp_(r2);
+            const real ir4 = ir2 * ir2;
+            const real ir6 = ir4 * ir2;
+            const real t1 = A * ir6 + nB;
+            fs = (t1 * ir4 + C) * ir4;
+        } else {
+            const real ir = rsq_(r2);
+            const real ir2 = ir * ir;
+            const real ir4 = ir2 * ir2;
+            const real ir6 = ir4 * ir2;
+            const real t1 = A * ir6 + nB;
+            fs = t1 * ir4 * ir4 + C * ir2 * ir;
+        }
+        // force on i = fs (x_i - x_j) = -fs d ; on j = +fs d, returned to the
+        // lane that owns j by the opposite rotation
+        const real tx = fs * dx, ty = fs * dy, tz = fs * dz;
+        fxi -= tx;
+        fyi -= ty;
+        fzi -= tz;
+        fxj += rowrot<KBACK>(tx);
+        fyj += rowrot<KBACK>(ty);
+        fzj += rowrot<KBACK>(tz);
+    }
+}
+
+template <typename real, int NS, int DIEL, bool ENERGY>
+__device__ __forceinline__ void nonbonded(Regs<real, NS>& r, const real* tab_ab, const real* tab_c, int l16,
+                                          double& eacc)
+{
+    static_for<0, NS>([&](auto Jc) {
+        constexpr int J = decltype(Jc)::value;
+        constexpr int base = col_base(J);
+        // diagonal block J: rotations 1..8 (rotation 8 pairs each atom twice; the
+        // table masks lanes 8..15)
+        static_for<1, 9>([&](auto Kc) {
+            constexpr int K = decltype(Kc)::value;
+            constexpr int st = base + K - 1;
+            pair_step<real, DIEL, (16 - K) & 15, ENERGY>(
+                r.x[J], r.y[J], r.z[J], rowrot<K>(r.x[J]), rowrot<K>(r.y[J]), rowrot<K>(r.z[J]), r.fx[J],
+                r.fy[J], r.fz[J], r.fx[J], r.fy[J], r.fz[J], tab_ab + (st * 16 + l16) * 2,
+                tab_c + st * 16 + l16, eacc);
+            // one pair step per scheduling region: the steps are independent up
+            // to the force sums, and an unbounded window hoists the displacement
+            // math of many steps into spilled registers
+            __builtin_amdgcn_sched_barrier(0);
+        });
+        // blocks I < J against block J rotated by K
+        static_for<0, 16>([&](auto Kc) {
+            constexpr int K = decltype(Kc)::value;
+            const real xr = rowrot<K>(r.x[J]), yr = rowrot<K>(r.y[J]), zr = rowrot<K>(r.z[J]);
+            static_for<0, J>([&](auto Ic) {
+                constexpr int I = decltype(Ic)::value;
+                constexpr int st = base + 8 + K * J + I;
+                pair_step<real, DIEL, (16 - K) & 15, ENERGY>(r.x[I], r.y[I], r.z[I], xr, yr, zr, r.fx[I], r.fy[I],
+                                                             r.fz[I], r.fx[J], r.fy[J], r.fz[J],
+                                                             tab_ab + (st * 16 + l16) * 2, tab_c + st * 16 + l16,
+                                                             eacc);
+                __builtin_amdgcn_sched_barrier(0);
+            });
+        });
+    });
+}
+
+// ---------------------------------------------------------------------------
+// bonded terms on the LDS stage of one replica (pos, frc: [n][3])
+// ---------------------------------------------------------------------------
+template <typename real>
+__device__ __forceinline__ void ld3(const real* p, int a, real* v)
+{
+    v[0] = p[3 * a];
+    v[1] = p[3 * a + 1];
+    v[2] = p[3 * a + 2];
+}
+
+template <typename real, bool ENERGY>
+__device__ __forceinline__ void add3(real* frc, int a, real fx, real fy, real fz)
+{
+    if constexpr (!ENERGY) {
+        lds_add(&frc[3 * a], fx);
+        lds_add(&frc[3 * a + 1], fy);
+        lds_add(&frc[3 * a + 2], fz);
+    }
+}
+
+template <typename real, bool ENERGY>
+__device__ __forceinline__ void bonded_terms(const RunDev<real>& d, const real* pos, real* frc, int l16, double& eacc)
+{
+    // bonds: U = 1/2 k (r - r0)^2
+    for (int t0 = 0; t0 < d.nb; t0 += kRow) {
+        const int t = t0 + l16;
+        if (t < d.nb) {
+            const int4 ix = d.bidx[t];
+            const real k = d.bpar[2 * t], r0 = d.bpar[2 * t + 1];
+            real pi[3], pj[3];
+            ld3(pos, ix.x, pi);
+            ld3(pos, ix.y, pj);
+            const real dx = pi[0] - pj[0], dy = pi[1] - pj[1], dz = pi[2] - pj[2];
+            const real r2 = dx * dx + dy * dy + dz * dz;
+            if constexpr (ENERGY) {
+                const real dr = sqrt_(r2) - r0;
+                eacc += (double)((real)0.5 * k * dr * dr);
+            } else {
+                // -dU/dx_i = -k (r - r0) d / r = -k (1 - r0 / r) d
+                const real g = (r0 == (real)0) ? k : k * ((real)1 - r0 * rsq_(r2));
+                add3<real, ENERGY>(frc, ix.x, -g * dx, -g * dy, -g * dz);
+                add3<real, ENERGY>(frc, ix.y, g * dx, g * dy, g * dz);
+            }
+        }
+    }
+    // angles: U = 1/2 k (theta - theta0)^2, theta = atan2(|u x w|, u.w)
+    for (int t0 = 0; t0 < d.na; t0 += kRow) {
+        const int t = t0 + l16;
+        if (t < d.na) {
+            const int4 ix = d.aidx[t];
+            const real k = d.apar[2 * t], th0 = d.apar[2 * t + 1];
+            real pi[3], pj[3], pk[3];
+            ld3(pos, ix.x, pi);
+            ld3(pos, ix.y, pj);
+            ld3(pos, ix.z, pk);
+            const real ux = pi[0] - pj[0], uy = pi[1] - pj[1], uz = pi[2] - pj[2];
+            const real wx = pk[0] - pj[0], wy = pk[1] - pj[1], wz = pk[2] - pj[2];
+            const real cx = uy * wz - uz * wy, cy = uz * wx - ux * wz, cz = ux * wy - uy * wx;
+            const real sn = sqrt_(cx * cx + cy * cy + cz * cz);
+            const real cs = ux * wx + uy * wy + uz * wz;
+            const real th = atan2_(sn, cs);
+            const real dth = th - th0;
+            if constexpr (ENERGY) {
+                eacc += (double)((real)0.5 * k * dth * dth);
+            } else {
+                const real iu = rsq_(ux * ux + uy * uy + uz * uz);
+                const real iw = rsq_(wx * wx + wy * wy + wz * wz);
+                const real cost = cs * iu * iw;
+                real sint = sn * iu * iw;
+                sint = sint < (real)1e-8 ? (real)1e-8 : sint;
+                const real g = k * dth * rcp_(sint);
+                // F_i = -k dth (cos u^ - w^) / (|u| sin) ; F_k likewise ; F_j = -(F_i + F_k)
+                const real gi = g * iu, gk = g * iw;
+                const real fix = -gi * (cost * ux * iu - wx * iw);
+                const real fiy = -gi * (cost * uy * iu - wy * iw);
+                const real fiz = -gi * (cost * uz * iu - wz * iw);
+                const real fkx = -gk * (cost * wx * iw - ux * iu);
+                const real fky = -gk * (cost * wy * iw - uy * iu);
+                const real fkz = -gk * (cost * wz * iw - uz * iu);
+                add3<real, ENERGY>(frc, ix.x, fix, fiy, fiz);
+                add3<real, ENERGY>(frc, ix.z, fkx, fky, fkz);
+                add3<real, ENERGY>(frc, ix.y, -(fix + fkx), -(fiy + fky), -(fiz + fkz));
+            }
+        }
+    }
+    // dihedrals: U = kc (1 + cos(n phi)) with kc = k cos(delta), delta in {0, pi}
+    for (int t0 = 0; t0 < d.nd; t0 += kRow) {
+        const int t = t0 + l16;
+        if (t < d.nd) {
+            const int4 ix = d.didx[t];
+            const real kc = d.dpar[2 * t];
+            const int nmul = (int)d.dpar[2 * t + 1];
+            real pi[3], pj[3], pk[3], pl[3];
+            ld3(pos, ix.x, pi);
+            ld3(pos, ix.y, pj);
+            ld3(pos, ix.z, pk);
+            ld3(pos, ix.w, pl);
+            const real b1x = pj[0] - pi[0], b1y = pj[1] - pi[1], b1z = pj[2] - pi[2];
+            const real b2x = pk[0] - pj[0], b2y = pk[1] - pj[1], b2z = pk[2] - pj[2];
+            const real b3x = pl[0] - pk[0], b3y = pl[1] - pk[1], b3z = pl[2] - pk[2];
+            const real n1x = b1y * b2z - b1z * b2y, n1y = b1z * b2x - b1x * b2z, n1z = b1x * b2y - b1y * b2x;
+            const real n2x = b2y * b3z - b2z * b3y, n2y = b2z * b3x - b2x * b3z, n2z = b2x * b3y - b2y * b3x;
+            real n1sq = n1x * n1x + n1y * n1y + n1z * n1z;
+            real n2sq = n2x * n2x + n2y * n2y + n2z * n2z;
+            n1sq = n1sq < (real)1e-30 ? (real)1e-30 : n1sq;
+            n2sq = n2sq < (real)1e-30 ? (real)1e-30 : n2sq;
+            const real b2sq = b2x * b2x + b2y * b2y + b2z * b2z;
+            const real lb2 = sqrt_(b2sq);
+            const real inn = rsq_(n1sq * n2sq);
+            const real c = (n1x * n2x + n1y * n2y + n1z * n2z) * inn;             // cos phi
+            const real s = lb2 * (b1x * n2x + b1y * n2y + b1z * n2z) * inn;       // sin phi
+            // Chebyshev: T_n(c) = cos(n phi), U_{n-1}(c) = sin(n phi) / sin(phi)
+            real tp = (real)1, tc = c, up = (real)0, uc = (real)1;
+            for (int q = 1; q < nmul; ++q) {
+                const real tn = (real)2 * c * tc - tp;
+                const real un = (real)2 * c * uc - up;
+                tp = tc;
+                tc = tn;
+                up = uc;
+                uc = un;
+            }
+            if constexpr (ENERGY) {
+                eacc += (double)(kc * ((real)1 + tc));
+            } else {
+                // dU/dphi = -kc n sin(n phi) = -kc n sin(phi) U_{n-1}(cos phi)
+                const real dU = -kc * (real)nmul * s * uc;
+                const real ai = -lb2 * rcp_(n1sq);
+                const real al = lb2 * rcp_(n2sq);
+                const real gix = ai * n1x, giy = ai * n1y, giz = ai * n1z;   // d phi / d x_i
+                const real glx = al * n2x, gly = al * n2y, glz = al * n2z;   // d phi / d x_l
+                const real ib2 = rcp_(b2sq);
+                const real p = (b1x * b2x + b1y * b2y + b1z * b2z) * ib2;
+                const real q = (b3x * b2x + b3y * b2y + b3z * b2z) * ib2;
+                const real gjx = (-(real)1 - p) * gix + q * glx, gjy = (-(real)1 - p) * giy + q * gly,
+                           gjz = (-(real)1 - p) * giz + q * glz;
+                const real gkx = p * gix + (-(real)1 - q) * glx, gky = p * giy + (-(real)1 - q) * gly,
+                           gkz = p * giz + (-(real)1 - q) * glz;
+                add3<real, ENERGY>(frc, ix.x, -dU * gix, -dU * giy, -dU * giz);
+                add3<real, ENERGY>(frc, ix.y, -dU * gjx, -dU * gjy, -dU * gjz);
+                add3<real, ENERGY>(frc, ix.z, -dU * gkx, -dU * gky, -dU * gkz);
+                add3<real, ENERGY>(frc, ix.w, -dU * glx, -dU * gly, -dU * glz);
+            }
+        }
+    }
+}
+
+template <typename real, int NS, int DIEL, bool ENERGY>
+__device__ __forceinline__ void evaluate(Regs<real, NS>& r, const RunDev<real>& d, const real* tab_ab,
+                                         const real* tab_c, real* pos, real* frc, int l16, double& eacc)
+{
+    if constexpr (!ENERGY) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            r.fx[s] = (real)0;
+            r.fy[s] = (real)0;
+            r.fz[s] = (real)0;
+        }
+    }
+    // stage positions for the bonded terms
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int a = 16 * s + l16;
+        if (a < d.n) {
+            pos[3 * a] = r.x[s];
+            pos[3 * a + 1] = r.y[s];
+            pos[3 * a + 2] = r.z[s];
+        }
+    }
+    wave_sync();
+    // bonded terms first: their LDS atomics complete while the register-only
+    // nonbonded tiles run
+    bonded_terms<real, ENERGY>(d, pos, frc, l16, eacc);
+    nonbonded<real, NS, DIEL, ENERGY>(r, tab_ab, tab_c, l16, eacc);
+    if constexpr (!ENERGY) {
+        // materialise the pair-force sums here (otherwise the sums are sunk to
+        // their use and every pair's partial force stays live)
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+            asm volatile("" : "+v"(r.fx[s]), "+v"(r.fy[s]), "+v"(r.fz[s]));
+        wave_sync();
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int a = 16 * s + l16;
+            if (a < d.n) {
+                r.fx[s] += frc[3 * a];
+                r.fy[s] += frc[3 * a + 1];
+                r.fz[s] += frc[3 * a + 2];
+                frc[3 * a] = (real)0;
+                frc[3 * a + 1] = (real)0;
+                frc[3 * a + 2] = (real)0;
+            }
+        }
+    }
+}
+
+template <typename real>
+__device__ __forceinline__ double row_sum(double v)
+{
+#pragma unroll
+    for (int o = 8; o >= 1; o >>= 1)
+        v += __shfl_xor(v, o, 16);
+    return v;
+}
+
+template <typename real, int NS>
+__device__ __forceinline__ void load_replica(Regs<real, NS>& r, const real* slab, int n, int l16)
+{
+    constexpr int npad = 16 * NS;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int a = 16 * s + l16;
+        if (a < n) {
+            r.x[s] = slab[a];
+            r.y[s] = slab[npad + a];
+            r.z[s] = slab[2 * npad + a];
+            r.vx[s] = slab[3 * npad + a];
+            r.vy[s] = slab[4 * npad + a];
+            r.vz[s] = slab[5 * npad + a];
+        } else {
+            // padding atoms: fixed, far apart from the molecule and from each other
+            r.x[s] = (real)(1000 + 10 * a);
+            r.y[s] = (real)1000;
+            r.z[s] = (real)1000;
+            r.vx[s] = r.vy[s] = r.vz[s] = (real)0;
+        }
+    }
+}
+
+template <typename real, int NS>
+__device__ __forceinline__ void store_replica(const Regs<real, NS>& r, real* slab, int l16)
+{
+    constexpr int npad = 16 * NS;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int a = 16 * s + l16;
+        {
+            slab[a] = r.x[s];
+            slab[npad + a] = r.y[s];
+            slab[2 * npad + a] = r.z[s];
+            slab[3 * npad + a] = r.vx[s];
+            slab[4 * npad + a] = r.vy[s];
+            slab[5 * npad + a] = r.vz[s];
+        }
+    }
+}
+
+// three standard normals from one Philox draw (Box-Muller)
+template <typename real>
+__device__ __forceinline__ void normals3(const u32x4& w, real* z)
+{
+    const real s24 = (real)(1.0 / 16777216.0);
+    const real u0 = ((real)(w.v[0] >> 8) + (real)0.5) * s24;
+    const real u1 = ((real)(w.v[1] >> 8) + (real)0.5) * s24;
+    const real u2 = ((real)(w.v[2] >> 8) + (real)0.5) * s24;
+    const real u3 = ((real)(w.v[3] >> 8) + (real)0.5) * s24;
+    const real two_pi = (real)6.283185307179586476925286766559;
+    const real r0 = sqrt_((real)-2 * log_(u0));
+    const real r1 = sqrt_((real)-2 * log_(u2));
+    real s0, c0, s1, c1;
+    sincos_(two_pi * u1, &s0, &c0);
+    sincos_(two_pi * u3, &s1, &c1);
+    z[0] = r0 * c0;
+    z[1] = r0 * s0;
+    z[2] = r1 * c1;
+}
+
+struct Lds {
+    template <typename real, int NS>
+    static constexpr size_t table_elems() { return (size_t)tile_steps(NS) * 16 * 3; }
+};
+
+// ---------------------------------------------------------------------------
+// the persistent MD kernel
+// ---------------------------------------------------------------------------
+template <typename real, int NS, int DIEL>
+__global__ __launch_bounds__(1024) void k_md(RunDev<real> d, int n_steps)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int NST = tile_steps(NS);
+    real* tab_ab = reinterpret_cast<real*>(smem);
+    real* tab_c = tab_ab + NST * 32;
+    real* stage = tab_c + NST * 16;
+    for (int i = threadIdx.x; i < NST * 32; i += blockDim.x)
+        tab_ab[i] = d.nb_ab[i];
+    for (int i = threadIdx.x; i < NST * 16; i += blockDim.x)
+        tab_c[i] = d.nb_c[i];
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63;
+    const int row = lane >> 4;
+    const int l16 = lane & 15;
+    const int wave = threadIdx.x >> 6;
+    real* pos = stage + (size_t)(wave * kRowsPerWave + row) * 6 * d.n;
+    real* frc = pos + 3 * d.n;
+
+    const RunCtl* ctl = d.ctl;
+    const int64_t R = ctl->R_cur;
+    const int cur = ctl->cur;
+    const uint32_t step0 = ctl->step;
+    const real kT = (real)(d.kB * ctl->T_cur);
+    const real dt = (real)d.dt;
+    real* slab_all = d.slab[cur];
+    constexpr int npad = 16 * NS;
+    const real two_over_dt = (real)(2.0 / d.dt);
+
+    // per-atom dt / (2 m); 0 for padding atoms, which therefore never move
+    real hdtm[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int a = 16 * s + l16;
+        hdtm[s] = (a < d.n) ? (real)(0.5 * d.dt / d.mass[a]) : (real)0;
+    }
+    // the force stage starts cleared
+    for (int i = l16; i < 3 * d.n; i += kRow)
+        frc[i] = (real)0;
+
+    for (;;) {
+        int g = 0;
+        if (lane == 0)
+            g = atomicAdd(&d.ctl->work, 1);
+        g = __builtin_amdgcn_readfirstlane(g);
+        const int64_t base = (int64_t)g * kRowsPerWave;
+        if (base >= R)
+            break;
+        const int64_t slot = base + row;
+        const bool valid = slot < R;
+        const int64_t ls = valid ? slot : base;
+        real* slab = slab_all + (size_t)ls * 6 * npad;
+
+        Regs<real, NS> r;
+        load_replica<real, NS>(r, slab, d.n, l16);
+        double eacc = 0.0;
+        evaluate<real, NS, DIEL, false>(r, d, tab_ab, tab_c, pos, frc, l16, eacc);
+
+        for (int st = 0; st < n_steps; ++st) {
+            // compiler-only memory barrier: keeps the (step-invariant) term
+            // records and pair coefficients from being hoisted out of the step
+            // loop into hundreds of live registers
+            asm volatile("" ::: "memory");
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                r.vx[s] += hdtm[s] * r.fx[s];
+                r.vy[s] += hdtm[s] * r.fy[s];
+                r.vz[s] += hdtm[s] * r.fz[s];
+                r.x[s] += dt * r.vx[s];
+                r.y[s] += dt * r.vy[s];
+                r.z[s] += dt * r.vz[s];
+            }
+            evaluate<real, NS, DIEL, false>(r, d, tab_ab, tab_c, pos, frc, l16, eacc);
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                r.vx[s] += hdtm[s] * r.fx[s];
+                r.vy[s] += hdtm[s] * r.fy[s];
+                r.vz[s] += hdtm[s] * r.fz[s];
+            }
+            // Andersen collisions
+            if (d.p24 != 0u) {
+                const uint32_t gstep = step0 + (uint32_t)st;
+#pragma unroll
+                for (int q = 0; q < (NS + 3) / 4; ++q) {
+                    const u32x4 w = philox10((uint32_t)ls, gstep, (uint32_t)(l16 + 16 * q), kStreamCollide,
+                                             d.key0, d.key1);
+#pragma unroll
+                    for (int s = 4 * q; s < NS && s < 4 * q + 4; ++s) {
+                        const int a = 16 * s + l16;
+                        if (a < d.n && (w.v[s & 3] >> 8) < d.p24) {
+                            const u32x4 wv = philox10((uint32_t)ls, gstep, (uint32_t)a, kStreamVelocity,
+                                                      d.key0, d.key1);
+                            real z[3];
+                            normals3<real>(wv, z);
+                            const real sd = sqrt_(kT * hdtm[s] * two_over_dt);
+                            r.vx[s] = sd * z[0];
+                            r.vy[s] = sd * z[1];
+                            r.vz[s] = sd * z[2];
+                        }
+                    }
+                }
+            }
+        }
+
+        // potential (FP64 sum of FP32 terms) and kinetic energy of the final state
+        double ep = 0.0;
+        evaluate<real, NS, DIEL, true>(r, d, tab_ab, tab_c, pos, frc, l16, ep);
+        double ek = 0.0;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int a = 16 * s + l16;
+            if (a < d.n) {
+                const double vx = r.vx[s], vy = r.vy[s], vz = r.vz[s];
+                ek += 0.5 * d.mass[a] * (vx * vx + vy * vy + vz * vz);
+            }
+        }
+        ep = row_sum<real>(ep);
+        ek = row_sum<real>(ek);
+        if (valid) {
+            store_replica<real, NS>(r, slab, l16);
+            if (l16 == 0) {
+                d.epot[cur][slot] = ep;
+                d.ekin[slot] = ek;
+                if (!isfinite(ep))
+                    atomicCAS(&d.ctl->error, 0, 4);
+            }
+        }
+    }
+}
+
+// forces and energies of replicas [r0, r0 + count) at their current positions
+template <typename real, int NS, int DIEL>
+__global__ __launch_bounds__(1024) void k_forces(RunDev<real> d, int64_t r0, int count)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int NST = tile_steps(NS);
+    real* tab_ab = reinterpret_cast<real*>(smem);
+    real* tab_c = tab_ab + NST * 32;
+    real* stage = tab_c + NST * 16;
+    for (int i = threadIdx.x; i < NST * 32; i += blockDim.x)
+        tab_ab[i] = d.nb_ab[i];
+    for (int i = threadIdx.x; i < NST * 16; i += blockDim.x)
+        tab_c[i] = d.nb_c[i];
+    __syncthreads();
+    const int lane = threadIdx.x & 63, row = lane >> 4, l16 = lane & 15, wave = threadIdx.x >> 6;
+    real* pos = stage + (size_t)(wave * kRowsPerWave + row) * 6 * d.n;
+    real* frc = pos + 3 * d.n;
+    for (int i = l16; i < 3 * d.n; i += kRow)
+        frc[i] = (real)0;
+    const int cur = d.ctl->cur;
+    const int64_t k = ((int64_t)blockIdx.x * (blockDim.x >> 6) + wave) * kRowsPerWave + row;
+    const bool valid = k < count;
+    const int64_t slot = r0 + (valid ? k : 0);
+    const real* slab = d.slab[cur] + (size_t)slot * 6 * (16 * NS);
+    Regs<real, NS> r;
+    load_replica<real, NS>(r, slab, d.n, l16);
+    double dummy = 0.0, ep = 0.0;
+    evaluate<real, NS, DIEL, false>(r, d, tab_ab, tab_c, pos, frc, l16, dummy);
+    evaluate<real, NS, DIEL, true>(r, d, tab_ab, tab_c, pos, frc, l16, ep);
+    ep = row_sum<real>(ep);
+    if (valid) {
+        double* o = d.dbg + (size_t)k * d.npad * 4;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int a = 16 * s + l16;
+            if (a < d.n) {
+                o[4 * a] = (double)r.fx[s];
+                o[4 * a + 1] = (double)r.fy[s];
+                o[4 * a + 2] = (double)r.fz[s];
+            }
+        }
+        if (l16 == 0)
+            o[3] = ep;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host-side dispatch
+// ---------------------------------------------------------------------------
+template <typename real>
+size_t md_lds_bytes(int nslot, int n, int waves)
+{
+    return (size_t)tile_steps(nslot) * 16 * 3 * sizeof(real) + (size_t)waves * kRowsPerWave * 6 * n * sizeof(real);
+}
+
+template <typename real, int NS, int DIEL>
+static hipError_t launch_md_t(const RunDev<real>& d, int n_steps, int blocks, int waves, hipStream_t s)
+{
+    const size_t lds = md_lds_bytes<real>(NS, d.n, waves);
+    hipError_t e = hipFuncSetAttribute((const void*)k_md<real, NS, DIEL>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL((k_md<real, NS, DIEL>), dim3(blocks), dim3(waves * 64), lds, s, d, n_steps);
+    return hipGetLastError();
+}
+
+template <typename real, int NS, int DIEL>
+static hipError_t launch_forces_t(const RunDev<real>& d, int64_t r0, int count, int waves, hipStream_t s)
+{
+    const size_t lds = md_lds_bytes<real>(NS, d.n, waves);
+    hipError_t e = hipFuncSetAttribute((const void*)k_forces<real, NS, DIEL>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess)
+        return e;
+    const int per_block = waves * kRowsPerWave;
+    const int blocks = (count + per_block - 1) / per_block;
+    hipLaunchKernelGGL((k_forces<real, NS, DIEL>), dim3(blocks), dim3(waves * 64), lds, s, d, r0, count);
+    return hipGetLastError();
+}
+
+template <typename real, int NS, int DIEL>
+static hipError_t occupancy_t(int waves, int* blocks_per_cu, int n)
+{
+    const size_t lds = md_lds_bytes<real>(NS, n, waves);
+    hipError_t e = hipFuncSetAttribute((const void*)k_md<real, NS, DIEL>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess)
+        return e;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, (const void*)k_md<real, NS, DIEL>,
+                                                        waves * 64, lds);
+}
+
+#define PAMD_DISPATCH(REAL, NSV, DIELV, CALL)                                                    \
+    switch (NSV * 2 + DIELV) {                                                                  \
+    case 1 * 2 + 0: return CALL(REAL, 1, 0);                                                    \
+    case 1 * 2 + 1: return CALL(REAL, 1, 1);                                                    \
+    case 2 * 2 + 0: return CALL(REAL, 2, 0);                                                    \
+    case 2 * 2 + 1: return CALL(REAL, 2, 1);                                                    \
+    case 3 * 2 + 0: return CALL(REAL, 3, 0);                                                    \
+    case 3 * 2 + 1: return CALL(REAL, 3, 1);                                                    \
+    case 4 * 2 + 0: return CALL(REAL, 4, 0);                                                    \
+    case 4 * 2 + 1: return CALL(REAL, 4, 1);                                                    \
+    case 5 * 2 + 0: return CALL(REAL, 5, 0);                                                    \
+    case 5 * 2 + 1: return CALL(REAL, 5, 1);                                                    \
+    default: return hipErrorInvalidValue;                                                       \
+    }
+
+#define PAMD_DISPATCH64(NSV, DIELV, CALL)                                                        \
+    switch (NSV * 2 + DIELV) {                                                                  \
+    case 1 * 2 + 0: return CALL(double, 1, 0);                                                  \
+    case 1 * 2 + 1: return CALL(double, 1, 1);                                                  \
+    case 2 * 2 + 0: return CALL(double, 2, 0);                                                  \
+    case 2 * 2 + 1: return CALL(double, 2, 1);                                                  \
+    default: return hipErrorInvalidValue;                                                       \
+    }
+
+hipError_t launch_md(const RunDev<float>& d, int n_steps, int blocks, int waves, hipStream_t s)
+{
+#define CALL(R, N, D) launch_md_t<R, N, D>(d, n_steps, blocks, waves, s)
+    PAMD_DISPATCH(float, d.nslot, d.dielectric, CALL)
+#undef CALL
+}
+hipError_t launch_md(const RunDev<double>& d, int n_steps, int blocks, int waves, hipStream_t s)
+{
+#define CALL(R, N, D) launch_md_t<R, N, D>(d, n_steps, blocks, waves, s)
+    PAMD_DISPATCH64(d.nslot, d.dielectric, CALL)
+#undef CALL
+}
+hipError_t launch_forces(const RunDev<float>& d, int64_t r0, int count, int waves, hipStream_t s)
+{
+#define CALL(R, N, D) launch_forces_t<R, N, D>(d, r0, count, waves, s)
+    PAMD_DISPATCH(float, d.nslot, d.dielectric, CALL)
+#undef CALL
+}
+hipError_t launch_forces(const RunDev<double>& d, int64_t r0, int count, int waves, hipStream_t s)
+{
+#define CALL(R, N, D) launch_forces_t<R, N, D>(d, r0, count, waves, s)
+    PAMD_DISPATCH64(d.nslot, d.dielectric, CALL)
+#undef CALL
+}
+hipError_t md_occupancy(int precision_fp32, int nslot, int diel, int n, int waves, int* blocks_per_cu)
+{
+    if (precision_fp32) {
+#define CALL(R, N, D) occupancy_t<R, N, D>(waves, blocks_per_cu, n)
+        PAMD_DISPATCH(float, nslot, diel, CALL)
+#undef CALL
+    } else {
+#define CALL(R, N, D) occupancy_t<R, N, D>(waves, blocks_per_cu, n)
+        PAMD_DISPATCH64(nslot, diel, CALL)
+#undef CALL
+    }
+}
+size_t md_lds(int precision_fp32, int nslot, int n, int waves)
+{
+    return precision_fp32 ? md_lds_bytes<float>(nslot, n, waves) : md_lds_bytes<double>(nslot, n, waves);
+}
+
+}  // namespace pamd

@@ -1,0 +1,78 @@
+// Internal structures shared by the HIP kernels and the host runtime of libpamd.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pamd {
+
+constexpr int kRow = 16;            // lanes per replica (one DPP row)
+constexpr int kRowsPerWave = 4;     // replicas per wave64
+constexpr int kMaxSlots = 5;        // 16-atom blocks held in registers (N <= 80)
+constexpr int kWaveSize = 64;
+
+// Number of tile steps of the all-pairs schedule for `nslot` blocks of 16 atoms:
+// each diagonal block takes 8 row rotations (k = 1..8, k = 8 half-masked),
+// each off-diagonal block pair takes 16 (k = 0..15).
+__host__ __device__ constexpr int tile_steps(int nslot) { return nslot * 8 + nslot * (nslot - 1) / 2 * 16; }
+
+// Device-resident control block of one run.  Everything that changes from
+// one temperature to the next lives here, so the per-temperature kernel
+// sequence needs no host values and can be replayed from a HIP graph.
+struct alignas(64) RunCtl {
+    double T_cur;        // bath temperature of the current population
+    double T_prev;
+    double T_next;       // chosen by the weights kernel (requested or adaptive)
+    double T_req;        // host request for the next resampling (<= 0: adaptive)
+    double dbeta;        // 1/(kB T_next) - 1/(kB T_cur)
+    double m;            // min E
+    double S;            // sum exp(-dbeta (E - m))
+    double S2;           // sum exp(-2 dbeta (E - m))
+    double lnQ_last;
+    double sum_lnQ;
+    double V_last;
+    int64_t R_cur;       // current population size
+    int64_t R_new;       // size after the pending resampling
+    int64_t R_prev;      // size before the last resampling (length of the counts array)
+    uint32_t step;       // global MD step counter (Philox counter word 1)
+    uint32_t temp_index; // i
+    int32_t cur;         // ping-pong buffer holding the current population
+    int32_t error;       // sticky PAMD_ERR_* code
+    int32_t work;        // persistent-kernel work counter
+    int32_t pad[3];
+};
+
+// Per-run device pointers and constants (passed by value to kernels).
+template <typename real>
+struct RunDev {
+    RunCtl* ctl;
+    real* slab[2];          // [R_cap][6][npad]  x | y | z | vx | vy | vz
+    double* epot[2];        // [R_cap]
+    double* ekin;           // [R_cap]
+    int32_t* anc[2];        // [R_cap]
+    int32_t* counts;        // [R_cap]
+    int32_t* src_of;        // [R_cap]
+    uint8_t* fam;           // [R_target] family flags
+    const double* unif;     // optional caller uniforms for this run
+    // topology / parameters
+    const real* nb_ab;      // [steps][16][2]   (12 c12 s, -6 c6 s)
+    const real* nb_c;       // [steps][16]      Coulomb coefficient
+    const int4* bidx;       // [nb]   (i, j, -, -)
+    const real* bpar;       // [nb][2] (k, r0)
+    const int4* aidx;       // [na]   (i, centre, k, -)
+    const real* apar;       // [na][2] (k, theta0)
+    const int4* didx;       // [nd]   (i, j, k, l)
+    const real* dpar;       // [nd][2] (k cos(delta), n)
+    const double* mass;     // [npad] (0 for padding)
+    const double* x_init;   // [n][3]
+    double* dbg;            // force-debug scratch [PAMD_FORCE_CHUNK][npad][4]
+    void* obs;              // device pamd_obs
+    int32_t n, npad, nslot, nb, na, nd;
+    int64_t R_target, R_cap;
+    double kB, dt, T0, V_target, T_final;
+    uint32_t p24;           // Andersen threshold: collide iff (w >> 8) < p24
+    uint32_t key0, key1;    // Philox key
+    int32_t dielectric;
+    int32_t waves_per_block;
+};
+
+}  // namespace pamd

@@ -1,0 +1,771 @@
+// Host runtime of libpamd: the C ABI declared in include/pamd.h.
+//
+// Owns no device memory: the caller's d_state / d_work buffers are carved
+// into per-run regions (256-byte aligned).  Builds, per run, the exclusion
+// and 1-4 lists from the bond graph, the per-tile pair-coefficient table of
+// the MD kernel and the bonded-term records, then drives the kernels of
+// md_kernel.hip (PAMD step 3) and resample.hip (steps 1, 2, 4).
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "pamd.h"
+#include "pamd_internal.h"
+
+namespace pamd {
+hipError_t launch_md(const RunDev<float>& d, int n_steps, int blocks, int waves, hipStream_t s);
+hipError_t launch_md(const RunDev<double>& d, int n_steps, int blocks, int waves, hipStream_t s);
+hipError_t launch_forces(const RunDev<float>& d, int64_t r0, int count, int waves, hipStream_t s);
+hipError_t launch_forces(const RunDev<double>& d, int64_t r0, int count, int waves, hipStream_t s);
+hipError_t md_occupancy(int precision_fp32, int nslot, int diel, int n, int waves, int* blocks_per_cu);
+size_t md_lds(int precision_fp32, int nslot, int n, int waves);
+hipError_t launch_init(const RunDev<float>& d, hipStream_t s);
+hipError_t launch_init(const RunDev<double>& d, hipStream_t s);
+hipError_t launch_resample(const RunDev<float>& d, double T_req, double mtot, int gb, hipStream_t s);
+hipError_t launch_resample(const RunDev<double>& d, double T_req, double mtot, int gb, hipStream_t s);
+hipError_t launch_md_finalize(const RunDev<float>& d, int n, hipStream_t s);
+hipError_t launch_md_finalize(const RunDev<double>& d, int n, hipStream_t s);
+hipError_t launch_observables(const RunDev<float>& d, hipStream_t s);
+hipError_t launch_observables(const RunDev<double>& d, hipStream_t s);
+}  // namespace pamd
+
+using namespace pamd;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+struct Carver {
+    char* base;
+    size_t off = 0;
+    explicit Carver(void* b) : base((char*)b) {}
+    template <typename T>
+    T* take(size_t count)
+    {
+        off = (off + kAlign - 1) / kAlign * kAlign;
+        T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+// host copies of the per-run tables (FP64; cast to the kernel precision on upload)
+struct HostTables {
+    int n = 0, npad = 0, nslot = 0;
+    std::vector<double> ab, c;           // [steps][16][2], [steps][16]
+    std::vector<int32_t> bidx, aidx, didx;  // int4 records
+    std::vector<double> bpar, apar, dpar;
+    std::vector<double> mass, x_init;
+    double mtot = 0;
+};
+
+struct Run {
+    RunDev<float> f{};
+    RunDev<double> d{};
+    HostTables tab;
+    double mtot = 0;
+};
+
+}  // namespace
+
+struct pamd_ctx {
+    int n_runs = 0;
+    int fp32 = 1;
+    std::vector<Run> runs;
+    std::string err;
+    int failed = 0;
+    int n_cu = 0, waves = 0, blocks = 0, gather_blocks = 0;
+    size_t lds = 0;
+};
+
+namespace {
+
+pamd_status fail(pamd_ctx* c, pamd_status st, const std::string& msg)
+{
+    if (c) {
+        c->err = msg;
+        if (st != PAMD_ERR_ARG)
+            c->failed = st;
+    }
+    return st;
+}
+
+#define HIPCHK(ctx, call)                                                                        \
+    do {                                                                                         \
+        hipError_t e_ = (call);                                                                  \
+        if (e_ != hipSuccess)                                                                    \
+            return fail(ctx, PAMD_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_));   \
+    } while (0)
+
+int nslot_of(int n) { return (n + kRow - 1) / kRow; }
+
+// graph distance (capped at 4) between every pair of atoms of the bond graph
+std::vector<int> graph_distance(int n, int nb, const int32_t* bidx)
+{
+    std::vector<std::vector<int>> adj(n);
+    for (int t = 0; t < nb; ++t) {
+        adj[bidx[2 * t]].push_back(bidx[2 * t + 1]);
+        adj[bidx[2 * t + 1]].push_back(bidx[2 * t]);
+    }
+    std::vector<int> dist((size_t)n * n, 4);
+    for (int s = 0; s < n; ++s) {
+        dist[(size_t)s * n + s] = 0;
+        std::vector<int> front{s};
+        for (int depth = 1; depth <= 3; ++depth) {
+            std::vector<int> next;
+            for (int u : front)
+                for (int w : adj[u])
+                    if (dist[(size_t)s * n + w] > depth) {
+                        dist[(size_t)s * n + w] = depth;
+                        next.push_back(w);
+                    }
+            front.swap(next);
+        }
+    }
+    return dist;
+}
+
+pamd_status validate(pamd_ctx* c, const pamd_system& s, const pamd_params& p, int fp32)
+{
+    if (s.n_atoms < 1 || s.n_atoms > PAMD_MAX_ATOMS)
+        return fail(c, PAMD_ERR_ARG, "n_atoms must be in 1.." + std::to_string(PAMD_MAX_ATOMS));
+    if (!fp32 && s.n_atoms > 2 * kRow)
+        return fail(c, PAMD_ERR_ARG, "FP64 precision supports at most 32 atoms");
+    if (!s.mass || !s.charge || !s.sigma || !s.epsilon || !s.x_init)
+        return fail(c, PAMD_ERR_ARG, "null per-atom array");
+    if (s.n_bonds < 0 || s.n_angles < 0 || s.n_dihedrals < 0)
+        return fail(c, PAMD_ERR_ARG, "negative term count");
+    if ((s.n_bonds && (!s.bond_idx || !s.bond_k || !s.bond_r0)) ||
+        (s.n_angles && (!s.angle_idx || !s.angle_k || !s.angle_theta0)) ||
+        (s.n_dihedrals && (!s.dih_idx || !s.dih_k || !s.dih_n || !s.dih_delta)))
+        return fail(c, PAMD_ERR_ARG, "null term array");
+    for (int a = 0; a < s.n_atoms; ++a)
+        if (!(s.mass[a] > 0.0) || !(s.epsilon[a] >= 0.0))
+            return fail(c, PAMD_ERR_ARG, "mass must be > 0 and epsilon >= 0");
+    auto in_range = [&](const int32_t* idx, int count, int k) {
+        for (int i = 0; i < count * k; ++i)
+            if (idx[i] < 0 || idx[i] >= s.n_atoms)
+                return false;
+        return true;
+    };
+    if (!in_range(s.bond_idx, s.n_bonds, 2) || !in_range(s.angle_idx, s.n_angles, 3) ||
+        !in_range(s.dih_idx, s.n_dihedrals, 4))
+        return fail(c, PAMD_ERR_ARG, "term index out of range");
+    for (int t = 0; t < s.n_dihedrals; ++t) {
+        if (s.dih_n[t] < 1 || s.dih_n[t] > 6)
+            return fail(c, PAMD_ERR_ARG, "dihedral multiplicity must be 1..6");
+        if (fabs(sin(s.dih_delta[t])) > 1e-9)
+            return fail(c, PAMD_ERR_ARG, "dihedral phase must be 0 or pi");
+    }
+    if (s.dielectric != PAMD_DIELECTRIC_VACUUM && s.dielectric != PAMD_DIELECTRIC_4R)
+        return fail(c, PAMD_ERR_ARG, "unknown dielectric mode");
+    if (p.R_target < 1 || p.R_cap < p.R_target || p.R_cap > (int64_t)1 << 30)
+        return fail(c, PAMD_ERR_ARG, "need 1 <= R_target <= R_cap <= 2^30");
+    if (!(p.T0 > 0) || !(p.dt > 0) || !(p.nu >= 0) || !(s.kB > 0))
+        return fail(c, PAMD_ERR_ARG, "T0, dt, kB must be > 0 and nu >= 0");
+    if (p.waves_per_block < 0 || p.waves_per_block > 16)
+        return fail(c, PAMD_ERR_ARG, "waves_per_block must be 0..16");
+    return PAMD_OK;
+}
+
+// Pair coefficients in the order the MD kernel walks its tiles: for block J,
+// the diagonal block (rotations k = 1..8; k = 8 only on lanes 0..7), then for
+// k = 0..15 the blocks I < J.  Lane l of step (I, J, k) pairs atom 16 I + l
+// with atom 16 J + ((l - k) mod 16).
+void build_tables(const pamd_system& s, HostTables& t)
+{
+    const int n = s.n_atoms;
+    t.n = n;
+    t.nslot = nslot_of(n);
+    t.npad = t.nslot * kRow;
+    const std::vector<int> dist = graph_distance(n, s.n_bonds, s.bond_idx);
+    const int steps = tile_steps(t.nslot);
+    t.ab.assign((size_t)steps * 16 * 2, 0.0);
+    t.c.assign((size_t)steps * 16, 0.0);
+    auto coef = [&](int st, int l, int i, int j) {
+        if (i >= n || j >= n || i == j)
+            return;
+        const int g = dist[(size_t)i * n + j];
+        if (g <= 2)
+            return;   // 1-2 and 1-3 pairs are excluded
+        const double slj = (g == 3) ? s.scale14_lj : 1.0;
+        const double sc = (g == 3) ? s.scale14_coul : 1.0;
+        const double sig = 0.5 * (s.sigma[i] + s.sigma[j]);
+        const double eps = sqrt(s.epsilon[i] * s.epsilon[j]);
+        const double s6 = pow(sig, 6.0);
+        const double c6 = 4.0 * eps * s6, c12 = 4.0 * eps * s6 * s6;
+        const double qq = s.coulomb_k * s.charge[i] * s.charge[j] * sc;
+        t.ab[((size_t)st * 16 + l) * 2] = 12.0 * c12 * slj;
+        t.ab[((size_t)st * 16 + l) * 2 + 1] = -6.0 * c6 * slj;
+        t.c[(size_t)st * 16 + l] = (s.dielectric == PAMD_DIELECTRIC_4R) ? 2.0 * qq / 4.0 : qq;
+    };
+    int st = 0;
+    for (int J = 0; J < t.nslot; ++J) {
+        for (int k = 1; k <= 8; ++k, ++st)
+            for (int l = 0; l < 16; ++l)
+                if (!(k == 8 && l >= 8))
+                    coef(st, l, 16 * J + l, 16 * J + ((l - k) & 15));
+        for (int k = 0; k < 16; ++k)
+            for (int I = 0; I < J; ++I, ++st)
+                for (int l = 0; l < 16; ++l)
+                    coef(st, l, 16 * I + l, 16 * J + ((l - k) & 15));
+    }
+    t.bidx.assign((size_t)std::max(1, s.n_bonds) * 4, 0);
+    t.bpar.assign((size_t)std::max(1, s.n_bonds) * 2, 0.0);
+    for (int q = 0; q < s.n_bonds; ++q) {
+        t.bidx[4 * q] = s.bond_idx[2 * q];
+        t.bidx[4 * q + 1] = s.bond_idx[2 * q + 1];
+        t.bpar[2 * q] = s.bond_k[q];
+        t.bpar[2 * q + 1] = s.bond_r0[q];
+    }
+    t.aidx.assign((size_t)std::max(1, s.n_angles) * 4, 0);
+    t.apar.assign((size_t)std::max(1, s.n_angles) * 2, 0.0);
+    for (int q = 0; q < s.n_angles; ++q) {
+        for (int k = 0; k < 3; ++k)
+            t.aidx[4 * q + k] = s.angle_idx[3 * q + k];
+        t.apar[2 * q] = s.angle_k[q];
+        t.apar[2 * q + 1] = s.angle_theta0[q];
+    }
+    t.didx.assign((size_t)std::max(1, s.n_dihedrals) * 4, 0);
+    t.dpar.assign((size_t)std::max(1, s.n_dihedrals) * 2, 0.0);
+    for (int q = 0; q < s.n_dihedrals; ++q) {
+        for (int k = 0; k < 4; ++k)
+            t.didx[4 * q + k] = s.dih_idx[4 * q + k];
+        t.dpar[2 * q] = s.dih_k[q] * (cos(s.dih_delta[q]) > 0 ? 1.0 : -1.0);
+        t.dpar[2 * q + 1] = (double)s.dih_n[q];
+    }
+    t.mass.assign(t.npad, 0.0);
+    t.mtot = 0;
+    for (int a = 0; a < n; ++a) {
+        t.mass[a] = s.mass[a];
+        t.mtot += s.mass[a];
+    }
+    t.x_init.assign(s.x_init, s.x_init + 3 * n);
+}
+
+template <typename real>
+void carve(Carver& st, Carver& wk, const pamd_system& s, const pamd_params& p, int run, RunDev<real>& d)
+{
+    const int n = s.n_atoms;
+    const int nslot = nslot_of(n);
+    const int npad = nslot * kRow;
+    const int64_t Rc = p.R_cap;
+    const int steps = tile_steps(nslot);
+    for (int b = 0; b < 2; ++b)
+        d.slab[b] = st.take<real>((size_t)Rc * 6 * npad);
+    for (int b = 0; b < 2; ++b)
+        d.epot[b] = st.take<double>(Rc);
+    d.ekin = st.take<double>(Rc);
+    for (int b = 0; b < 2; ++b)
+        d.anc[b] = st.take<int32_t>(Rc);
+    d.ctl = wk.take<RunCtl>(1);
+    d.counts = wk.take<int32_t>(Rc);
+    d.src_of = wk.take<int32_t>(Rc);
+    d.fam = wk.take<uint8_t>(p.R_target);
+    d.nb_ab = wk.take<real>((size_t)steps * 32);
+    d.nb_c = wk.take<real>((size_t)steps * 16);
+    d.bidx = wk.take<int4>(std::max(1, s.n_bonds));
+    d.bpar = wk.take<real>((size_t)std::max(1, s.n_bonds) * 2);
+    d.aidx = wk.take<int4>(std::max(1, s.n_angles));
+    d.apar = wk.take<real>((size_t)std::max(1, s.n_angles) * 2);
+    d.didx = wk.take<int4>(std::max(1, s.n_dihedrals));
+    d.dpar = wk.take<real>((size_t)std::max(1, s.n_dihedrals) * 2);
+    d.mass = wk.take<double>(npad);
+    d.x_init = wk.take<double>((size_t)3 * n);
+    d.dbg = wk.take<double>((size_t)PAMD_FORCE_CHUNK * npad * 4);
+    d.obs = wk.take<pamd_obs>(1);
+    d.unif = nullptr;
+    d.n = n;
+    d.npad = npad;
+    d.nslot = nslot;
+    d.nb = s.n_bonds;
+    d.na = s.n_angles;
+    d.nd = s.n_dihedrals;
+    d.R_target = p.R_target;
+    d.R_cap = Rc;
+    d.kB = s.kB;
+    d.dt = p.dt;
+    d.T0 = p.T0;
+    d.V_target = p.V_target > 0 ? p.V_target : 0.1;
+    d.T_final = p.T_final > 0 ? p.T_final : p.T0;
+    d.p24 = (uint32_t)llround((1.0 - exp(-p.nu * p.dt)) * 16777216.0);
+    d.key0 = (uint32_t)(p.seed & 0xFFFFFFFFu);
+    d.key1 = (uint32_t)(p.seed >> 32) + (uint32_t)run;
+    d.dielectric = s.dielectric;
+}
+
+template <typename real>
+hipError_t upload(const RunDev<real>& d, const HostTables& t, hipStream_t s)
+{
+    auto up = [&](const void* dst, const std::vector<double>& src) -> hipError_t {
+        std::vector<real> tmp(src.begin(), src.end());
+        hipError_t e = hipMemcpyAsync((void*)dst, tmp.data(), tmp.size() * sizeof(real), hipMemcpyHostToDevice, s);
+        if (e != hipSuccess)
+            return e;
+        return hipStreamSynchronize(s);
+    };
+    auto upi = [&](const void* dst, const std::vector<int32_t>& src) -> hipError_t {
+        hipError_t e = hipMemcpyAsync((void*)dst, src.data(), src.size() * sizeof(int32_t), hipMemcpyHostToDevice, s);
+        if (e != hipSuccess)
+            return e;
+        return hipStreamSynchronize(s);
+    };
+    auto upd = [&](const void* dst, const std::vector<double>& src) -> hipError_t {
+        hipError_t e = hipMemcpyAsync((void*)dst, src.data(), src.size() * sizeof(double), hipMemcpyHostToDevice, s);
+        if (e != hipSuccess)
+            return e;
+        return hipStreamSynchronize(s);
+    };
+    hipError_t e;
+    if ((e = up(d.nb_ab, t.ab)) != hipSuccess) return e;
+    if ((e = up(d.nb_c, t.c)) != hipSuccess) return e;
+    if ((e = upi(d.bidx, t.bidx)) != hipSuccess) return e;
+    if ((e = up(d.bpar, t.bpar)) != hipSuccess) return e;
+    if ((e = upi(d.aidx, t.aidx)) != hipSuccess) return e;
+    if ((e = up(d.apar, t.apar)) != hipSuccess) return e;
+    if ((e = upi(d.didx, t.didx)) != hipSuccess) return e;
+    if ((e = up(d.dpar, t.dpar)) != hipSuccess) return e;
+    if ((e = upd(d.mass, t.mass)) != hipSuccess) return e;
+    if ((e = upd(d.x_init, t.x_init)) != hipSuccess) return e;
+    return hipSuccess;
+}
+
+pamd_status layout(const pamd_system* sys, int32_t n_runs, const pamd_params* p, void* d_state, void* d_work,
+                   std::vector<Run>* runs, size_t* sb, size_t* wb)
+{
+    Carver st(d_state), wk(d_work);
+    for (int r = 0; r < n_runs; ++r) {
+        if (p[0].precision == PAMD_FP32) {
+            RunDev<float> d{};
+            carve<float>(st, wk, sys[r], p[r], r, d);
+            if (runs)
+                (*runs)[r].f = d;
+        } else {
+            RunDev<double> d{};
+            carve<double>(st, wk, sys[r], p[r], r, d);
+            if (runs)
+                (*runs)[r].d = d;
+        }
+    }
+    *sb = (st.off + kAlign - 1) / kAlign * kAlign;
+    *wb = (wk.off + kAlign - 1) / kAlign * kAlign;
+    return PAMD_OK;
+}
+
+template <typename real>
+RunDev<real>& dev(Run& r);
+template <>
+RunDev<float>& dev<float>(Run& r) { return r.f; }
+template <>
+RunDev<double>& dev<double>(Run& r) { return r.d; }
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+pamd_status check_ctx(pamd_ctx* c)
+{
+    if (!c)
+        return PAMD_ERR_ARG;
+    if (c->failed)
+        return fail(c, PAMD_ERR_STATE, "context failed earlier: " + c->err);
+    return PAMD_OK;
+}
+
+template <typename real>
+pamd_status read_ctl(pamd_ctx* c, Run& run, RunCtl* ctl, hipStream_t s)
+{
+    HIPCHK(c, hipMemcpyAsync(ctl, dev<real>(run).ctl, sizeof(RunCtl), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    return PAMD_OK;
+}
+
+pamd_status surface_device_error(pamd_ctx* c, int code)
+{
+    if (code == 0)
+        return PAMD_OK;
+    const char* what = code == PAMD_ERR_CAPACITY   ? "resampled population over capacity (or extinct)"
+                       : code == PAMD_ERR_NONFINITE ? "non-finite potential energy"
+                                                    : "device error";
+    return fail(c, code, what);
+}
+
+}  // namespace
+
+// Entry points: declared extern "C" in pamd.h, so these definitions have C linkage.
+
+pamd_status pamd_query_sizes(const pamd_system* sys, int32_t n_runs, const pamd_params* p, size_t* state_bytes,
+                             size_t* work_bytes)
+{
+    if (!sys || !p || !state_bytes || !work_bytes || n_runs < 1)
+        return PAMD_ERR_ARG;
+    const int fp32 = p[0].precision == PAMD_FP32;
+    for (int r = 0; r < n_runs; ++r) {
+        if (p[r].precision != p[0].precision)
+            return PAMD_ERR_ARG;
+        pamd_status st = validate(nullptr, sys[r], p[r], fp32);
+        if (st != PAMD_OK)
+            return st;
+    }
+    return layout(sys, n_runs, p, nullptr, nullptr, nullptr, state_bytes, work_bytes);
+}
+
+template <typename real>
+static pamd_status init_runs(pamd_ctx* c, const pamd_system* sys, hipStream_t s)
+{
+    for (int r = 0; r < c->n_runs; ++r) {
+        Run& run = c->runs[r];
+        build_tables(sys[r], run.tab);
+        run.mtot = run.tab.mtot;
+        HIPCHK(c, upload<real>(dev<real>(run), run.tab, s));
+        HIPCHK(c, launch_init(dev<real>(run), s));
+    }
+    HIPCHK(c, hipStreamSynchronize(s));
+    return PAMD_OK;
+}
+
+pamd_status pamd_init(const pamd_system* sys, int32_t n_runs, const pamd_params* p, void* d_state,
+                      size_t state_bytes, void* d_work, size_t work_bytes, void* stream, pamd_ctx** out)
+{
+    if (!out)
+        return PAMD_ERR_ARG;
+    *out = nullptr;
+    if (!sys || !p || n_runs < 1 || !d_state || !d_work)
+        return PAMD_ERR_ARG;
+    if (((uintptr_t)d_state % kAlign) || ((uintptr_t)d_work % kAlign))
+        return PAMD_ERR_ARG;
+    size_t sb = 0, wb = 0;
+    pamd_status st = pamd_query_sizes(sys, n_runs, p, &sb, &wb);
+    if (st != PAMD_OK)
+        return st;
+    if (state_bytes < sb || work_bytes < wb)
+        return PAMD_ERR_ARG;
+    pamd_ctx* c = new pamd_ctx();
+    *out = c;
+    c->n_runs = n_runs;
+    c->fp32 = p[0].precision == PAMD_FP32;
+    c->runs.resize(n_runs);
+    layout(sys, n_runs, p, d_state, d_work, &c->runs, &sb, &wb);
+    hipStream_t s = as_stream(stream);
+
+    int dev_id = 0;
+    HIPCHK(c, hipGetDevice(&dev_id));
+    HIPCHK(c, hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, dev_id));
+    int max_lds = 0;
+    HIPCHK(c, hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev_id));
+
+    // launch shape: the largest workgroup (<= 16 waves) whose LDS fits, all
+    // runs sharing it; enough resident blocks to fill every CU
+    int n_max = 0, ns_max = 0;
+    for (int r = 0; r < n_runs; ++r) {
+        n_max = std::max(n_max, sys[r].n_atoms);
+        ns_max = std::max(ns_max, nslot_of(sys[r].n_atoms));
+    }
+    int waves = p[0].waves_per_block;
+    if (waves == 0) {
+        waves = 16;
+        while (waves > 1 && md_lds(c->fp32, ns_max, n_max, waves) > (size_t)max_lds)
+            --waves;
+    }
+    c->lds = md_lds(c->fp32, ns_max, n_max, waves);
+    if (c->lds > (size_t)max_lds)
+        return fail(c, PAMD_ERR_ARG, "system too large for the LDS of one workgroup");
+    int bpc = 0;
+    HIPCHK(c, md_occupancy(c->fp32, ns_max, sys[0].dielectric, n_max, waves, &bpc));
+    if (bpc < 1)
+        return fail(c, PAMD_ERR_ARG, "MD kernel cannot be resident with this launch shape");
+    c->waves = waves;
+    c->blocks = c->n_cu * bpc;
+    c->gather_blocks = c->n_cu * 8;
+    for (int r = 0; r < n_runs; ++r) {
+        c->runs[r].f.waves_per_block = waves;
+        c->runs[r].d.waves_per_block = waves;
+    }
+    return c->fp32 ? init_runs<float>(c, sys, s) : init_runs<double>(c, sys, s);
+}
+
+pamd_status pamd_md_steps(pamd_ctx* c, int32_t n_steps, void* stream)
+{
+    pamd_status st = check_ctx(c);
+    if (st != PAMD_OK)
+        return st;
+    if (n_steps < 0)
+        return fail(c, PAMD_ERR_ARG, "n_steps < 0");
+    hipStream_t s = as_stream(stream);
+    for (auto& run : c->runs) {
+        if (c->fp32) {
+            HIPCHK(c, launch_md(run.f, n_steps, c->blocks, c->waves, s));
+            HIPCHK(c, launch_md_finalize(run.f, n_steps, s));
+        } else {
+            HIPCHK(c, launch_md(run.d, n_steps, c->blocks, c->waves, s));
+            HIPCHK(c, launch_md_finalize(run.d, n_steps, s));
+        }
+    }
+    return PAMD_OK;
+}
+
+pamd_status pamd_resample(pamd_ctx* c, const double* T_next, const double* d_uniforms, void* stream)
+{
+    pamd_status st = check_ctx(c);
+    if (st != PAMD_OK)
+        return st;
+    hipStream_t s = as_stream(stream);
+    for (int r = 0; r < c->n_runs; ++r) {
+        Run& run = c->runs[r];
+        const double Treq = T_next ? T_next[r] : 0.0;
+        if (c->fp32) {
+            RunDev<float> d = run.f;
+            d.unif = d_uniforms ? d_uniforms + (size_t)r * d.R_cap : nullptr;
+            HIPCHK(c, launch_resample(d, Treq, run.mtot, c->gather_blocks, s));
+        } else {
+            RunDev<double> d = run.d;
+            d.unif = d_uniforms ? d_uniforms + (size_t)r * d.R_cap : nullptr;
+            HIPCHK(c, launch_resample(d, Treq, run.mtot, c->gather_blocks, s));
+        }
+    }
+    return PAMD_OK;
+}
+
+pamd_status pamd_observables(pamd_ctx* c, pamd_obs* out, void* stream)
+{
+    pamd_status st = check_ctx(c);
+    if (st != PAMD_OK)
+        return st;
+    if (!out)
+        return fail(c, PAMD_ERR_ARG, "null output");
+    hipStream_t s = as_stream(stream);
+    for (int r = 0; r < c->n_runs; ++r) {
+        Run& run = c->runs[r];
+        void* obs = c->fp32 ? run.f.obs : run.d.obs;
+        if (c->fp32)
+            HIPCHK(c, launch_observables(run.f, s));
+        else
+            HIPCHK(c, launch_observables(run.d, s));
+        HIPCHK(c, hipMemcpyAsync(&out[r], obs, sizeof(pamd_obs), hipMemcpyDeviceToHost, s));
+    }
+    HIPCHK(c, hipStreamSynchronize(s));
+    for (int r = 0; r < c->n_runs; ++r)
+        if (out[r].error)
+            return surface_device_error(c, out[r].error);
+    return PAMD_OK;
+}
+
+template <typename real>
+static pamd_status get_forces_t(pamd_ctx* c, Run& run, int64_t r0, int32_t count, double* F, double* E,
+                                hipStream_t s)
+{
+    RunCtl ctl;
+    pamd_status st = read_ctl<real>(c, run, &ctl, s);
+    if (st != PAMD_OK)
+        return st;
+    if (ctl.error)
+        return surface_device_error(c, ctl.error);
+    if (r0 < 0 || count < 1 || count > PAMD_FORCE_CHUNK || r0 + count > ctl.R_cur)
+        return fail(c, PAMD_ERR_ARG, "replica range outside the population or chunk");
+    RunDev<real>& d = dev<real>(run);
+    HIPCHK(c, launch_forces(d, r0, count, c->waves, s));
+    std::vector<double> buf((size_t)count * d.npad * 4);
+    HIPCHK(c, hipMemcpyAsync(buf.data(), d.dbg, buf.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    for (int k = 0; k < count; ++k) {
+        const double* o = buf.data() + (size_t)k * d.npad * 4;
+        if (F)
+            for (int a = 0; a < d.n; ++a)
+                for (int q = 0; q < 3; ++q)
+                    F[((size_t)k * d.n + a) * 3 + q] = o[4 * a + q];
+        if (E)
+            E[k] = o[3];
+    }
+    return PAMD_OK;
+}
+
+pamd_status pamd_get_forces(pamd_ctx* c, int32_t run, int64_t r0, int32_t count, double* host_F, double* host_E,
+                            void* stream)
+{
+    pamd_status st = check_ctx(c);
+    if (st != PAMD_OK)
+        return st;
+    if (run < 0 || run >= c->n_runs)
+        return fail(c, PAMD_ERR_ARG, "run index out of range");
+    hipStream_t s = as_stream(stream);
+    return c->fp32 ? get_forces_t<float>(c, c->runs[run], r0, count, host_F, host_E, s)
+                   : get_forces_t<double>(c, c->runs[run], r0, count, host_F, host_E, s);
+}
+
+template <typename real>
+static pamd_status get_state_t(pamd_ctx* c, Run& run, double* x, double* v, double* Ep, double* Ek, int32_t* anc,
+                               pamd_run_scalars* sc, hipStream_t s)
+{
+    RunCtl ctl;
+    pamd_status st = read_ctl<real>(c, run, &ctl, s);
+    if (st != PAMD_OK)
+        return st;
+    RunDev<real>& d = dev<real>(run);
+    const int64_t R = ctl.R_cur;
+    const int cur = ctl.cur;
+    if (x || v) {
+        std::vector<real> buf((size_t)R * 6 * d.npad);
+        if (R > 0)
+            HIPCHK(c, hipMemcpyAsync(buf.data(), d.slab[cur], buf.size() * sizeof(real), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        for (int64_t r = 0; r < R; ++r) {
+            const real* sl = buf.data() + (size_t)r * 6 * d.npad;
+            for (int a = 0; a < d.n; ++a)
+                for (int q = 0; q < 3; ++q) {
+                    if (x)
+                        x[((size_t)r * d.n + a) * 3 + q] = (double)sl[q * d.npad + a];
+                    if (v)
+                        v[((size_t)r * d.n + a) * 3 + q] = (double)sl[(3 + q) * d.npad + a];
+                }
+        }
+    }
+    if (Ep && R > 0)
+        HIPCHK(c, hipMemcpyAsync(Ep, d.epot[cur], R * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (Ek && R > 0)
+        HIPCHK(c, hipMemcpyAsync(Ek, d.ekin, R * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (anc && R > 0)
+        HIPCHK(c, hipMemcpyAsync(anc, d.anc[cur], R * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    if (sc) {
+        sc->T = ctl.T_cur;
+        sc->T_prev = ctl.T_prev;
+        sc->sum_lnQ = ctl.sum_lnQ;
+        sc->lnQ_last = ctl.lnQ_last;
+        sc->R = R;
+        sc->step = ctl.step;
+        sc->temp_index = ctl.temp_index;
+    }
+    if (ctl.error)
+        return surface_device_error(c, ctl.error);
+    return PAMD_OK;
+}
+
+pamd_status pamd_get_state(pamd_ctx* c, int32_t run, double* x, double* v, double* E_pot, double* E_kin,
+                           int32_t* ancestor, pamd_run_scalars* scalars, void* stream)
+{
+    if (!c)
+        return PAMD_ERR_ARG;
+    if (run < 0 || run >= c->n_runs)
+        return fail(c, PAMD_ERR_ARG, "run index out of range");
+    hipStream_t s = as_stream(stream);
+    return c->fp32 ? get_state_t<float>(c, c->runs[run], x, v, E_pot, E_kin, ancestor, scalars, s)
+                   : get_state_t<double>(c, c->runs[run], x, v, E_pot, E_kin, ancestor, scalars, s);
+}
+
+template <typename real>
+static pamd_status set_state_t(pamd_ctx* c, Run& run, const double* x, const double* v, const double* Ep,
+                               const int32_t* anc, const pamd_run_scalars* sc, hipStream_t s)
+{
+    RunDev<real>& d = dev<real>(run);
+    const int64_t R = sc->R;
+    if (R < 1 || R > d.R_cap)
+        return fail(c, PAMD_ERR_ARG, "R outside 1..R_cap");
+    if (!(sc->T > 0))
+        return fail(c, PAMD_ERR_ARG, "T must be > 0");
+    RunCtl ctl;
+    pamd_status st = read_ctl<real>(c, run, &ctl, s);
+    if (st != PAMD_OK)
+        return st;
+    const int cur = ctl.cur;
+    std::vector<real> buf((size_t)R * 6 * d.npad);
+    for (int64_t r = 0; r < R; ++r) {
+        real* sl = buf.data() + (size_t)r * 6 * d.npad;
+        for (int a = 0; a < d.npad; ++a) {
+            for (int q = 0; q < 3; ++q) {
+                if (a < d.n) {
+                    sl[q * d.npad + a] = (real)x[((size_t)r * d.n + a) * 3 + q];
+                    sl[(3 + q) * d.npad + a] = (real)v[((size_t)r * d.n + a) * 3 + q];
+                } else {
+                    sl[q * d.npad + a] = (real)(q == 0 ? 1000 + 10 * a : 1000);
+                    sl[(3 + q) * d.npad + a] = (real)0;
+                }
+            }
+        }
+    }
+    std::vector<double> e(R, 0.0);
+    if (Ep)
+        e.assign(Ep, Ep + R);
+    std::vector<int32_t> an(R);
+    for (int64_t r = 0; r < R; ++r)
+        an[r] = anc ? anc[r] : (int32_t)r;
+    HIPCHK(c, hipMemcpyAsync(d.slab[cur], buf.data(), buf.size() * sizeof(real), hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(d.epot[cur], e.data(), R * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(d.anc[cur], an.data(), R * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    ctl.R_cur = R;
+    ctl.R_new = R;
+    ctl.T_cur = sc->T;
+    ctl.T_prev = sc->T_prev > 0 ? sc->T_prev : sc->T;
+    ctl.sum_lnQ = sc->sum_lnQ;
+    ctl.lnQ_last = sc->lnQ_last;
+    ctl.step = sc->step;
+    ctl.temp_index = sc->temp_index;
+    ctl.work = 0;
+    HIPCHK(c, hipMemcpyAsync(d.ctl, &ctl, sizeof(RunCtl), hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    return PAMD_OK;
+}
+
+pamd_status pamd_set_state(pamd_ctx* c, int32_t run, const double* x, const double* v, const double* E_pot,
+                           const int32_t* ancestor, const pamd_run_scalars* scalars, void* stream)
+{
+    pamd_status st = check_ctx(c);
+    if (st != PAMD_OK)
+        return st;
+    if (run < 0 || run >= c->n_runs || !x || !v || !scalars)
+        return fail(c, PAMD_ERR_ARG, "bad run index or null state array");
+    hipStream_t s = as_stream(stream);
+    return c->fp32 ? set_state_t<float>(c, c->runs[run], x, v, E_pot, ancestor, scalars, s)
+                   : set_state_t<double>(c, c->runs[run], x, v, E_pot, ancestor, scalars, s);
+}
+
+template <typename real>
+static pamd_status get_counts_t(pamd_ctx* c, Run& run, int32_t* host_c, int64_t* n, hipStream_t s)
+{
+    RunCtl ctl;
+    pamd_status st = read_ctl<real>(c, run, &ctl, s);
+    if (st != PAMD_OK)
+        return st;
+    const int64_t R = ctl.R_prev;
+    if (n)
+        *n = R;
+    if (host_c && R > 0) {
+        HIPCHK(c, hipMemcpyAsync(host_c, dev<real>(run).counts, R * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+    }
+    return PAMD_OK;
+}
+
+pamd_status pamd_get_counts(pamd_ctx* c, int32_t run, int32_t* host_c, int64_t* n, void* stream)
+{
+    if (!c)
+        return PAMD_ERR_ARG;
+    if (run < 0 || run >= c->n_runs)
+        return fail(c, PAMD_ERR_ARG, "run index out of range");
+    hipStream_t s = as_stream(stream);
+    return c->fp32 ? get_counts_t<float>(c, c->runs[run], host_c, n, s)
+                   : get_counts_t<double>(c, c->runs[run], host_c, n, s);
+}
+
+pamd_status pamd_launch_info(const pamd_ctx* c, int32_t* waves_per_block, int32_t* blocks, int32_t* lds_bytes)
+{
+    if (!c)
+        return PAMD_ERR_ARG;
+    if (waves_per_block)
+        *waves_per_block = c->waves;
+    if (blocks)
+        *blocks = c->blocks;
+    if (lds_bytes)
+        *lds_bytes = (int32_t)c->lds;
+    return PAMD_OK;
+}
+
+void pamd_destroy(pamd_ctx* c) { delete c; }
+
+const char* pamd_last_error(const pamd_ctx* c)
+{
+    if (!c)
+        return "null context";
+    return c->err.c_str();
+}
+

@@ -1,0 +1,288 @@
+"""ctypes binding of libpamd.so (the C ABI in include/pamd.h).
+
+Argument marshalling only: every step of the PAMD path runs in the HIP
+kernels of the library.  PyTorch provides the device buffers and the stream.
+Raises ``RuntimeError`` when the library has not been built (no fallback).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpamd.so")
+
+PAMD_OK, PAMD_ERR_ARG, PAMD_ERR_HIP, PAMD_ERR_CAPACITY, PAMD_ERR_NONFINITE, PAMD_ERR_STATE = range(6)
+PAMD_FP64, PAMD_FP32 = 0, 1
+PAMD_FORCE_CHUNK = 256
+MAX_ATOMS = 80
+
+
+class PamdError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"pamd error {code}: {msg}")
+        self.code = code
+
+
+class pamd_system(C.Structure):
+    _fields_ = [
+        ("n_atoms", C.c_int32), ("n_bonds", C.c_int32), ("n_angles", C.c_int32),
+        ("n_dihedrals", C.c_int32),
+        ("mass", C.c_void_p), ("charge", C.c_void_p), ("sigma", C.c_void_p), ("epsilon", C.c_void_p),
+        ("bond_idx", C.c_void_p), ("bond_k", C.c_void_p), ("bond_r0", C.c_void_p),
+        ("angle_idx", C.c_void_p), ("angle_k", C.c_void_p), ("angle_theta0", C.c_void_p),
+        ("dih_idx", C.c_void_p), ("dih_k", C.c_void_p), ("dih_n", C.c_void_p), ("dih_delta", C.c_void_p),
+        ("scale14_lj", C.c_double), ("scale14_coul", C.c_double), ("coulomb_k", C.c_double),
+        ("dielectric", C.c_int32), ("reserved", C.c_int32), ("kB", C.c_double), ("x_init", C.c_void_p),
+    ]
+
+
+class pamd_params(C.Structure):
+    _fields_ = [
+        ("R_target", C.c_int64), ("R_cap", C.c_int64), ("T0", C.c_double), ("dt", C.c_double),
+        ("nu", C.c_double), ("seed", C.c_uint64), ("precision", C.c_int32),
+        ("waves_per_block", C.c_int32), ("V_target", C.c_double), ("T_final", C.c_double),
+    ]
+
+
+class pamd_obs(C.Structure):
+    _fields_ = [
+        ("T", C.c_double), ("T_prev", C.c_double), ("lnQ_last", C.c_double), ("sum_lnQ", C.c_double),
+        ("V_last", C.c_double), ("E_mean", C.c_double), ("E2_mean", C.c_double), ("K_mean", C.c_double),
+        ("T_measured", C.c_double), ("Cv", C.c_double), ("R", C.c_int64), ("families", C.c_int64),
+        ("temp_index", C.c_int64), ("step", C.c_int64), ("error", C.c_int32), ("reserved", C.c_int32),
+    ]
+
+
+class pamd_run_scalars(C.Structure):
+    _fields_ = [("T", C.c_double), ("T_prev", C.c_double), ("sum_lnQ", C.c_double),
+                ("lnQ_last", C.c_double), ("R", C.c_int64), ("step", C.c_uint32),
+                ("temp_index", C.c_uint32)]
+
+
+EXPORTS = ["pamd_query_sizes", "pamd_init", "pamd_md_steps", "pamd_resample", "pamd_observables",
+           "pamd_get_forces", "pamd_get_state", "pamd_set_state", "pamd_get_counts",
+           "pamd_launch_info", "pamd_destroy", "pamd_last_error"]
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libpamd.so (built by ``python -m paper_1806_06016_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_1806_06016_amd.build` "
+                           "(the PAMD path has no fallback)")
+    lib = C.CDLL(path)
+    vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+    P = C.POINTER
+    lib.pamd_query_sizes.argtypes = [vp, i32, vp, P(C.c_size_t), P(C.c_size_t)]
+    lib.pamd_init.argtypes = [vp, i32, vp, vp, C.c_size_t, vp, C.c_size_t, vp, P(vp)]
+    lib.pamd_md_steps.argtypes = [vp, i32, vp]
+    lib.pamd_resample.argtypes = [vp, vp, vp, vp]
+    lib.pamd_observables.argtypes = [vp, vp, vp]
+    lib.pamd_get_forces.argtypes = [vp, i32, i64, i32, vp, vp, vp]
+    lib.pamd_get_state.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
+    lib.pamd_set_state.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
+    lib.pamd_get_counts.argtypes = [vp, i32, vp, P(i64), vp]
+    lib.pamd_launch_info.argtypes = [vp, P(i32), P(i32), P(i32)]
+    lib.pamd_destroy.argtypes = [vp]
+    lib.pamd_destroy.restype = None
+    lib.pamd_last_error.argtypes = [vp]
+    lib.pamd_last_error.restype = C.c_char_p
+    for name in EXPORTS[:-2]:
+        getattr(lib, name).restype = i32
+    _lib = lib
+    return lib
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data
+
+
+def make_system_struct(sysd, keep: list) -> pamd_system:
+    """Fill a pamd_system from an input-system object (numpy arrays)."""
+    def f64(a):
+        a = np.ascontiguousarray(a, np.float64)
+        keep.append(a)
+        return a.ctypes.data
+
+    def i32(a):
+        a = np.ascontiguousarray(a, np.int32)
+        keep.append(a)
+        return a.ctypes.data
+
+    s = pamd_system()
+    s.n_atoms = int(sysd.n_atoms)
+    s.n_bonds, s.n_angles, s.n_dihedrals = len(sysd.bonds), len(sysd.angles), len(sysd.dihedrals)
+    s.mass, s.charge, s.sigma, s.epsilon = (f64(sysd.mass), f64(sysd.charge), f64(sysd.sigma),
+                                            f64(sysd.epsilon))
+    s.bond_idx, s.bond_k, s.bond_r0 = i32(sysd.bonds), f64(sysd.bond_k), f64(sysd.bond_r0)
+    s.angle_idx, s.angle_k, s.angle_theta0 = i32(sysd.angles), f64(sysd.angle_k), f64(sysd.angle_theta0)
+    s.dih_idx, s.dih_k, s.dih_n, s.dih_delta = (i32(sysd.dihedrals), f64(sysd.dih_k), i32(sysd.dih_n),
+                                                f64(sysd.dih_delta))
+    s.scale14_lj, s.scale14_coul = float(sysd.scale14_lj), float(sysd.scale14_coul)
+    s.coulomb_k, s.dielectric, s.kB = float(sysd.coulomb_k), int(sysd.dielectric), float(sysd.kB)
+    s.x_init = f64(sysd.x_init)
+    return s
+
+
+class Pamd:
+    """One PAMD context: n_runs independent populations on the current GPU."""
+
+    def __init__(self, systems: Sequence, R_target: int, T0: float, dt: float, nu: float, seed: int,
+                 precision: int = PAMD_FP32, R_cap: Optional[int] = None, V_target: float = 0.1,
+                 T_final: Optional[float] = None, waves_per_block: int = 0, stream=None):
+        import torch
+        self.torch = torch
+        self.lib = load_library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("the PAMD library needs a ROCm GPU")
+        self.systems = list(systems)
+        self.n_runs = len(self.systems)
+        self.n_atoms = [int(s.n_atoms) for s in self.systems]
+        if R_cap is None:
+            R_cap = max(int(np.ceil(1.02 * R_target)), R_target + 64)
+        self.R_cap = int(R_cap)
+        self.R_target = int(R_target)
+        self._keep: list = []
+        S = pamd_system * self.n_runs
+        P = pamd_params * self.n_runs
+        self._sys = S(*[make_system_struct(s, self._keep) for s in self.systems])
+        prm = []
+        for r in range(self.n_runs):
+            p = pamd_params()
+            p.R_target, p.R_cap = self.R_target, self.R_cap
+            p.T0, p.dt, p.nu, p.seed = float(T0), float(dt), float(nu), int(seed)
+            p.precision = int(precision)
+            p.waves_per_block = int(waves_per_block)
+            p.V_target = float(V_target)
+            p.T_final = float(T_final if T_final is not None else T0)
+            prm.append(p)
+        self._prm = P(*prm)
+        sb, wb = C.c_size_t(), C.c_size_t()
+        self._check(self.lib.pamd_query_sizes(C.byref(self._sys), self.n_runs, C.byref(self._prm),
+                                              C.byref(sb), C.byref(wb)), None)
+        self.state_bytes, self.work_bytes = sb.value, wb.value
+        self.d_state = torch.empty(self.state_bytes + 256, dtype=torch.uint8, device="cuda")
+        self.d_work = torch.empty(self.work_bytes + 256, dtype=torch.uint8, device="cuda")
+        self._sp = (self.d_state.data_ptr() + 255) // 256 * 256
+        self._wp = (self.d_work.data_ptr() + 255) // 256 * 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        ctx = C.c_void_p()
+        st = self.lib.pamd_init(C.byref(self._sys), self.n_runs, C.byref(self._prm), self._sp,
+                                self.state_bytes, self._wp, self.work_bytes, self._s(), C.byref(ctx))
+        self.ctx = ctx
+        self._check(st, ctx)
+
+    # -- helpers ------------------------------------------------------------
+    def _s(self):
+        return C.c_void_p(self.stream.cuda_stream)
+
+    def _check(self, st: int, ctx):
+        if st != PAMD_OK:
+            msg = self.lib.pamd_last_error(ctx).decode() if ctx else "invalid arguments"
+            raise PamdError(st, msg)
+
+    def last_error(self) -> str:
+        return self.lib.pamd_last_error(self.ctx).decode()
+
+    def launch_info(self) -> Dict[str, int]:
+        w, b, l = C.c_int32(), C.c_int32(), C.c_int32()
+        self._check(self.lib.pamd_launch_info(self.ctx, C.byref(w), C.byref(b), C.byref(l)), self.ctx)
+        return dict(waves_per_block=w.value, blocks=b.value, lds_bytes=l.value)
+
+    # -- PAMD steps -----------------------------------------------------------
+    def md_steps(self, n: int) -> None:
+        self._check(self.lib.pamd_md_steps(self.ctx, int(n), self._s()), self.ctx)
+
+    def resample(self, T_next: Optional[Sequence[float]] = None, uniforms=None) -> None:
+        """T_next: per-run temperatures (<= 0 or None: adaptive).  uniforms: optional
+        torch float64 CUDA tensor [n_runs, R_cap]."""
+        tn = None
+        if T_next is not None:
+            tn = (C.c_double * self.n_runs)(*[float(t) for t in T_next])
+        up = None
+        if uniforms is not None:
+            assert uniforms.is_cuda and uniforms.dtype == self.torch.float64
+            assert uniforms.numel() >= self.n_runs * self.R_cap and uniforms.is_contiguous()
+            up = uniforms.data_ptr()
+        self._check(self.lib.pamd_resample(self.ctx, tn, up, self._s()), self.ctx)
+
+    def observables(self) -> List[Dict]:
+        out = (pamd_obs * self.n_runs)()
+        self._check(self.lib.pamd_observables(self.ctx, out, self._s()), self.ctx)
+        return [{k: getattr(o, k) for k, _ in pamd_obs._fields_} for o in out]
+
+    # -- inspection -------------------------------------------------------------
+    def get_forces(self, run: int = 0, r0: int = 0, count: Optional[int] = None):
+        n = self.n_atoms[run]
+        st = self.get_state(run, want_xv=False)
+        R = st["R"]
+        count = R - r0 if count is None else count
+        F = np.zeros((count, n, 3))
+        E = np.zeros(count)
+        for c0 in range(0, count, PAMD_FORCE_CHUNK):
+            c = min(PAMD_FORCE_CHUNK, count - c0)
+            Fc = np.zeros((c, n, 3))
+            Ec = np.zeros(c)
+            self._check(self.lib.pamd_get_forces(self.ctx, run, r0 + c0, c, _ptr(Fc), _ptr(Ec), self._s()),
+                        self.ctx)
+            F[c0:c0 + c] = Fc
+            E[c0:c0 + c] = Ec
+        return F, E
+
+    def get_state(self, run: int = 0, want_xv: bool = True) -> Dict:
+        n = self.n_atoms[run]
+        sc = pamd_run_scalars()
+        x = np.zeros((self.R_cap, n, 3)) if want_xv else None
+        v = np.zeros((self.R_cap, n, 3)) if want_xv else None
+        Ep = np.zeros(self.R_cap)
+        Ek = np.zeros(self.R_cap)
+        anc = np.zeros(self.R_cap, np.int32)
+        self._check(self.lib.pamd_get_state(self.ctx, run, _ptr(x), _ptr(v), _ptr(Ep), _ptr(Ek), _ptr(anc),
+                                            C.byref(sc), self._s()), self.ctx)
+        R = int(sc.R)
+        d = dict(R=R, T=sc.T, T_prev=sc.T_prev, sum_lnQ=sc.sum_lnQ, lnQ_last=sc.lnQ_last, step=int(sc.step),
+                 temp_index=int(sc.temp_index), E_pot=Ep[:R].copy(), E_kin=Ek[:R].copy(),
+                 ancestor=anc[:R].copy())
+        if want_xv:
+            d["x"] = x[:R].copy()
+            d["v"] = v[:R].copy()
+        return d
+
+    def set_state(self, run: int, x: np.ndarray, v: np.ndarray, T: float, step: int = 0, temp_index: int = 0,
+                  E_pot: Optional[np.ndarray] = None, ancestor: Optional[np.ndarray] = None,
+                  T_prev: Optional[float] = None, sum_lnQ: float = 0.0, lnQ_last: float = 0.0) -> None:
+        x = np.ascontiguousarray(x, np.float64)
+        v = np.ascontiguousarray(v, np.float64)
+        R = x.shape[0]
+        sc = pamd_run_scalars()
+        sc.T, sc.T_prev, sc.sum_lnQ, sc.lnQ_last = float(T), float(T_prev or T), float(sum_lnQ), float(lnQ_last)
+        sc.R, sc.step, sc.temp_index = R, int(step), int(temp_index)
+        Ep = None if E_pot is None else np.ascontiguousarray(E_pot, np.float64)
+        an = None if ancestor is None else np.ascontiguousarray(ancestor, np.int32)
+        self._check(self.lib.pamd_set_state(self.ctx, run, _ptr(x), _ptr(v), _ptr(Ep), _ptr(an), C.byref(sc),
+                                            self._s()), self.ctx)
+
+    def get_counts(self, run: int = 0) -> np.ndarray:
+        c = np.zeros(self.R_cap, np.int32)
+        n = C.c_int64()
+        self._check(self.lib.pamd_get_counts(self.ctx, run, _ptr(c), C.byref(n), self._s()), self.ctx)
+        return c[:n.value].copy()
+
+    def close(self) -> None:
+        if getattr(self, "ctx", None):
+            self.lib.pamd_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

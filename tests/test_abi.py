@@ -1,0 +1,97 @@
+"""CPU checks of the C ABI boundary: the library loads and exports every entry
+point declared in include/pamd.h, the binding's structures match the header's
+field lists, and the build does not leave packed-FP32 instructions behind."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pamd.h")
+LIB = os.path.join(ROOT, "paper_1806_06016_amd", "libpamd.so")
+
+
+def _declared_functions():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(pamd_[a-z_]+)\s*\(", txt)))
+
+
+def _struct_fields(name):
+    txt = open(HEADER).read()
+    m = re.search(r"typedef struct " + name + r" \{(.*?)\} " + name + ";", txt, re.S)
+    body = re.sub(r"/\*.*?\*/", "", m.group(1), flags=re.S)
+    fields = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        decl = re.sub(r"\bconst\b", "", decl)
+        parts = decl.split(None, 1)
+        for nm in parts[1].split(","):
+            fields.append(nm.strip().lstrip("*").strip())
+    return fields
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libpamd.so not built")
+def test_library_exports_every_declared_entry_point():
+    lib = ctypes.CDLL(LIB)
+    names = _declared_functions()
+    assert "pamd_init" in names and "pamd_md_steps" in names and "pamd_resample" in names
+    assert "pamd_observables" in names
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_structs_match_header():
+    from paper_1806_06016_amd import pamd as B
+    for cname, py in [("pamd_system", B.pamd_system), ("pamd_params", B.pamd_params),
+                      ("pamd_obs", B.pamd_obs), ("pamd_run_scalars", B.pamd_run_scalars)]:
+        assert [f for f, _ in py._fields_] == _struct_fields(cname), cname
+
+
+def test_binding_exports_list_matches_header():
+    from paper_1806_06016_amd import pamd as B
+    assert sorted(B.EXPORTS) == _declared_functions()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libpamd.so not built")
+def test_query_sizes_is_host_only_and_validates():
+    """pamd_query_sizes needs no GPU; it rejects bad descriptors."""
+    import numpy as np
+    from paper_1806_06016_amd import pamd as B
+    from pamd_inputs import systems as S
+    lib = B.load_library()
+    keep = []
+    sysd = S.c2_system()
+    s = B.make_system_struct(sysd, keep)
+    p = B.pamd_params()
+    p.R_target, p.R_cap, p.T0, p.dt, p.nu, p.seed, p.precision = 1000, 1100, 700.0, 0.001, 1.0, 1, 1
+    sb, wb = ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.pamd_query_sizes(ctypes.byref(s), 1, ctypes.byref(p), ctypes.byref(sb), ctypes.byref(wb)) == 0
+    # 2 ping-pong slabs of R_cap x 6 x 80 floats dominate the state
+    assert sb.value >= 2 * 1100 * 6 * 80 * 4
+    p.R_cap = 10
+    assert lib.pamd_query_sizes(ctypes.byref(s), 1, ctypes.byref(p), ctypes.byref(sb),
+                                ctypes.byref(wb)) == B.PAMD_ERR_ARG
+    p.R_cap = 1100
+    bad = S.c2_system()
+    bad.dih_delta = bad.dih_delta + 0.3        # only 0 / pi phases are supported
+    sb2 = B.make_system_struct(bad, keep)
+    assert lib.pamd_query_sizes(ctypes.byref(sb2), 1, ctypes.byref(p), ctypes.byref(sb),
+                                ctypes.byref(wb)) == B.PAMD_ERR_ARG
+    big = S.make_peptide(1806, 120)            # more atoms than the register tiles hold
+    s3 = B.make_system_struct(big, keep)
+    assert lib.pamd_query_sizes(ctypes.byref(s3), 1, ctypes.byref(p), ctypes.byref(sb),
+                                ctypes.byref(wb)) == B.PAMD_ERR_ARG
+
+
+def test_binding_fails_loudly_without_library(tmp_path):
+    from paper_1806_06016_amd import pamd as B
+    saved = B._lib
+    B._lib = None
+    try:
+        with pytest.raises(RuntimeError, match="missing"):
+            B.load_library(str(tmp_path / "nope.so"))
+    finally:
+        B._lib = saved

@@ -1,0 +1,274 @@
+"""GPU parity of the HIP path against the FP64 oracle (needs an MI355X).
+
+Every call goes through libpamd's C ABI.  Tolerances:
+  * forces: per atom |F_gpu - F_ora| <= tol (|F_ora,a| + F_rms) with tol = 1e-4 in FP32
+    (pair terms and force sums in FP32) and 1e-9 in FP64; energies within
+    1e-5 (FP32) / 1e-10 (FP64) of sum |terms|;
+  * trajectories: positions within 1e-4 nm after 100 steps (FP32, identical
+    Philox streams), 1e-8 reduced units in FP64;
+  * copy numbers: bit-exact given the same energies and uniforms;
+  * log-sum-exp / ln Q: 1e-12 relative (FP64 on both sides, different
+    summation order).
+"""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle import oracle as O  # noqa: E402
+from pamd_inputs import systems as S  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1806_06016_amd import pamd as B
+    B.load_library()
+    return B
+
+
+def _ctx(B, sysd, R, prec, T0=None, dt=None, nu=1.0, seed=1806, **kw):
+    if T0 is None:
+        T0 = 2.0 if sysd.units == "reduced" else 700.0
+    if dt is None:
+        dt = 0.002 if sysd.units == "reduced" else 0.001
+    return B.Pamd([sysd], R_target=R, T0=T0, dt=dt, nu=nu, seed=seed, precision=prec, **kw)
+
+
+def _force_check(F, Fo, tol):
+    frms = np.sqrt((Fo ** 2).sum(-1).mean(-1))[:, None]
+    err = np.linalg.norm(F - Fo, axis=-1)
+    bound = tol * (np.linalg.norm(Fo, axis=-1) + frms)
+    return float((err / bound).max())
+
+
+def _perturbed(sysd, R, scale, seed):
+    rng = np.random.default_rng(seed)
+    return np.ascontiguousarray(sysd.x_init[None] + rng.normal(0, scale, size=(R,) + sysd.x_init.shape))
+
+
+@pytest.mark.parametrize("which,prec", [("chain", 0), ("peptide", 1), ("chain", 1)])
+def test_forces_and_energies(gpu, which, prec):
+    sysd = S.c1_system() if which == "chain" else S.c2_system()
+    R = 37                                 # ragged: not a multiple of the 4 replicas per wave
+    print(f"forces {which} prec={prec}", flush=True)
+    p = _ctx(gpu, sysd, R, prec)
+    x = _perturbed(sysd, R, 0.1 if which == "chain" else 0.01, 5)
+    v = np.zeros_like(x)
+    p.set_state(0, x, v, T=700.0 if which == "peptide" else 2.0)
+    xs = p.get_state(0)["x"]               # the positions as the GPU holds them
+    F, E = p.get_forces(0)
+    osys = O.OracleSystem(sysd)
+    Eo, Fo, terms = O.energy_forces(osys, xs, want_terms=True)
+    tolF = 1e-9 if prec == 0 else 1e-4
+    tolE = 1e-10 if prec == 0 else 1e-5
+    assert _force_check(F, Fo, tolF) <= 1.0
+    assert np.all(np.abs(E - Eo) <= tolE * np.abs(terms).sum(1))
+    p.close()
+
+
+def test_init_velocities_match_oracle(gpu):
+    for sysd, prec in [(S.c1_system(), 0), (S.c2_system(), 1)]:
+        R = 21
+        p = _ctx(gpu, sysd, R, prec)
+        st = p.get_state(0)
+        osys = O.OracleSystem(sysd)
+        vo = O.init_velocities(osys, R, 2.0 if prec == 0 else 700.0, seed=1806)
+        rel = np.abs(st["v"] - vo).max() / np.abs(vo).max()
+        assert rel < (1e-14 if prec == 0 else 1e-6), rel
+        assert np.abs(st["x"] - sysd.x_init[None]).max() < (1e-15 if prec == 0 else 1e-6)
+        assert (st["ancestor"] == np.arange(R)).all() and st["R"] == R
+        p.close()
+
+
+@pytest.mark.parametrize("which,prec,nsteps,tol", [("peptide", 1, 100, 1e-4), ("chain", 0, 100, 1e-8),
+                                                    ("chain", 1, 100, 1e-4)])
+def test_trajectory_matches_oracle(gpu, which, prec, nsteps, tol):
+    """Same start, same Philox streams: positions agree after 100 NVT steps
+    (Andersen collisions happen at the same atoms and steps on both sides)."""
+    sysd = S.c1_system() if which == "chain" else S.c2_system()
+    R = 45
+    T = 700.0 if which == "peptide" else 1.3
+    nu = 1.0 if which == "peptide" else 5.0
+    print(f"trajectory {which} prec={prec}", flush=True)
+    p = _ctx(gpu, sysd, R, prec, T0=T, nu=nu, seed=77)
+    osys = O.OracleSystem(sysd)
+    x = _perturbed(sysd, R, 0.005 if which == "peptide" else 0.05, 8)
+    v = O.init_velocities(osys, R, T, seed=3)
+    p.set_state(0, x, v, T=T, step=500)
+    st = p.get_state(0)
+    xo, vo = st["x"].copy(), st["v"].copy()
+    p.md_steps(nsteps)
+    g = p.get_state(0)
+    Ep, Ek, col = O.md_steps(osys, xo, vo, nsteps, T, 0.001 if which == "peptide" else 0.002, nu, 77,
+                             step0=500, want_collisions=True)
+    assert col.sum() > 0                       # the thermostat actually acted
+    err = np.abs(g["x"] - xo).max()
+    assert err < tol, err
+    assert g["step"] == 500 + nsteps
+    scale = np.abs(Ep).mean()
+    assert np.abs(g["E_pot"] - Ep).max() <= (1e-3 if prec else 1e-9) * scale
+    assert np.allclose(g["E_kin"], Ek, rtol=1e-3 if prec else 1e-9)
+    p.close()
+
+
+def _synthetic_population(p, sysd, R, E, T, seed=0):
+    rng = np.random.default_rng(seed)
+    x = _perturbed(sysd, R, 0.01, seed)
+    v = rng.normal(size=x.shape)
+    p.set_state(0, x, v, T=T, E_pot=E, ancestor=np.arange(R) + 1000 * 0)
+    return p.get_state(0)
+
+
+@pytest.mark.parametrize("R", [1, 7, 1000, 4099])
+def test_resample_counts_bit_exact_given_uniforms(gpu, R):
+    sysd = S.c2_system()
+    rng = np.random.default_rng(R)
+    E = rng.normal(-500.0, 25.0, R)
+    T0, T1 = 700.0, 650.0
+    p = _ctx(gpu, sysd, R, 1, R_cap=max(2 * R, R + 64))
+    st = _synthetic_population(p, sysd, R, E, T0, seed=R)
+    u = rng.random(p.R_cap)
+    ut = torch.tensor(u, dtype=torch.float64, device="cuda")
+    p.resample([T1], uniforms=ut)
+    c = p.get_counts(0)
+    dbeta = 1 / (sysd.kB * T1) - 1 / (sysd.kB * T0)
+    co, tau = O.copy_counts(st["E_pot"], dbeta, R, u[:R])
+    mism = np.nonzero(c != co)[0]
+    if len(mism):
+        margin = np.abs(u[mism] - (tau[mism] - np.floor(tau[mism])))
+        pytest.fail(f"{len(mism)} copy numbers differ; margins {margin[:5]}")
+    g = p.get_state(0)
+    m, S_, S2, lq = O.lse(st["E_pot"], dbeta)
+    assert abs(g["lnQ_last"] - lq) <= 1e-12 * max(1.0, abs(lq))
+    assert abs(g["sum_lnQ"] - lq) <= 1e-12 * max(1.0, abs(lq))
+    assert g["R"] == co.sum() and g["temp_index"] == 1
+    assert abs(g["T"] - T1) < 1e-12 and abs(g["T_prev"] - T0) < 1e-12
+    # gather: canonical order, ancestors, energies, recentred x, rescaled v
+    xo, vo, Eo, ao = O.gather(co, [st["x"], st["v"], st["E_pot"], st["ancestor"]])
+    assert (g["ancestor"] == ao).all()
+    assert (g["E_pot"] == Eo).all()
+    xo = O.recentre(xo, sysd.mass)
+    assert np.abs(g["x"] - xo).max() < 2e-6
+    assert np.abs(g["v"] - vo * math.sqrt(T1 / T0)).max() < 1e-6 * np.abs(vo).max()
+    p.close()
+
+
+def test_resample_philox_uniforms_match_oracle(gpu):
+    sysd = S.c1_system()
+    R = 3000
+    rng = np.random.default_rng(2)
+    E = rng.normal(10.0, 3.0, R)
+    p = _ctx(gpu, sysd, R, 0, seed=4242)
+    st = _synthetic_population(p, sysd, R, E, 2.0)
+    p.resample([1.8])
+    c = p.get_counts(0)
+    u = O.resample_uniforms(R, 1, seed=4242)
+    co, _ = O.copy_counts(st["E_pot"], 1 / 1.8 - 1 / 2.0, R, u)
+    assert (c == co).all()
+    p.close()
+
+
+def test_adaptive_temperature_matches_oracle(gpu):
+    """Adaptive step: largest T-decrement with normalised weight variance 0.1."""
+    sysd = S.c2_system()
+    R = 20000
+    rng = np.random.default_rng(9)
+    T0 = 700.0
+    d = 219
+    E = rng.gamma(d / 2, sysd.kB * T0, R) - 800.0
+    p = _ctx(gpu, sysd, R, 1, T0=T0, T_final=250.0, V_target=0.1)
+    st = _synthetic_population(p, sysd, R, E, T0)
+    p.resample(None)
+    g = p.get_state(0)
+    kB = sysd.kB
+    dmax = 1 / (kB * 250.0) - 1 / (kB * T0)
+    db = O.adaptive_dbeta(st["E_pot"], dmax, 0.1)
+    To = 1 / (kB * (db + 1 / (kB * T0)))
+    assert abs(g["T"] - To) <= 1e-9 * To, (g["T"], To)
+    V = O.weight_variance(st["E_pot"], 1 / (kB * To) - 1 / (kB * T0))
+    assert abs(V - 0.1) < 1e-6
+    obs = p.observables()[0]
+    assert abs(obs["V_last"] - V) < 1e-9
+    p.close()
+
+
+def test_observables_match_oracle(gpu):
+    sysd = S.c2_system()
+    R = 333
+    p = _ctx(gpu, sysd, R, 1)
+    p.md_steps(10)
+    obs = p.observables()[0]
+    st = p.get_state(0)
+    o = O.observables(st["E_pot"], st["E_kin"], st["ancestor"], sysd.n_atoms, sysd.kB, 700.0)
+    for k in ("E_mean", "E2_mean", "K_mean", "T_measured", "Cv"):
+        assert abs(obs[k] - o[k]) <= 1e-12 * abs(o[k]) + 1e-12, k
+    assert obs["R"] == R and obs["families"] == R and obs["step"] == 10
+    p.close()
+
+
+def test_capacity_overflow_is_reported_and_state_kept(gpu):
+    from paper_1806_06016_amd import PamdError, PAMD_ERR_CAPACITY
+    sysd = S.c1_system()
+    R = 200
+    E = np.zeros(R)
+    E[:100] = 0.0
+    E[100:] = 50.0
+    p = _ctx(gpu, sysd, R, 0, R_cap=220)
+    _synthetic_population(p, sysd, R, E, 2.0)
+    # half of the copies get ~2 copies each only if weights are flat; make them not:
+    u = torch.zeros(p.R_cap, dtype=torch.float64, device="cuda")      # every fractional part rounds up
+    p.resample([1.0], uniforms=u)
+    with pytest.raises(PamdError) as ei:
+        p.observables()
+    assert ei.value.code in (PAMD_ERR_CAPACITY,)
+    p.close()
+
+
+def test_nonfinite_energy_is_reported(gpu):
+    from paper_1806_06016_amd import PamdError, PAMD_ERR_NONFINITE
+    sysd = S.c2_system()
+    R = 8
+    p = _ctx(gpu, sysd, R, 1)
+    x = _perturbed(sysd, R, 0.01, 1)
+    x[3, 5, 0] = np.nan
+    p.set_state(0, x, np.zeros_like(x), T=700.0)
+    p.md_steps(0)
+    with pytest.raises(PamdError) as ei:
+        p.observables()
+    assert ei.value.code == PAMD_ERR_NONFINITE
+    p.close()
+
+
+def test_determinism_same_seed_same_state(gpu):
+    sysd = S.c2_system()
+    out = []
+    for _ in range(2):
+        p = _ctx(gpu, sysd, 130, 1, seed=99)
+        p.md_steps(50)
+        p.resample([650.0])
+        p.md_steps(50)
+        st = p.get_state(0)
+        out.append((st["x"], st["v"], st["E_pot"]))
+        p.close()
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
+
+
+def test_copies_decorrelate(gpu):
+    """Two copies of one configuration separate under the stochastic thermostat
+    (their collision streams are keyed by distinct slots)."""
+    sysd = S.c2_system()
+    R = 16
+    p = _ctx(gpu, sysd, R, 1)
+    x = np.ascontiguousarray(np.broadcast_to(sysd.x_init, (R, sysd.n_atoms, 3)))
+    v = np.zeros_like(x)
+    p.set_state(0, x, v, T=700.0)
+    p.md_steps(200)
+    st = p.get_state(0)
+    assert np.abs(st["x"][0] - st["x"][1]).max() > 1e-3
+    p.close()
