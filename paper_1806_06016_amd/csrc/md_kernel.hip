@@ -290,7 +290,7 @@ __device__ __forceinline__ void bonded_terms(const RunDev<real>& d, const real* 
             }
         }
     }
-    // dihedrals: U = kc (1 + cos(n phi)) with kc = k cos(delta), delta in {0, pi}
+    // dihedrals: U = k (1 + cos(n phi - delta)) = k + kc cos(n phi), kc = k cos(delta), delta in {0, pi}
     for (int t0 = 0; t0 < d.nd; t0 += kRow) {
         const int t = t0 + l16;
         if (t < d.nd) {
@@ -327,7 +327,8 @@ __device__ __forceinline__ void bonded_terms(const RunDev<real>& d, const real* 
                 uc = un;
             }
             if constexpr (ENERGY) {
-                eacc += (double)(kc * ((real)1 + tc));
+                // k (1 + cos(n phi - delta)) = |kc| + kc cos(n phi)
+                eacc += (double)(fabs(kc) + kc * tc);
             } else {
                 // dU/dphi = -kc n sin(n phi) = -kc n sin(phi) U_{n-1}(cos phi)
                 const real dU = -kc * (real)nmul * s * uc;
