@@ -15,8 +15,9 @@
 //     Coulomb factor with exclusions / 1-4 scaling folded in) sit in LDS,
 //     shared by every replica of the workgroup;
 //   * bonded terms: positions are staged in a per-replica LDS slice, each
-//     lane evaluates one term per pass and scatters its forces with LDS
-//     float atomics;
+//     lane evaluates one term per pass and scatters its forces with plain LDS
+//     read-modify-writes (terms packed so that no two lanes of a pass touch
+//     the same atom in the same role);
 //   * persistent workgroups pull groups of four replicas from a device work
 //     counter, so the launch needs no host-side knowledge of R.
 //
@@ -115,15 +116,32 @@ struct Regs {
 // ---------------------------------------------------------------------------
 // nonbonded pair step: pair (atom of lane l in block I, atom of lane l-K in block J)
 // ---------------------------------------------------------------------------
+// pair coefficients of one tile step, loaded one step ahead of their use
+template <typename real>
+struct Coef {
+    real A, nB, C;   // 12 c12 s, -6 c6 s, Coulomb factor (2 k q q s / 4 for eps = 4r; k q q s for 1/r)
+};
+
+// ab_lane / c_lane point at this lane's entry of step 0; step st sits a
+// constant 16 entries further per step, so every read is an immediate offset
+// from one base register
+template <int ST, typename real>
+__device__ __forceinline__ Coef<real> load_coef(const real* ab_lane, const real* c_lane)
+{
+    Coef<real> c;
+    c.A = ab_lane[ST * 32];
+    c.nB = ab_lane[ST * 32 + 1];
+    c.C = c_lane[ST * 16];
+    return c;
+}
+
 template <typename real, int DIEL, int KBACK, bool ENERGY>
 __device__ __forceinline__ void pair_step(real xi, real yi, real zi, real xjr, real yjr, real zjr,
                                           real& fxi, real& fyi, real& fzi, real& fxj, real& fyj,
-                                          real& fzj, const real* ab, const real* cc, double& eacc)
+                                          real& fzj, const Coef<real>& cf, double& eacc)
 {
     // (xjr, yjr, zjr): position of the partner atom, already rotated to this lane
-    const real A = ab[0];    // 12 c12 s
-    const real nB = ab[1];   // -6 c6 s
-    const real C = cc[0];    // Coulomb factor (2 k q q s / 4 for eps = 4r; k q q s for 1/r)
+    const real A = cf.A, nB = cf.nB, C = cf.C;
     const real dx = xjr - xi;
     const real dy = yjr - yi;
     const real dz = zjr - zi;
@@ -170,6 +188,12 @@ template <typename real, int NS, int DIEL, bool ENERGY>
 __device__ __forceinline__ void nonbonded(Regs<real, NS>& r, const real* tab_ab, const real* tab_c, int l16,
                                           double& eacc)
 {
+    constexpr int NST = tile_steps(NS);
+    const real* ab_lane = tab_ab + 2 * l16;
+    const real* c_lane = tab_c + l16;
+    // software pipeline: the LDS reads of step st + 1 are issued before the
+    // arithmetic of step st, so their latency hides behind it
+    Coef<real> cur = load_coef<0>(ab_lane, c_lane);
     static_for<0, NS>([&](auto Jc) {
         constexpr int J = decltype(Jc)::value;
         constexpr int base = col_base(J);
@@ -178,10 +202,11 @@ __device__ __forceinline__ void nonbonded(Regs<real, NS>& r, const real* tab_ab,
         static_for<1, 9>([&](auto Kc) {
             constexpr int K = decltype(Kc)::value;
             constexpr int st = base + K - 1;
-            pair_step<real, DIEL, (16 - K) & 15, ENERGY>(
-                r.x[J], r.y[J], r.z[J], rowrot<K>(r.x[J]), rowrot<K>(r.y[J]), rowrot<K>(r.z[J]), r.fx[J],
-                r.fy[J], r.fz[J], r.fx[J], r.fy[J], r.fz[J], tab_ab + (st * 16 + l16) * 2,
-                tab_c + st * 16 + l16, eacc);
+            const Coef<real> nxt = load_coef<(st + 1 < NST ? st + 1 : st)>(ab_lane, c_lane);
+            pair_step<real, DIEL, (16 - K) & 15, ENERGY>(r.x[J], r.y[J], r.z[J], rowrot<K>(r.x[J]),
+                                                         rowrot<K>(r.y[J]), rowrot<K>(r.z[J]), r.fx[J], r.fy[J],
+                                                         r.fz[J], r.fx[J], r.fy[J], r.fz[J], cur, eacc);
+            cur = nxt;
             // one pair step per scheduling region: the steps are independent up
             // to the force sums, and an unbounded window hoists the displacement
             // math of many steps into spilled registers
@@ -194,10 +219,10 @@ __device__ __forceinline__ void nonbonded(Regs<real, NS>& r, const real* tab_ab,
             static_for<0, J>([&](auto Ic) {
                 constexpr int I = decltype(Ic)::value;
                 constexpr int st = base + 8 + K * J + I;
+                const Coef<real> nxt = load_coef<(st + 1 < NST ? st + 1 : st)>(ab_lane, c_lane);
                 pair_step<real, DIEL, (16 - K) & 15, ENERGY>(r.x[I], r.y[I], r.z[I], xr, yr, zr, r.fx[I], r.fy[I],
-                                                             r.fz[I], r.fx[J], r.fy[J], r.fz[J],
-                                                             tab_ab + (st * 16 + l16) * 2, tab_c + st * 16 + l16,
-                                                             eacc);
+                                                             r.fz[I], r.fx[J], r.fy[J], r.fz[J], cur, eacc);
+                cur = nxt;
                 __builtin_amdgcn_sched_barrier(0);
             });
         });
@@ -215,13 +240,17 @@ __device__ __forceinline__ void ld3(const real* p, int a, real* v)
     v[2] = p[3 * a + 2];
 }
 
+// Scatter of a bonded-term force into the replica's LDS force stage.  Plain
+// read-modify-write (LDS float atomics are far slower): the host packs the
+// terms so that, within one pass of 16 lanes, no two lanes name the same atom
+// in the same role, and the roles are scattered one after the other.
 template <typename real, bool ENERGY>
 __device__ __forceinline__ void add3(real* frc, int a, real fx, real fy, real fz)
 {
     if constexpr (!ENERGY) {
-        lds_add(&frc[3 * a], fx);
-        lds_add(&frc[3 * a + 1], fy);
-        lds_add(&frc[3 * a + 2], fz);
+        frc[3 * a] += fx;
+        frc[3 * a + 1] += fy;
+        frc[3 * a + 2] += fz;
     }
 }
 
@@ -231,8 +260,8 @@ __device__ __forceinline__ void bonded_terms(const RunDev<real>& d, const real* 
     // bonds: U = 1/2 k (r - r0)^2
     for (int t0 = 0; t0 < d.nb; t0 += kRow) {
         const int t = t0 + l16;
-        if (t < d.nb) {
-            const int4 ix = d.bidx[t];
+        const int4 ix = d.bidx[t];
+        if (ix.x >= 0) {
             const real k = d.bpar[2 * t], r0 = d.bpar[2 * t + 1];
             real pi[3], pj[3];
             ld3(pos, ix.x, pi);
@@ -253,8 +282,8 @@ __device__ __forceinline__ void bonded_terms(const RunDev<real>& d, const real* 
     // angles: U = 1/2 k (theta - theta0)^2, theta = atan2(|u x w|, u.w)
     for (int t0 = 0; t0 < d.na; t0 += kRow) {
         const int t = t0 + l16;
-        if (t < d.na) {
-            const int4 ix = d.aidx[t];
+        const int4 ix = d.aidx[t];
+        if (ix.x >= 0) {
             const real k = d.apar[2 * t], th0 = d.apar[2 * t + 1];
             real pi[3], pj[3], pk[3];
             ld3(pos, ix.x, pi);
@@ -293,8 +322,8 @@ __device__ __forceinline__ void bonded_terms(const RunDev<real>& d, const real* 
     // dihedrals: U = k (1 + cos(n phi - delta)) = k + kc cos(n phi), kc = k cos(delta), delta in {0, pi}
     for (int t0 = 0; t0 < d.nd; t0 += kRow) {
         const int t = t0 + l16;
-        if (t < d.nd) {
-            const int4 ix = d.didx[t];
+        const int4 ix = d.didx[t];
+        if (ix.x >= 0) {
             const real kc = d.dpar[2 * t];
             const int nmul = (int)d.dpar[2 * t + 1];
             real pi[3], pj[3], pk[3], pl[3];
@@ -452,30 +481,37 @@ __device__ __forceinline__ void store_replica(const Regs<real, NS>& r, real* sla
     }
 }
 
-// three standard normals from one Philox draw (Box-Muller)
-template <typename real>
-__device__ __forceinline__ void normals3(const u32x4& w, real* z)
+// three standard normals from one Philox draw (Box-Muller); the FP32 path
+// uses the hardware sine / cosine (argument in revolutions, which is what
+// the uniform already is) and logarithm
+__device__ __forceinline__ void normals3(const u32x4& w, float* z)
 {
-    const real s24 = (real)(1.0 / 16777216.0);
-    const real u0 = ((real)(w.v[0] >> 8) + (real)0.5) * s24;
-    const real u1 = ((real)(w.v[1] >> 8) + (real)0.5) * s24;
-    const real u2 = ((real)(w.v[2] >> 8) + (real)0.5) * s24;
-    const real u3 = ((real)(w.v[3] >> 8) + (real)0.5) * s24;
-    const real two_pi = (real)6.283185307179586476925286766559;
-    const real r0 = sqrt_((real)-2 * log_(u0));
-    const real r1 = sqrt_((real)-2 * log_(u2));
-    real s0, c0, s1, c1;
-    sincos_(two_pi * u1, &s0, &c0);
-    sincos_(two_pi * u3, &s1, &c1);
-    z[0] = r0 * c0;
-    z[1] = r0 * s0;
-    z[2] = r1 * c1;
+    const float s24 = 1.0f / 16777216.0f;
+    const float u0 = ((float)(w.v[0] >> 8) + 0.5f) * s24;
+    const float u1 = ((float)(w.v[1] >> 8) + 0.5f) * s24;
+    const float u2 = ((float)(w.v[2] >> 8) + 0.5f) * s24;
+    const float u3 = ((float)(w.v[3] >> 8) + 0.5f) * s24;
+    const float ln2 = 0.693147180559945309f;
+    const float r0 = __builtin_sqrtf(-2.0f * ln2 * __builtin_amdgcn_logf(u0));
+    const float r1 = __builtin_sqrtf(-2.0f * ln2 * __builtin_amdgcn_logf(u2));
+    z[0] = r0 * __builtin_amdgcn_cosf(u1);
+    z[1] = r0 * __builtin_amdgcn_sinf(u1);
+    z[2] = r1 * __builtin_amdgcn_cosf(u3);
 }
-
-struct Lds {
-    template <typename real, int NS>
-    static constexpr size_t table_elems() { return (size_t)tile_steps(NS) * 16 * 3; }
-};
+__device__ __forceinline__ void normals3(const u32x4& w, double* z)
+{
+    const double s24 = 1.0 / 16777216.0;
+    const double u0 = ((double)(w.v[0] >> 8) + 0.5) * s24;
+    const double u1 = ((double)(w.v[1] >> 8) + 0.5) * s24;
+    const double u2 = ((double)(w.v[2] >> 8) + 0.5) * s24;
+    const double u3 = ((double)(w.v[3] >> 8) + 0.5) * s24;
+    const double two_pi = 6.283185307179586476925286766559;
+    const double r0 = sqrt(-2.0 * log(u0));
+    const double r1 = sqrt(-2.0 * log(u2));
+    z[0] = r0 * cos(two_pi * u1);
+    z[1] = r0 * sin(two_pi * u1);
+    z[2] = r1 * cos(two_pi * u3);
+}
 
 // ---------------------------------------------------------------------------
 // the persistent MD kernel
@@ -538,57 +574,61 @@ __global__ __launch_bounds__(1024) void k_md(RunDev<real> d, int n_steps)
         Regs<real, NS> r;
         load_replica<real, NS>(r, slab, d.n, l16);
         double eacc = 0.0;
-        evaluate<real, NS, DIEL, false>(r, d, tab_ab, tab_c, pos, frc, l16, eacc);
-
-        for (int st = 0; st < n_steps; ++st) {
+        // velocity Verlet with the force evaluation at the top of each pass:
+        // pass st evaluates F(x_st), finishes step st - 1 (second half kick,
+        // collisions) and starts step st (first half kick, drift)
+        for (int st = 0; st <= n_steps; ++st) {
             // compiler-only memory barrier: keeps the (step-invariant) term
             // records and pair coefficients from being hoisted out of the step
             // loop into hundreds of live registers
             asm volatile("" ::: "memory");
-#pragma unroll
-            for (int s = 0; s < NS; ++s) {
-                r.vx[s] += hdtm[s] * r.fx[s];
-                r.vy[s] += hdtm[s] * r.fy[s];
-                r.vz[s] += hdtm[s] * r.fz[s];
-                r.x[s] += dt * r.vx[s];
-                r.y[s] += dt * r.vy[s];
-                r.z[s] += dt * r.vz[s];
-            }
             evaluate<real, NS, DIEL, false>(r, d, tab_ab, tab_c, pos, frc, l16, eacc);
+            if (st > 0) {
 #pragma unroll
-            for (int s = 0; s < NS; ++s) {
-                r.vx[s] += hdtm[s] * r.fx[s];
-                r.vy[s] += hdtm[s] * r.fy[s];
-                r.vz[s] += hdtm[s] * r.fz[s];
-            }
-            // Andersen collisions
-            if (d.p24 != 0u) {
-                const uint32_t gstep = step0 + (uint32_t)st;
+                for (int s = 0; s < NS; ++s) {
+                    r.vx[s] += hdtm[s] * r.fx[s];
+                    r.vy[s] += hdtm[s] * r.fy[s];
+                    r.vz[s] += hdtm[s] * r.fz[s];
+                }
+                // Andersen collisions
+                if (d.p24 != 0u) {
+                    const uint32_t gstep = step0 + (uint32_t)(st - 1);
 #pragma unroll
-                for (int q = 0; q < (NS + 3) / 4; ++q) {
-                    const u32x4 w = philox10((uint32_t)ls, gstep, (uint32_t)(l16 + 16 * q), kStreamCollide,
-                                             d.key0, d.key1);
+                    for (int q = 0; q < (NS + 3) / 4; ++q) {
+                        const u32x4 w = philox10((uint32_t)ls, gstep, (uint32_t)(l16 + 16 * q), kStreamCollide,
+                                                 d.key0, d.key1);
 #pragma unroll
-                    for (int s = 4 * q; s < NS && s < 4 * q + 4; ++s) {
-                        const int a = 16 * s + l16;
-                        if (a < d.n && (w.v[s & 3] >> 8) < d.p24) {
-                            const u32x4 wv = philox10((uint32_t)ls, gstep, (uint32_t)a, kStreamVelocity,
-                                                      d.key0, d.key1);
-                            real z[3];
-                            normals3<real>(wv, z);
-                            const real sd = sqrt_(kT * hdtm[s] * two_over_dt);
-                            r.vx[s] = sd * z[0];
-                            r.vy[s] = sd * z[1];
-                            r.vz[s] = sd * z[2];
+                        for (int s = 4 * q; s < NS && s < 4 * q + 4; ++s) {
+                            const int a = 16 * s + l16;
+                            if (a < d.n && (w.v[s & 3] >> 8) < d.p24) {
+                                const u32x4 wv = philox10((uint32_t)ls, gstep, (uint32_t)a, kStreamVelocity,
+                                                          d.key0, d.key1);
+                                real z[3];
+                                normals3(wv, z);
+                                const real sd = sqrt_(kT * hdtm[s] * two_over_dt);
+                                r.vx[s] = sd * z[0];
+                                r.vy[s] = sd * z[1];
+                                r.vz[s] = sd * z[2];
+                            }
                         }
                     }
                 }
             }
+            if (st < n_steps) {
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    r.vx[s] += hdtm[s] * r.fx[s];
+                    r.vy[s] += hdtm[s] * r.fy[s];
+                    r.vz[s] += hdtm[s] * r.fz[s];
+                    r.x[s] += dt * r.vx[s];
+                    r.y[s] += dt * r.vy[s];
+                    r.z[s] += dt * r.vz[s];
+                }
+            }
         }
 
-        // potential (FP64 sum of FP32 terms) and kinetic energy of the final state
-        double ep = 0.0;
-        evaluate<real, NS, DIEL, true>(r, d, tab_ab, tab_c, pos, frc, l16, ep);
+        // kinetic energy (FP64) of the final state; the potential energy is
+        // evaluated by k_energy after this kernel
         double ek = 0.0;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
@@ -598,16 +638,49 @@ __global__ __launch_bounds__(1024) void k_md(RunDev<real> d, int n_steps)
                 ek += 0.5 * d.mass[a] * (vx * vx + vy * vy + vz * vz);
             }
         }
-        ep = row_sum<real>(ep);
         ek = row_sum<real>(ek);
         if (valid) {
             store_replica<real, NS>(r, slab, l16);
-            if (l16 == 0) {
-                d.epot[cur][slot] = ep;
+            if (l16 == 0)
                 d.ekin[slot] = ek;
-                if (!isfinite(ep))
-                    atomicCAS(&d.ctl->error, 0, 4);
-            }
+        }
+    }
+}
+
+// potential energy (FP64 sum of FP32 terms) of every replica at its current
+// positions: E_j of the resampling weights
+template <typename real, int NS, int DIEL>
+__global__ __launch_bounds__(1024) void k_energy(RunDev<real> d)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int NST = tile_steps(NS);
+    real* tab_ab = reinterpret_cast<real*>(smem);
+    real* tab_c = tab_ab + NST * 32;
+    real* stage = tab_c + NST * 16;
+    for (int i = threadIdx.x; i < NST * 32; i += blockDim.x)
+        tab_ab[i] = d.nb_ab[i];
+    for (int i = threadIdx.x; i < NST * 16; i += blockDim.x)
+        tab_c[i] = d.nb_c[i];
+    __syncthreads();
+    const int lane = threadIdx.x & 63, row = lane >> 4, l16 = lane & 15, wave = threadIdx.x >> 6;
+    real* pos = stage + (size_t)(wave * kRowsPerWave + row) * 6 * d.n;
+    real* frc = pos + 3 * d.n;
+    const int64_t R = d.ctl->R_cur;
+    const int cur = d.ctl->cur;
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t g = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave; g * kRowsPerWave < R; g += nw) {
+        const int64_t slot = g * kRowsPerWave + row;
+        const bool valid = slot < R;
+        const real* slab = d.slab[cur] + (size_t)(valid ? slot : g * kRowsPerWave) * 6 * (16 * NS);
+        Regs<real, NS> r;
+        load_replica<real, NS>(r, slab, d.n, l16);
+        double ep = 0.0;
+        evaluate<real, NS, DIEL, true>(r, d, tab_ab, tab_c, pos, frc, l16, ep);
+        ep = row_sum<real>(ep);
+        if (valid && l16 == 0) {
+            d.epot[cur][slot] = ep;
+            if (!isfinite(ep))
+                atomicCAS(&d.ctl->error, 0, 4);
         }
     }
 }
@@ -680,6 +753,18 @@ static hipError_t launch_md_t(const RunDev<real>& d, int n_steps, int blocks, in
 }
 
 template <typename real, int NS, int DIEL>
+static hipError_t launch_energy_t(const RunDev<real>& d, int blocks, int waves, hipStream_t s)
+{
+    const size_t lds = md_lds_bytes<real>(NS, d.n, waves);
+    hipError_t e = hipFuncSetAttribute((const void*)k_energy<real, NS, DIEL>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL((k_energy<real, NS, DIEL>), dim3(blocks), dim3(waves * 64), lds, s, d);
+    return hipGetLastError();
+}
+
+template <typename real, int NS, int DIEL>
 static hipError_t launch_forces_t(const RunDev<real>& d, int64_t r0, int count, int waves, hipStream_t s)
 {
     const size_t lds = md_lds_bytes<real>(NS, d.n, waves);
@@ -738,6 +823,18 @@ hipError_t launch_md(const RunDev<float>& d, int n_steps, int blocks, int waves,
 hipError_t launch_md(const RunDev<double>& d, int n_steps, int blocks, int waves, hipStream_t s)
 {
 #define CALL(R, N, D) launch_md_t<R, N, D>(d, n_steps, blocks, waves, s)
+    PAMD_DISPATCH64(d.nslot, d.dielectric, CALL)
+#undef CALL
+}
+hipError_t launch_energy(const RunDev<float>& d, int blocks, int waves, hipStream_t s)
+{
+#define CALL(R, N, D) launch_energy_t<R, N, D>(d, blocks, waves, s)
+    PAMD_DISPATCH(float, d.nslot, d.dielectric, CALL)
+#undef CALL
+}
+hipError_t launch_energy(const RunDev<double>& d, int blocks, int waves, hipStream_t s)
+{
+#define CALL(R, N, D) launch_energy_t<R, N, D>(d, blocks, waves, s)
     PAMD_DISPATCH64(d.nslot, d.dielectric, CALL)
 #undef CALL
 }

@@ -18,6 +18,8 @@
 namespace pamd {
 hipError_t launch_md(const RunDev<float>& d, int n_steps, int blocks, int waves, hipStream_t s);
 hipError_t launch_md(const RunDev<double>& d, int n_steps, int blocks, int waves, hipStream_t s);
+hipError_t launch_energy(const RunDev<float>& d, int blocks, int waves, hipStream_t s);
+hipError_t launch_energy(const RunDev<double>& d, int blocks, int waves, hipStream_t s);
 hipError_t launch_forces(const RunDev<float>& d, int64_t r0, int count, int waves, hipStream_t s);
 hipError_t launch_forces(const RunDev<double>& d, int64_t r0, int count, int waves, hipStream_t s);
 hipError_t md_occupancy(int precision_fp32, int nslot, int diel, int n, int waves, int* blocks_per_cu);
@@ -171,6 +173,54 @@ pamd_status validate(pamd_ctx* c, const pamd_system& s, const pamd_params& p, in
     return PAMD_OK;
 }
 
+// Pack terms of k atoms into passes of 16 lanes such that no two terms of a
+// pass share an atom in the same role (position in the term); a term may be
+// stored reversed (a bond, angle or dihedral read backwards is the same
+// term).  Empty lanes get index -1.  Returns the packed records
+// (4 indices + 2 parameters per slot).
+void pack_terms(int count, int k, const int32_t* idx, const double* p0, const double* p1,
+                std::vector<int32_t>& rec, std::vector<double>& par)
+{
+    std::vector<std::vector<std::vector<int>>> passes;   // pass -> terms -> atoms (oriented)
+    std::vector<std::vector<int>> pass_term;
+    for (int t = 0; t < count; ++t) {
+        std::vector<int> fwd(idx + (size_t)t * k, idx + (size_t)t * k + k);
+        std::vector<int> rev(fwd.rbegin(), fwd.rend());
+        bool placed = false;
+        for (int o = 0; o < 2 && !placed; ++o) {
+            const std::vector<int>& cand = o == 0 ? fwd : rev;
+            for (size_t b = 0; b < passes.size() && !placed; ++b) {
+                if (passes[b].size() >= (size_t)kRow)
+                    continue;
+                bool ok = true;
+                for (const auto& other : passes[b])
+                    for (int r = 0; r < k && ok; ++r)
+                        ok = other[r] != cand[r];
+                if (ok) {
+                    passes[b].push_back(cand);
+                    pass_term[b].push_back(t);
+                    placed = true;
+                }
+            }
+        }
+        if (!placed) {
+            passes.push_back({fwd});
+            pass_term.push_back({t});
+        }
+    }
+    const size_t slots = std::max<size_t>(1, passes.size()) * kRow;
+    rec.assign(slots * 4, -1);
+    par.assign(slots * 2, 0.0);
+    for (size_t b = 0; b < passes.size(); ++b)
+        for (size_t q = 0; q < passes[b].size(); ++q) {
+            const size_t sl = b * kRow + q;
+            for (int r = 0; r < 4; ++r)
+                rec[sl * 4 + r] = r < k ? passes[b][q][r] : 0;
+            par[sl * 2] = p0[pass_term[b][q]];
+            par[sl * 2 + 1] = p1[pass_term[b][q]];
+        }
+}
+
 // Pair coefficients in the order the MD kernel walks its tiles: for block J,
 // the diagonal block (rotations k = 1..8; k = 8 only on lanes 0..7), then for
 // k = 0..15 the blocks I < J.  Lane l of step (I, J, k) pairs atom 16 I + l
@@ -213,30 +263,14 @@ void build_tables(const pamd_system& s, HostTables& t)
                 for (int l = 0; l < 16; ++l)
                     coef(st, l, 16 * I + l, 16 * J + ((l - k) & 15));
     }
-    t.bidx.assign((size_t)std::max(1, s.n_bonds) * 4, 0);
-    t.bpar.assign((size_t)std::max(1, s.n_bonds) * 2, 0.0);
-    for (int q = 0; q < s.n_bonds; ++q) {
-        t.bidx[4 * q] = s.bond_idx[2 * q];
-        t.bidx[4 * q + 1] = s.bond_idx[2 * q + 1];
-        t.bpar[2 * q] = s.bond_k[q];
-        t.bpar[2 * q + 1] = s.bond_r0[q];
-    }
-    t.aidx.assign((size_t)std::max(1, s.n_angles) * 4, 0);
-    t.apar.assign((size_t)std::max(1, s.n_angles) * 2, 0.0);
-    for (int q = 0; q < s.n_angles; ++q) {
-        for (int k = 0; k < 3; ++k)
-            t.aidx[4 * q + k] = s.angle_idx[3 * q + k];
-        t.apar[2 * q] = s.angle_k[q];
-        t.apar[2 * q + 1] = s.angle_theta0[q];
-    }
-    t.didx.assign((size_t)std::max(1, s.n_dihedrals) * 4, 0);
-    t.dpar.assign((size_t)std::max(1, s.n_dihedrals) * 2, 0.0);
+    pack_terms(s.n_bonds, 2, s.bond_idx, s.bond_k, s.bond_r0, t.bidx, t.bpar);
+    pack_terms(s.n_angles, 3, s.angle_idx, s.angle_k, s.angle_theta0, t.aidx, t.apar);
+    std::vector<double> kc(s.n_dihedrals), nm(s.n_dihedrals);
     for (int q = 0; q < s.n_dihedrals; ++q) {
-        for (int k = 0; k < 4; ++k)
-            t.didx[4 * q + k] = s.dih_idx[4 * q + k];
-        t.dpar[2 * q] = s.dih_k[q] * (cos(s.dih_delta[q]) > 0 ? 1.0 : -1.0);
-        t.dpar[2 * q + 1] = (double)s.dih_n[q];
+        kc[q] = s.dih_k[q] * (cos(s.dih_delta[q]) > 0 ? 1.0 : -1.0);   // k cos(delta), delta in {0, pi}
+        nm[q] = (double)s.dih_n[q];
     }
+    pack_terms(s.n_dihedrals, 4, s.dih_idx, kc.data(), nm.data(), t.didx, t.dpar);
     t.mass.assign(t.npad, 0.0);
     t.mtot = 0;
     for (int a = 0; a < n; ++a) {
@@ -267,12 +301,22 @@ void carve(Carver& st, Carver& wk, const pamd_system& s, const pamd_params& p, i
     d.fam = wk.take<uint8_t>(p.R_target);
     d.nb_ab = wk.take<real>((size_t)steps * 32);
     d.nb_c = wk.take<real>((size_t)steps * 16);
-    d.bidx = wk.take<int4>(std::max(1, s.n_bonds));
-    d.bpar = wk.take<real>((size_t)std::max(1, s.n_bonds) * 2);
-    d.aidx = wk.take<int4>(std::max(1, s.n_angles));
-    d.apar = wk.take<real>((size_t)std::max(1, s.n_angles) * 2);
-    d.didx = wk.take<int4>(std::max(1, s.n_dihedrals));
-    d.dpar = wk.take<real>((size_t)std::max(1, s.n_dihedrals) * 2);
+    // packed term slots (passes of 16 lanes)
+    std::vector<int32_t> rec;
+    std::vector<double> par;
+    std::vector<double> zeros(std::max({s.n_bonds, s.n_angles, s.n_dihedrals, 1}), 0.0);
+    pack_terms(s.n_bonds, 2, s.bond_idx, zeros.data(), zeros.data(), rec, par);
+    const int nb_slots = (int)(rec.size() / 4);
+    pack_terms(s.n_angles, 3, s.angle_idx, zeros.data(), zeros.data(), rec, par);
+    const int na_slots = (int)(rec.size() / 4);
+    pack_terms(s.n_dihedrals, 4, s.dih_idx, zeros.data(), zeros.data(), rec, par);
+    const int nd_slots = (int)(rec.size() / 4);
+    d.bidx = wk.take<int4>(nb_slots);
+    d.bpar = wk.take<real>((size_t)nb_slots * 2);
+    d.aidx = wk.take<int4>(na_slots);
+    d.apar = wk.take<real>((size_t)na_slots * 2);
+    d.didx = wk.take<int4>(nd_slots);
+    d.dpar = wk.take<real>((size_t)nd_slots * 2);
     d.mass = wk.take<double>(npad);
     d.x_init = wk.take<double>((size_t)3 * n);
     d.dbg = wk.take<double>((size_t)PAMD_FORCE_CHUNK * npad * 4);
@@ -281,9 +325,9 @@ void carve(Carver& st, Carver& wk, const pamd_system& s, const pamd_params& p, i
     d.n = n;
     d.npad = npad;
     d.nslot = nslot;
-    d.nb = s.n_bonds;
-    d.na = s.n_angles;
-    d.nd = s.n_dihedrals;
+    d.nb = s.n_bonds > 0 ? nb_slots : 0;
+    d.na = s.n_angles > 0 ? na_slots : 0;
+    d.nd = s.n_dihedrals > 0 ? nd_slots : 0;
     d.R_target = p.R_target;
     d.R_cap = Rc;
     d.kB = s.kB;
@@ -496,9 +540,11 @@ pamd_status pamd_md_steps(pamd_ctx* c, int32_t n_steps, void* stream)
     for (auto& run : c->runs) {
         if (c->fp32) {
             HIPCHK(c, launch_md(run.f, n_steps, c->blocks, c->waves, s));
+            HIPCHK(c, launch_energy(run.f, c->blocks, c->waves, s));
             HIPCHK(c, launch_md_finalize(run.f, n_steps, s));
         } else {
             HIPCHK(c, launch_md(run.d, n_steps, c->blocks, c->waves, s));
+            HIPCHK(c, launch_energy(run.d, c->blocks, c->waves, s));
             HIPCHK(c, launch_md_finalize(run.d, n_steps, s));
         }
     }

@@ -75,6 +75,9 @@ def load_library(path: str = LIB_PATH):
     global _lib
     if _lib is not None:
         return _lib
+    # torch first: libpamd then binds to the HIP runtime torch already loaded
+    # (one runtime per process)
+    import torch  # noqa: F401
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with `python -m paper_1806_06016_amd.build` "
                            "(the PAMD path has no fallback)")
