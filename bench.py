@@ -38,6 +38,26 @@ def algorithmic_flops_per_replica_step(sysd) -> float:
         + 18.0 * n, pairs
 
 
+def measured_traffic():
+    """HBM bytes per MD-kernel launch from the committed rocprofv3 counter
+    summary, or None when the kernel source changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_md_traffic.txt")
+    src = os.path.join(ROOT, "paper_1806_06016_amd", "csrc", "md_kernel.hip")
+    try:
+        kv = {}
+        for line in open(path):
+            if "=" in line and not line.lstrip().startswith("#"):
+                k, v = line.split("=", 1)
+                kv[k.strip()] = v.strip()
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        if kv.get("kernel_source_sha256_prefix") != sha:
+            return None
+        return int(kv["fetch_bytes_per_launch"]) + int(kv["write_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(sysd, seconds_target: float = 15.0):
     """The FP64 oracle (plain C, OpenMP over replicas) on the host cores, on a
     bounded sample of the same workload: R_s replicas x theta_s steps of the
@@ -73,6 +93,8 @@ def main():
     ap.add_argument("--waves", type=int, default=0, help="waves per workgroup (0: automatic)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="also run one device-to-device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -91,6 +113,13 @@ def main():
              V_target=0.1, T_final=T_final, waves_per_block=args.waves)
     info = p.launch_info()
     stream = torch.cuda.current_stream()
+    if args.copy_mb > 0:
+        nbytes = args.copy_mb << 20
+        src = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     # setup (untimed): equilibration at T0
     p.md_steps(args.theta_eq)
     p.observables()
@@ -148,7 +177,8 @@ def main():
         "md_replica_steps_per_s": R_steps / md_s,
         "launch": info,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_VALU_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP32_VALU_TFLOPS,
+                     "traffic": measured_traffic() if R == 100000 and args.theta == 1000 else None,
                      "flops_per_replica_step": flops_rs},
     }
     if not args.no_cpu_baseline:
