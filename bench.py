@@ -93,6 +93,8 @@ def main():
     ap.add_argument("--waves", type=int, default=0, help="waves per workgroup (0: automatic)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-graph", action="store_true", help="eager launches instead of HIP graphs")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -109,8 +111,14 @@ def main():
     flops_rs, pairs = algorithmic_flops_per_replica_step(sysd)
     R = args.replicas
     T0, T_final, dt, nu, seed = 700.0, 250.0, 0.001, 1.0, 1806
+    tuned = None
+    waves = args.waves
+    if waves == 0 and not args.no_autotune:
+        from paper_1806_06016_amd.autotune import autotune
+        tuned = autotune(sysd, PAMD_FP32)
+        waves = tuned["waves_per_block"]
     p = Pamd([sysd], R_target=R, T0=T0, dt=dt, nu=nu, seed=seed, precision=PAMD_FP32,
-             V_target=0.1, T_final=T_final, waves_per_block=args.waves)
+             V_target=0.1, T_final=T_final, waves_per_block=waves)
     info = p.launch_info()
     stream = torch.cuda.current_stream()
     if args.copy_mb > 0:
@@ -120,21 +128,32 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    # setup (untimed): equilibration at T0
+    # setup (untimed): equilibration at T0; one-time graph captures (slot 0:
+    # adaptive resampling, slot 1: theta MD steps), replayed every temperature
     p.md_steps(args.theta_eq)
     p.observables()
+    use_graph = not args.no_graph
+    if use_graph:
+        p.graph_capture(0, "adaptive", slot=0, parts="resample")
+        p.graph_capture(args.theta, "adaptive", slot=1, parts="md")
 
     ev_md = []
     R_steps = 0
 
     def temperature_step(record: bool):
         nonlocal R_steps
-        p.resample(None)
+        if use_graph:
+            p.graph_launch(0)
+        else:
+            p.resample(None)
         if record:
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record(stream)
-        p.md_steps(args.theta)
+        if use_graph:
+            p.graph_launch(1)
+        else:
+            p.md_steps(args.theta)
         if record:
             e1.record(stream)
             ev_md.append((e0, e1))
@@ -175,7 +194,7 @@ def main():
         "pair_interactions_per_s": value * pairs,
         "md_kernel_ms_avg": float(np.mean(md_ms)),
         "md_replica_steps_per_s": R_steps / md_s,
-        "launch": info,
+        "launch": dict(info, graph=use_graph, autotune=tuned),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_VALU_TFLOPS,
                      "traffic": measured_traffic() if R == 100000 and args.theta == 1000 else None,

@@ -124,7 +124,7 @@ typedef struct pamd_obs {
     double E2_mean;                /* <E_pot^2> */
     double K_mean;                 /* <E_kin> */
     double T_measured;             /* 2 <E_kin> / (3 N kB) */
-    double Cv;                     /* (<E^2> - <E>^2) / (kB T^2)  (heat capacity / kB ... in kB units) */
+    double Cv;                     /* (<E^2> - <E>^2) / (kB T)^2 = heat capacity / kB */
     int64_t R;                     /* current population size R_i */
     int64_t families;              /* distinct ancestors among the R_i copies */
     int64_t temp_index;            /* i */
@@ -156,8 +156,10 @@ pamd_status pamd_init(const pamd_system* sys, int32_t n_runs, const pamd_params*
 pamd_status pamd_md_steps(pamd_ctx* ctx, int32_t n_steps, void* stream);
 
 /* PAMD step 2.  T_next: host [n_runs]; T_next[r] > 0 is the next temperature
- * of run r, T_next[r] <= 0 (or T_next == NULL) chooses it adaptively (largest
- * step with normalised weight variance <= V_target, not below T_final).
+ * of run r, T_next[r] == 0 (or T_next == NULL) chooses it adaptively (largest
+ * step with normalised weight variance <= V_target, not below T_final), and
+ * T_next[r] < 0 takes the next entry of the run's device schedule
+ * (pamd_set_schedule; the last entry repeats once it is reached).
  * d_uniforms: device [n_runs][R_cap] doubles in [0,1) for the rounding draws,
  * or NULL to draw them from Philox stream 2.  Copy numbers are
  * c_j = floor(tau_j) + [u_j < frac(tau_j)] with tau_j = R_target w_j / sum w;
@@ -167,6 +169,24 @@ pamd_status pamd_md_steps(pamd_ctx* ctx, int32_t n_steps, void* stream);
  * leaves the state unchanged and raises PAMD_ERR_CAPACITY at the next sync. */
 pamd_status pamd_resample(pamd_ctx* ctx, const double* T_next, const double* d_uniforms,
                           void* stream);
+
+/* PAMD steps 2 and 3 as HIP graphs.  Captures into graph `slot` (0..3), on
+ * `stream` (must not be the null stream), the work selected by `parts`:
+ * 1 = one resampling of every run (mode 0: adaptive temperature, mode 1: next
+ * entry of the device schedule), 2 = n_steps MD steps of every run, 3 = both
+ * in that order; then instantiates it (replacing that slot's previous graph).
+ * Every value that changes between temperatures lives in device memory, so
+ * one capture is replayed for the whole anneal.  The graphs hold kernels only. */
+pamd_status pamd_graph_capture(pamd_ctx* ctx, int32_t slot, int32_t parts, int32_t n_steps, int32_t mode,
+                               void* stream);
+
+/* Replays graph `slot` on `stream` (any stream).  Asynchronous. */
+pamd_status pamd_graph_launch(pamd_ctx* ctx, int32_t slot, void* stream);
+
+/* Device temperature schedule of `run` (T[0] = T0 ... T[n-1] = T_N; n <= 4096),
+ * used by pamd_resample with T_next[run] < 0 and by graphs of mode 1.
+ * Synchronises `stream`. */
+pamd_status pamd_set_schedule(pamd_ctx* ctx, int32_t run, const double* T, int32_t n, void* stream);
 
 /* PAMD step 4.  out: host [n_runs].  Synchronises `stream`. */
 pamd_status pamd_observables(pamd_ctx* ctx, pamd_obs* out, void* stream);

@@ -744,10 +744,6 @@ template <typename real, int NS, int DIEL>
 static hipError_t launch_md_t(const RunDev<real>& d, int n_steps, int blocks, int waves, hipStream_t s)
 {
     const size_t lds = md_lds_bytes<real>(NS, d.n, waves);
-    hipError_t e = hipFuncSetAttribute((const void*)k_md<real, NS, DIEL>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess)
-        return e;
     hipLaunchKernelGGL((k_md<real, NS, DIEL>), dim3(blocks), dim3(waves * 64), lds, s, d, n_steps);
     return hipGetLastError();
 }
@@ -756,10 +752,6 @@ template <typename real, int NS, int DIEL>
 static hipError_t launch_energy_t(const RunDev<real>& d, int blocks, int waves, hipStream_t s)
 {
     const size_t lds = md_lds_bytes<real>(NS, d.n, waves);
-    hipError_t e = hipFuncSetAttribute((const void*)k_energy<real, NS, DIEL>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess)
-        return e;
     hipLaunchKernelGGL((k_energy<real, NS, DIEL>), dim3(blocks), dim3(waves * 64), lds, s, d);
     return hipGetLastError();
 }
@@ -768,24 +760,25 @@ template <typename real, int NS, int DIEL>
 static hipError_t launch_forces_t(const RunDev<real>& d, int64_t r0, int count, int waves, hipStream_t s)
 {
     const size_t lds = md_lds_bytes<real>(NS, d.n, waves);
-    hipError_t e = hipFuncSetAttribute((const void*)k_forces<real, NS, DIEL>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess)
-        return e;
     const int per_block = waves * kRowsPerWave;
     const int blocks = (count + per_block - 1) / per_block;
     hipLaunchKernelGGL((k_forces<real, NS, DIEL>), dim3(blocks), dim3(waves * 64), lds, s, d, r0, count);
     return hipGetLastError();
 }
 
+// one-time set-up of an instantiation: LDS limit of its three kernels (outside
+// any stream capture) and the resident workgroups per CU of k_md
 template <typename real, int NS, int DIEL>
 static hipError_t occupancy_t(int waves, int* blocks_per_cu, int n)
 {
     const size_t lds = md_lds_bytes<real>(NS, n, waves);
-    hipError_t e = hipFuncSetAttribute((const void*)k_md<real, NS, DIEL>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess)
-        return e;
+    const void* fns[3] = {(const void*)k_md<real, NS, DIEL>, (const void*)k_energy<real, NS, DIEL>,
+                          (const void*)k_forces<real, NS, DIEL>};
+    for (const void* f : fns) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess)
+            return e;
+    }
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, (const void*)k_md<real, NS, DIEL>,
                                                         waves * 64, lds);
 }

@@ -9,6 +9,7 @@ constexpr int kRow = 16;            // lanes per replica (one DPP row)
 constexpr int kRowsPerWave = 4;     // replicas per wave64
 constexpr int kMaxSlots = 5;        // 16-atom blocks held in registers (N <= 80)
 constexpr int kWaveSize = 64;
+constexpr int kMaxSched = 4096;  // temperatures a device schedule can hold
 
 // Number of tile steps of the all-pairs schedule for `nslot` blocks of 16 atoms:
 // each diagonal block takes 8 row rotations (k = 1..8, k = 8 half-masked),
@@ -22,7 +23,7 @@ struct alignas(64) RunCtl {
     double T_cur;        // bath temperature of the current population
     double T_prev;
     double T_next;       // chosen by the weights kernel (requested or adaptive)
-    double T_req;        // host request for the next resampling (<= 0: adaptive)
+    double T_req;        // last request: > 0 explicit T, 0 adaptive, < 0 device schedule
     double dbeta;        // 1/(kB T_next) - 1/(kB T_cur)
     double m;            // min E
     double S;            // sum exp(-dbeta (E - m))
@@ -64,6 +65,8 @@ struct RunDev {
     const real* dpar;       // [nd][2] (k cos(delta), n)
     const double* mass;     // [npad] (0 for padding)
     const double* x_init;   // [n][3]
+    const double* sched;    // device temperature schedule [kMaxSched]
+    int32_t n_sched;        // its length (set by pamd_set_schedule; 0 = none)
     double* dbg;            // force-debug scratch [PAMD_FORCE_CHUNK][npad][4]
     void* obs;              // device pamd_obs
     int32_t n, npad, nslot, nb, na, nd;

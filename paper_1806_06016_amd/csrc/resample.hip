@@ -179,6 +179,10 @@ __global__ __launch_bounds__(kBlk) void k_weights(RunDev<real> d, double T_req)
     double Tn;
     if (T_req > 0.0) {
         Tn = T_req;
+    } else if (T_req < 0.0) {
+        // device schedule: the next entry, or stay at the last one
+        const int64_t nx = (int64_t)c->temp_index + 1;
+        Tn = (d.sched && nx < d.n_sched) ? d.sched[nx] : T;
     } else {
         const double dmax = 1.0 / (kB * d.T_final) - 1.0 / (kB * T);
         if (!(dmax > 0.0)) {

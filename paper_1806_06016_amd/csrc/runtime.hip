@@ -73,7 +73,11 @@ struct Run {
 
 }  // namespace
 
+constexpr int kGraphSlots = 4;
+
 struct pamd_ctx {
+    hipGraph_t graph[kGraphSlots] = {};
+    hipGraphExec_t graph_exec[kGraphSlots] = {};
     int n_runs = 0;
     int fp32 = 1;
     std::vector<Run> runs;
@@ -319,6 +323,8 @@ void carve(Carver& st, Carver& wk, const pamd_system& s, const pamd_params& p, i
     d.dpar = wk.take<real>((size_t)nd_slots * 2);
     d.mass = wk.take<double>(npad);
     d.x_init = wk.take<double>((size_t)3 * n);
+    d.sched = wk.take<double>(kMaxSched);
+    d.n_sched = 0;
     d.dbg = wk.take<double>((size_t)PAMD_FORCE_CHUNK * npad * 4);
     d.obs = wk.take<pamd_obs>(1);
     d.unif = nullptr;
@@ -806,7 +812,88 @@ pamd_status pamd_launch_info(const pamd_ctx* c, int32_t* waves_per_block, int32_
     return PAMD_OK;
 }
 
-void pamd_destroy(pamd_ctx* c) { delete c; }
+pamd_status pamd_set_schedule(pamd_ctx* c, int32_t run, const double* T, int32_t n, void* stream)
+{
+    pamd_status st = check_ctx(c);
+    if (st != PAMD_OK)
+        return st;
+    if (run < 0 || run >= c->n_runs || !T || n < 1 || n > kMaxSched)
+        return fail(c, PAMD_ERR_ARG, "bad run index or schedule length (1.." + std::to_string(kMaxSched) + ")");
+    for (int i = 0; i < n; ++i)
+        if (!(T[i] > 0.0))
+            return fail(c, PAMD_ERR_ARG, "schedule temperatures must be > 0");
+    hipStream_t s = as_stream(stream);
+    Run& r = c->runs[run];
+    const double* dst = c->fp32 ? r.f.sched : r.d.sched;
+    HIPCHK(c, hipMemcpyAsync((void*)dst, T, sizeof(double) * n, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    r.f.n_sched = n;
+    r.d.n_sched = n;
+    return PAMD_OK;
+}
+
+static void drop_graph(pamd_ctx* c, int slot)
+{
+    if (c->graph_exec[slot])
+        (void)hipGraphExecDestroy(c->graph_exec[slot]);
+    if (c->graph[slot])
+        (void)hipGraphDestroy(c->graph[slot]);
+    c->graph_exec[slot] = nullptr;
+    c->graph[slot] = nullptr;
+}
+
+pamd_status pamd_graph_capture(pamd_ctx* c, int32_t slot, int32_t parts, int32_t n_steps, int32_t mode,
+                               void* stream)
+{
+    pamd_status st = check_ctx(c);
+    if (st != PAMD_OK)
+        return st;
+    if (!stream)
+        return fail(c, PAMD_ERR_ARG, "graph capture needs a non-null stream");
+    if (slot < 0 || slot >= kGraphSlots || parts < 1 || parts > 3 || n_steps < 0 || (mode != 0 && mode != 1))
+        return fail(c, PAMD_ERR_ARG, "bad graph slot, parts, n_steps or schedule mode");
+    hipStream_t s = as_stream(stream);
+    drop_graph(c, slot);
+    HIPCHK(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    std::vector<double> req(c->n_runs, mode == 0 ? 0.0 : -1.0);
+    pamd_status b = PAMD_OK;
+    if (parts & 1)
+        b = pamd_resample(c, req.data(), nullptr, stream);
+    if (b == PAMD_OK && (parts & 2))
+        b = pamd_md_steps(c, n_steps, stream);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(s, &g);
+    if (b != PAMD_OK) {
+        if (g)
+            (void)hipGraphDestroy(g);
+        return b;
+    }
+    if (e != hipSuccess)
+        return fail(c, PAMD_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    c->graph[slot] = g;
+    HIPCHK(c, hipGraphInstantiate(&c->graph_exec[slot], g, nullptr, nullptr, 0));
+    return PAMD_OK;
+}
+
+pamd_status pamd_graph_launch(pamd_ctx* c, int32_t slot, void* stream)
+{
+    pamd_status st = check_ctx(c);
+    if (st != PAMD_OK)
+        return st;
+    if (slot < 0 || slot >= kGraphSlots || !c->graph_exec[slot])
+        return fail(c, PAMD_ERR_STATE, "no captured graph in this slot");
+    HIPCHK(c, hipGraphLaunch(c->graph_exec[slot], as_stream(stream)));
+    return PAMD_OK;
+}
+
+void pamd_destroy(pamd_ctx* c)
+{
+    if (!c)
+        return;
+    for (int g = 0; g < kGraphSlots; ++g)
+        drop_graph(c, g);
+    delete c;
+}
 
 const char* pamd_last_error(const pamd_ctx* c)
 {

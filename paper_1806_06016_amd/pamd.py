@@ -64,6 +64,7 @@ class pamd_run_scalars(C.Structure):
 
 
 EXPORTS = ["pamd_query_sizes", "pamd_init", "pamd_md_steps", "pamd_resample", "pamd_observables",
+           "pamd_graph_capture", "pamd_graph_launch", "pamd_set_schedule",
            "pamd_get_forces", "pamd_get_state", "pamd_set_state", "pamd_get_counts",
            "pamd_launch_info", "pamd_destroy", "pamd_last_error"]
 
@@ -89,6 +90,9 @@ def load_library(path: str = LIB_PATH):
     lib.pamd_md_steps.argtypes = [vp, i32, vp]
     lib.pamd_resample.argtypes = [vp, vp, vp, vp]
     lib.pamd_observables.argtypes = [vp, vp, vp]
+    lib.pamd_graph_capture.argtypes = [vp, i32, i32, i32, i32, vp]
+    lib.pamd_graph_launch.argtypes = [vp, i32, vp]
+    lib.pamd_set_schedule.argtypes = [vp, i32, vp, i32, vp]
     lib.pamd_get_forces.argtypes = [vp, i32, i64, i32, vp, vp, vp]
     lib.pamd_get_state.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
     lib.pamd_set_state.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
@@ -216,6 +220,28 @@ class Pamd:
             assert uniforms.numel() >= self.n_runs * self.R_cap and uniforms.is_contiguous()
             up = uniforms.data_ptr()
         self._check(self.lib.pamd_resample(self.ctx, tn, up, self._s()), self.ctx)
+
+    def set_schedule(self, run: int, temps: Sequence[float]) -> None:
+        t = np.ascontiguousarray(np.asarray(temps, np.float64))
+        self._check(self.lib.pamd_set_schedule(self.ctx, run, _ptr(t), len(t), self._s()), self.ctx)
+
+    def graph_capture(self, n_steps: int, mode: str = "adaptive", slot: int = 0,
+                      parts: str = "both") -> None:
+        """Capture a HIP graph into `slot`: parts "resample", "md" or "both"
+        (one temperature step: resample + n_steps MD steps); mode "adaptive"
+        or "schedule" (device schedule) for the resampling."""
+        torch = self.torch
+        if getattr(self, "_cap_stream", None) is None:
+            self._cap_stream = torch.cuda.Stream()
+        self._cap_stream.wait_stream(self.stream)
+        m = {"adaptive": 0, "schedule": 1}[mode]
+        pm = {"resample": 1, "md": 2, "both": 3}[parts]
+        self._check(self.lib.pamd_graph_capture(self.ctx, int(slot), pm, int(n_steps), m,
+                                                C.c_void_p(self._cap_stream.cuda_stream)), self.ctx)
+        self.stream.wait_stream(self._cap_stream)
+
+    def graph_launch(self, slot: int = 0) -> None:
+        self._check(self.lib.pamd_graph_launch(self.ctx, int(slot), self._s()), self.ctx)
 
     def observables(self) -> List[Dict]:
         out = (pamd_obs * self.n_runs)()
