@@ -18,8 +18,9 @@ Definitions (all FP64):
   loss      L = mean over configurations, atoms, components of (F_NN - F_target)^2
   RESPA     outer step Dt = M dt: v += Dt/2 (F_nb - F_NN)/m; M velocity-Verlet
             steps of dt with F_bonded + F_NN; v += Dt/2 (F_nb - F_NN)/m; then
-            Andersen collisions with p = 1 - exp(-nu Dt) (outer-step counter as
-            the Philox step word).
+            Andersen collisions with p = 1 - exp(-nu Dt), drawn with the MD step
+            counter at the start of the outer step (step0 + o M) as the Philox
+            step word.
 """
 from __future__ import annotations
 
@@ -173,7 +174,7 @@ def respa_steps(osys, sysd, x, v, n_outer: int, outer_ratio: int, dt_inner: floa
         Fnb = O.energy_forces(osys, x, nonb)[1]
         v += 0.5 * Dt * (Fnb - Fnn) / m
         # Andersen collisions, one draw per atom per outer step
-        _andersen(osys, x, v, T, p24, seed, step0 + o, run)
+        _andersen(osys, x, v, T, p24, seed, step0 + o * outer_ratio, run)
     Ep = O.energy_forces(osys, x)[0]
     Ek = 0.5 * (m * v * v).sum((1, 2))
     return Ep, Ek
