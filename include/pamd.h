@@ -33,7 +33,9 @@
  *  - Host arrays passed in are only read during the call (copied).
  *  - Device memory: the caller allocates `d_state` and `d_work` (sizes from
  *    pamd_query_sizes, 256-byte aligned) and keeps them alive until
- *    pamd_destroy(); the library allocates no device memory.
+ *    pamd_destroy(); the core calls allocate no device memory.  The optional
+ *    learned multiple-time-step surrogate (pamd_nn_*, pamd_set_mts) allocates
+ *    its own weights, workspace and per-run buffers with hipMalloc.
  */
 #ifndef PAMD_H
 #define PAMD_H
@@ -152,7 +154,8 @@ pamd_status pamd_init(const pamd_system* sys, int32_t n_runs, const pamd_params*
 /* PAMD step 3.  n_steps >= 0 NVT velocity-Verlet steps (Andersen collisions
  * after each step) of every copy of every run at the run's current T; leaves
  * E_pot and E_kin of the final configurations (n_steps = 0 only evaluates
- * them).  Asynchronous. */
+ * them).  With a surrogate attached (pamd_set_mts) the same time span is
+ * covered by r-RESPA outer steps.  Asynchronous. */
 pamd_status pamd_md_steps(pamd_ctx* ctx, int32_t n_steps, void* stream);
 
 /* PAMD step 2.  T_next: host [n_runs]; T_next[r] > 0 is the next temperature
@@ -228,6 +231,80 @@ pamd_status pamd_launch_info(const pamd_ctx* ctx, int32_t* waves_per_block, int3
 
 void pamd_destroy(pamd_ctx* ctx);
 const char* pamd_last_error(const pamd_ctx* ctx);
+
+/* ---- learned multiple-time-step (MTS) surrogate --------------------------
+ * Not part of the paper's scheme: an optional acceleration of the MD update
+ * of step 3 by r-RESPA.  A network shared by all atoms maps Gaussian radial
+ * features of an atom's nonbonded partners to an atomic energy,
+ *   G_i[t][k] = sum over partners j of type t of exp(-(r_ij - mu_k)^2 / (2 s^2)),
+ *   mu_k = 0.1 + k s, s = 1.1 / 31 (positions in nm), k = 0..31, t = 0..7,
+ *   E_i = w3 . silu(W2^T silu(W1^T G_i + b1) + b2) + b3,  E_NN = sum_i E_i,
+ *   F_NN = -grad E_NN,  silu(x) = x / (1 + exp(-x)),
+ * where the partners are the nonbonded pair set (1-2 and 1-3 pairs excluded,
+ * 1-4 pairs included unscaled).  Parameters are FP32 masters with BF16 copies
+ * for the matrix cores (FP32 accumulation); features and hidden activations
+ * are rounded to BF16, so forces agree with an exact evaluation to about 1e-2
+ * relative.  All device arrays below are FP32 [n_conf][n_atoms][3] unless
+ * stated; calls marked asynchronous only enqueue work on `stream`. */
+#define PAMD_NN_TYPES 8
+#define PAMD_NN_FEATURES 256
+#define PAMD_NN_HIDDEN 128
+/* flat parameter vector: W1 [256][128], b1 [128], W2 [128][128], b2 [128], w3 [128], b3 [1] */
+#define PAMD_NN_PARAMS 49665
+
+typedef struct pamd_nn pamd_nn;
+
+/* Surrogate for molecule `sys` (its atom count and bonds are used) with
+ * atom_type[n_atoms] in 0..7.  Parameters start at zero (F_NN = 0). */
+pamd_status pamd_nn_create(const pamd_system* sys, const int32_t* atom_type, pamd_nn** out);
+
+/* Host params[PAMD_NN_PARAMS] -> device masters and BF16 copies; resets the
+ * Adam state.  Synchronises `stream`. */
+pamd_status pamd_nn_set_weights(pamd_nn* nn, const float* params, void* stream);
+
+/* Device masters -> host params[PAMD_NN_PARAMS].  Synchronises `stream`. */
+pamd_status pamd_nn_get_weights(pamd_nn* nn, float* params, void* stream);
+
+/* E_NN (d_E [n_conf], may be NULL) and F_NN (d_F) of the configurations
+ * d_x.  Asynchronous (the first call of a larger size allocates). */
+pamd_status pamd_nn_forces(pamd_nn* nn, int64_t n_conf, const float* d_x, float* d_F, float* d_E, void* stream);
+
+/* Force-matching loss L = mean over configurations, atoms and components of
+ * (F_NN - F_target)^2 into device float *d_loss, and its gradient with
+ * respect to the FP32 parameters into d_grad (device [PAMD_NN_PARAMS]; NULL:
+ * loss only).  The gradient is reverse mode through the forward-mode
+ * derivative of the network along the features' derivative in the direction
+ * dL/dF.  Asynchronous. */
+pamd_status pamd_nn_loss_grad(pamd_nn* nn, int64_t n_conf, const float* d_x, const float* d_F_target,
+                              float* d_loss, float* d_grad, void* stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, step size lr) on that
+ * gradient of the batch; the batch loss before the step goes to *d_loss
+ * (may be NULL).  Asynchronous. */
+pamd_status pamd_nn_train_step(pamd_nn* nn, int64_t n_conf, const float* d_x, const float* d_F_target, float lr,
+                               float* d_loss, void* stream);
+
+void pamd_nn_destroy(pamd_nn* nn);
+const char* pamd_nn_last_error(const pamd_nn* nn);
+
+/* Positions and exact nonbonded (LJ + Coulomb) forces of replicas
+ * [r0, r0 + count) of `run` of an FP32 context into device arrays d_x and
+ * d_F_nb (training data of the surrogate).  Asynchronous. */
+pamd_status pamd_export_configs(pamd_ctx* ctx, int32_t run, int64_t r0, int64_t count, float* d_x, float* d_F_nb,
+                                void* stream);
+
+/* Switch pamd_md_steps of an FP32 context to r-RESPA with surrogate `nn`
+ * (every run must have nn's atom count): per outer step of Dt = outer_ratio dt
+ *   v += Dt/2 (F_nb - F_NN) / m;
+ *   outer_ratio velocity-Verlet steps of dt with the force F_bonded + F_NN;
+ *   v += Dt/2 (F_nb - F_NN) / m;
+ *   Andersen collisions with probability 1 - exp(-nu Dt) per atom, drawn
+ *   with the MD step counter at the start of the outer step as Philox step word.
+ * n_steps of pamd_md_steps must then be a multiple of outer_ratio; energies
+ * for the resampling weights stay exact.  nn = NULL switches back to plain
+ * velocity Verlet.  Allocates per-run buffers of about R_cap * n_atoms KiB;
+ * nn must stay alive while attached.  Synchronises `stream`. */
+pamd_status pamd_set_mts(pamd_ctx* ctx, pamd_nn* nn, int32_t outer_ratio, void* stream);
 
 #ifdef __cplusplus
 }

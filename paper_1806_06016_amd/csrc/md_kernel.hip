@@ -381,7 +381,8 @@ __device__ __forceinline__ void bonded_terms(const RunDev<real>& d, const real* 
     }
 }
 
-template <typename real, int NS, int DIEL, bool ENERGY>
+// TERMS: 1 bonded, 2 nonbonded, 3 both
+template <typename real, int NS, int DIEL, bool ENERGY, int TERMS = 3>
 __device__ __forceinline__ void evaluate(Regs<real, NS>& r, const RunDev<real>& d, const real* tab_ab,
                                          const real* tab_c, real* pos, real* frc, int l16, double& eacc)
 {
@@ -393,27 +394,32 @@ __device__ __forceinline__ void evaluate(Regs<real, NS>& r, const RunDev<real>& 
             r.fz[s] = (real)0;
         }
     }
-    // stage positions for the bonded terms
+    if constexpr ((TERMS & 1) != 0) {
+        // stage positions for the bonded terms
 #pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        const int a = 16 * s + l16;
-        if (a < d.n) {
-            pos[3 * a] = r.x[s];
-            pos[3 * a + 1] = r.y[s];
-            pos[3 * a + 2] = r.z[s];
+        for (int s = 0; s < NS; ++s) {
+            const int a = 16 * s + l16;
+            if (a < d.n) {
+                pos[3 * a] = r.x[s];
+                pos[3 * a + 1] = r.y[s];
+                pos[3 * a + 2] = r.z[s];
+            }
         }
+        wave_sync();
+        // bonded terms first: their LDS scatter completes while the
+        // register-only nonbonded tiles run
+        bonded_terms<real, ENERGY>(d, pos, frc, l16, eacc);
     }
-    wave_sync();
-    // bonded terms first: their LDS atomics complete while the register-only
-    // nonbonded tiles run
-    bonded_terms<real, ENERGY>(d, pos, frc, l16, eacc);
-    nonbonded<real, NS, DIEL, ENERGY>(r, tab_ab, tab_c, l16, eacc);
+    if constexpr ((TERMS & 2) != 0)
+        nonbonded<real, NS, DIEL, ENERGY>(r, tab_ab, tab_c, l16, eacc);
     if constexpr (!ENERGY) {
         // materialise the pair-force sums here (otherwise the sums are sunk to
         // their use and every pair's partial force stays live)
 #pragma unroll
         for (int s = 0; s < NS; ++s)
             asm volatile("" : "+v"(r.fx[s]), "+v"(r.fy[s]), "+v"(r.fz[s]));
+    }
+    if constexpr (!ENERGY && (TERMS & 1) != 0) {
         wave_sync();
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
@@ -513,6 +519,32 @@ __device__ __forceinline__ void normals3(const u32x4& w, double* z)
     z[2] = r1 * cos(two_pi * u3);
 }
 
+// Andersen collisions of one replica at MD step `gstep`: atom a collides iff
+// the top 24 bits of its collision word are below p24; its new velocity is
+// drawn from Maxwell-Boltzmann at kT (hdtm * two_over_dt = 1 / m)
+template <typename real, int NS>
+__device__ __forceinline__ void andersen(Regs<real, NS>& r, const RunDev<real>& d, uint32_t slot, uint32_t gstep,
+                                         uint32_t p24, real kT, const real* hdtm, real two_over_dt, int l16)
+{
+#pragma unroll
+    for (int q = 0; q < (NS + 3) / 4; ++q) {
+        const u32x4 w = philox10(slot, gstep, (uint32_t)(l16 + 16 * q), kStreamCollide, d.key0, d.key1);
+#pragma unroll
+        for (int s = 4 * q; s < NS && s < 4 * q + 4; ++s) {
+            const int a = 16 * s + l16;
+            if (a < d.n && (w.v[s & 3] >> 8) < p24) {
+                const u32x4 wv = philox10(slot, gstep, (uint32_t)a, kStreamVelocity, d.key0, d.key1);
+                real z[3];
+                normals3(wv, z);
+                const real sd = sqrt_(kT * hdtm[s] * two_over_dt);
+                r.vx[s] = sd * z[0];
+                r.vy[s] = sd * z[1];
+                r.vz[s] = sd * z[2];
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // the persistent MD kernel
 // ---------------------------------------------------------------------------
@@ -591,28 +623,9 @@ __global__ __launch_bounds__(1024) void k_md(RunDev<real> d, int n_steps)
                     r.vz[s] += hdtm[s] * r.fz[s];
                 }
                 // Andersen collisions
-                if (d.p24 != 0u) {
-                    const uint32_t gstep = step0 + (uint32_t)(st - 1);
-#pragma unroll
-                    for (int q = 0; q < (NS + 3) / 4; ++q) {
-                        const u32x4 w = philox10((uint32_t)ls, gstep, (uint32_t)(l16 + 16 * q), kStreamCollide,
-                                                 d.key0, d.key1);
-#pragma unroll
-                        for (int s = 4 * q; s < NS && s < 4 * q + 4; ++s) {
-                            const int a = 16 * s + l16;
-                            if (a < d.n && (w.v[s & 3] >> 8) < d.p24) {
-                                const u32x4 wv = philox10((uint32_t)ls, gstep, (uint32_t)a, kStreamVelocity,
-                                                          d.key0, d.key1);
-                                real z[3];
-                                normals3(wv, z);
-                                const real sd = sqrt_(kT * hdtm[s] * two_over_dt);
-                                r.vx[s] = sd * z[0];
-                                r.vy[s] = sd * z[1];
-                                r.vz[s] = sd * z[2];
-                            }
-                        }
-                    }
-                }
+                if (d.p24 != 0u)
+                    andersen<real, NS>(r, d, (uint32_t)ls, step0 + (uint32_t)(st - 1), d.p24, kT, hdtm, two_over_dt,
+                                       l16);
             }
             if (st < n_steps) {
 #pragma unroll
@@ -732,6 +745,181 @@ __global__ __launch_bounds__(1024) void k_forces(RunDev<real> d, int64_t r0, int
 }
 
 // ---------------------------------------------------------------------------
+// r-RESPA pieces for FP32 runs with a learned surrogate (outer step Dt = M dt,
+// inner force F_bonded + F_NN, outer impulse F_nb - F_NN).  `ops` selects what
+// is applied, in this order, at the current positions:
+//   kRespaInnerKick   v += dt/2 (F_b + F_NN) / m      (end of an inner step)
+//   kRespaOuterEnd    v += Dt/2 (F_nb - F_NN) / m
+//   kRespaCollide     Andersen collisions, step word ctl->step + step_off
+//   kRespaOuterStart  v += Dt/2 (F_nb - F_NN) / m
+//   kRespaDrift       v += dt/2 (F_b + F_NN) / m; x += dt v  (start of an inner step)
+// F_NN comes from `fnn` ([R_cap][3][npad], computed at the current positions);
+// F_b and F_nb are evaluated here.  Without kRespaDrift the kinetic energy is stored.
+// ---------------------------------------------------------------------------
+template <int NS, int DIEL>
+__global__ __launch_bounds__(1024) void k_respa(RunDev<float> d, const float* fnn, int ops, uint32_t step_off,
+                                                double dt_outer, uint32_t p24_outer)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int NST = tile_steps(NS);
+    float* tab_ab = reinterpret_cast<float*>(smem);
+    float* tab_c = tab_ab + NST * 32;
+    float* stage = tab_c + NST * 16;
+    for (int i = threadIdx.x; i < NST * 32; i += blockDim.x)
+        tab_ab[i] = d.nb_ab[i];
+    for (int i = threadIdx.x; i < NST * 16; i += blockDim.x)
+        tab_c[i] = d.nb_c[i];
+    __syncthreads();
+    const int lane = threadIdx.x & 63, row = lane >> 4, l16 = lane & 15, wave = threadIdx.x >> 6;
+    float* pos = stage + (size_t)(wave * kRowsPerWave + row) * 6 * d.n;
+    float* frc = pos + 3 * d.n;
+    for (int i = l16; i < 3 * d.n; i += kRow)
+        frc[i] = 0.f;
+    const RunCtl* ctl = d.ctl;
+    const int64_t R = ctl->R_cur;
+    const int cur = ctl->cur;
+    const uint32_t gstep = ctl->step + step_off;
+    const float kT = (float)(d.kB * ctl->T_cur);
+    const float dt = (float)d.dt;
+    const float two_over_dt = (float)(2.0 / d.dt);
+    constexpr int npad = 16 * NS;
+    float hin[NS], hout[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int a = 16 * s + l16;
+        hin[s] = (a < d.n) ? (float)(0.5 * d.dt / d.mass[a]) : 0.f;
+        hout[s] = (a < d.n) ? (float)(0.5 * dt_outer / d.mass[a]) : 0.f;
+    }
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t g = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave; g * kRowsPerWave < R; g += nw) {
+        const int64_t slot = g * kRowsPerWave + row;
+        const bool valid = slot < R;
+        const int64_t ls = valid ? slot : g * kRowsPerWave;
+        float* slab = d.slab[cur] + (size_t)ls * 6 * npad;
+        Regs<float, NS> r;
+        load_replica<float, NS>(r, slab, d.n, l16);
+        double unused = 0.0;
+        evaluate<float, NS, DIEL, false, 1>(r, d, tab_ab, tab_c, pos, frc, l16, unused);
+        float bx[NS], by[NS], bz[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            bx[s] = r.fx[s];
+            by[s] = r.fy[s];
+            bz[s] = r.fz[s];
+        }
+        if (ops & (kRespaOuterEnd | kRespaOuterStart))
+            evaluate<float, NS, DIEL, false, 2>(r, d, tab_ab, tab_c, pos, frc, l16, unused);
+        const float* fn = fnn + (size_t)ls * 3 * npad;
+        float nx[NS], ny[NS], nz[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int a = 16 * s + l16;
+            nx[s] = (a < d.n) ? fn[a] : 0.f;
+            ny[s] = (a < d.n) ? fn[npad + a] : 0.f;
+            nz[s] = (a < d.n) ? fn[2 * npad + a] : 0.f;
+        }
+        if (ops & kRespaInnerKick) {
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                r.vx[s] += hin[s] * (bx[s] + nx[s]);
+                r.vy[s] += hin[s] * (by[s] + ny[s]);
+                r.vz[s] += hin[s] * (bz[s] + nz[s]);
+            }
+        }
+        if (ops & kRespaOuterEnd) {
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                r.vx[s] += hout[s] * (r.fx[s] - nx[s]);
+                r.vy[s] += hout[s] * (r.fy[s] - ny[s]);
+                r.vz[s] += hout[s] * (r.fz[s] - nz[s]);
+            }
+        }
+        if ((ops & kRespaCollide) && p24_outer != 0u)
+            andersen<float, NS>(r, d, (uint32_t)ls, gstep, p24_outer, kT, hin, two_over_dt, l16);
+        if (ops & kRespaOuterStart) {
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                r.vx[s] += hout[s] * (r.fx[s] - nx[s]);
+                r.vy[s] += hout[s] * (r.fy[s] - ny[s]);
+                r.vz[s] += hout[s] * (r.fz[s] - nz[s]);
+            }
+        }
+        if (ops & kRespaDrift) {
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                r.vx[s] += hin[s] * (bx[s] + nx[s]);
+                r.vy[s] += hin[s] * (by[s] + ny[s]);
+                r.vz[s] += hin[s] * (bz[s] + nz[s]);
+                r.x[s] += dt * r.vx[s];
+                r.y[s] += dt * r.vy[s];
+                r.z[s] += dt * r.vz[s];
+            }
+        }
+        double ek = 0.0;
+        if (!(ops & kRespaDrift)) {
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                const int a = 16 * s + l16;
+                if (a < d.n) {
+                    const double vx = r.vx[s], vy = r.vy[s], vz = r.vz[s];
+                    ek += 0.5 * d.mass[a] * (vx * vx + vy * vy + vz * vz);
+                }
+            }
+            ek = row_sum<float>(ek);
+        }
+        if (valid) {
+            store_replica<float, NS>(r, slab, l16);
+            if (!(ops & kRespaDrift) && l16 == 0)
+                d.ekin[slot] = ek;
+        }
+    }
+}
+
+// positions and exact nonbonded forces of replicas [r0, r0 + count) as
+// [count][n][3] FP32 arrays (training data of the surrogate)
+template <int NS, int DIEL>
+__global__ __launch_bounds__(1024) void k_export(RunDev<float> d, int64_t r0, int64_t count, float* xo, float* fo)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int NST = tile_steps(NS);
+    float* tab_ab = reinterpret_cast<float*>(smem);
+    float* tab_c = tab_ab + NST * 32;
+    for (int i = threadIdx.x; i < NST * 32; i += blockDim.x)
+        tab_ab[i] = d.nb_ab[i];
+    for (int i = threadIdx.x; i < NST * 16; i += blockDim.x)
+        tab_c[i] = d.nb_c[i];
+    __syncthreads();
+    const int lane = threadIdx.x & 63, row = lane >> 4, l16 = lane & 15, wave = threadIdx.x >> 6;
+    const int cur = d.ctl->cur;
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t g = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave; g * kRowsPerWave < count; g += nw) {
+        const int64_t k = g * kRowsPerWave + row;
+        const bool valid = k < count;
+        const float* slab = d.slab[cur] + (size_t)(r0 + (valid ? k : g * kRowsPerWave)) * 6 * (16 * NS);
+        Regs<float, NS> r;
+        load_replica<float, NS>(r, slab, d.n, l16);
+        double unused = 0.0;
+        evaluate<float, NS, DIEL, false, 2>(r, d, tab_ab, tab_c, nullptr, nullptr, l16, unused);
+        if (valid) {
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                const int a = 16 * s + l16;
+                if (a < d.n) {
+                    float* xa = xo + ((size_t)k * d.n + a) * 3;
+                    float* fa = fo + ((size_t)k * d.n + a) * 3;
+                    xa[0] = r.x[s];
+                    xa[1] = r.y[s];
+                    xa[2] = r.z[s];
+                    fa[0] = r.fx[s];
+                    fa[1] = r.fy[s];
+                    fa[2] = r.fz[s];
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // host-side dispatch
 // ---------------------------------------------------------------------------
 template <typename real>
@@ -766,15 +954,43 @@ static hipError_t launch_forces_t(const RunDev<real>& d, int64_t r0, int count, 
     return hipGetLastError();
 }
 
+template <int NS, int DIEL>
+static hipError_t launch_respa_t(const RunDev<float>& d, const float* fnn, int ops, uint32_t step_off,
+                                 double dt_outer, uint32_t p24_outer, int blocks, int waves, hipStream_t s)
+{
+    const size_t lds = md_lds_bytes<float>(NS, d.n, waves);
+    hipLaunchKernelGGL((k_respa<NS, DIEL>), dim3(blocks), dim3(waves * 64), lds, s, d, fnn, ops, step_off, dt_outer,
+                       p24_outer);
+    return hipGetLastError();
+}
+
+template <int NS, int DIEL>
+static hipError_t launch_export_t(const RunDev<float>& d, int64_t r0, int64_t count, float* xo, float* fo,
+                                  int waves, hipStream_t s)
+{
+    const size_t lds = md_lds_bytes<float>(NS, d.n, waves);
+    const int64_t per_block = (int64_t)waves * kRowsPerWave;
+    const int64_t blocks = (count + per_block - 1) / per_block;
+    hipLaunchKernelGGL((k_export<NS, DIEL>), dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(waves * 64),
+                       lds, s, d, r0, count, xo, fo);
+    return hipGetLastError();
+}
+
 // one-time set-up of an instantiation: LDS limit of its three kernels (outside
 // any stream capture) and the resident workgroups per CU of k_md
 template <typename real, int NS, int DIEL>
 static hipError_t occupancy_t(int waves, int* blocks_per_cu, int n)
 {
     const size_t lds = md_lds_bytes<real>(NS, n, waves);
-    const void* fns[3] = {(const void*)k_md<real, NS, DIEL>, (const void*)k_energy<real, NS, DIEL>,
-                          (const void*)k_forces<real, NS, DIEL>};
+    const void* fns[5] = {(const void*)k_md<real, NS, DIEL>, (const void*)k_energy<real, NS, DIEL>,
+                          (const void*)k_forces<real, NS, DIEL>, nullptr, nullptr};
+    if constexpr (sizeof(real) == 4) {
+        fns[3] = (const void*)k_respa<NS, DIEL>;
+        fns[4] = (const void*)k_export<NS, DIEL>;
+    }
     for (const void* f : fns) {
+        if (!f)
+            continue;
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess)
             return e;
@@ -841,6 +1057,20 @@ hipError_t launch_forces(const RunDev<double>& d, int64_t r0, int count, int wav
 {
 #define CALL(R, N, D) launch_forces_t<R, N, D>(d, r0, count, waves, s)
     PAMD_DISPATCH64(d.nslot, d.dielectric, CALL)
+#undef CALL
+}
+hipError_t launch_respa(const RunDev<float>& d, const float* fnn, int ops, uint32_t step_off, double dt_outer,
+                        uint32_t p24_outer, int blocks, int waves, hipStream_t s)
+{
+#define CALL(R, N, D) launch_respa_t<N, D>(d, fnn, ops, step_off, dt_outer, p24_outer, blocks, waves, s)
+    PAMD_DISPATCH(float, d.nslot, d.dielectric, CALL)
+#undef CALL
+}
+hipError_t launch_export(const RunDev<float>& d, int64_t r0, int64_t count, float* xo, float* fo, int waves,
+                         hipStream_t s)
+{
+#define CALL(R, N, D) launch_export_t<N, D>(d, r0, count, xo, fo, waves, s)
+    PAMD_DISPATCH(float, d.nslot, d.dielectric, CALL)
 #undef CALL
 }
 hipError_t md_occupancy(int precision_fp32, int nslot, int diel, int n, int waves, int* blocks_per_cu)

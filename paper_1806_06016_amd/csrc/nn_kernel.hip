@@ -1,0 +1,839 @@
+// Kernels of the learned multiple-time-step surrogate (an addition to the
+// paper's method: it accelerates the MD update of PAMD step 3 by r-RESPA).
+//
+//   features   G[i, t, k] = sum over partners j of type t of
+//              phi_k(r_ij) = exp(-(r_ij - mu_k)^2 / (2 s^2))  (VALU, one lane
+//              per (configuration, atom) row, Gaussians by a two-exponential
+//              recurrence in chunks of 8)
+//   MLP        E_i = w3 . silu(W2^T silu(W1^T G_i + b1) + b2) + b3 and its
+//              input gradient dE_i/dG_i, fused in one kernel per 64-row tile
+//              (BF16 MFMA 16x16x32, FP32 accumulate, activations in LDS)
+//   forces     F_i = -sum_j (A_ij + A_ji) (x_i - x_j) / r_ij with
+//              A_ij = sum_k dE_i/dG_i[t_j, k] phi_k'(r_ij)  (A staged in LDS)
+//   training   the force-matching loss gradient: the directional derivative
+//              v_i of the features along dL/dF (same kernel as the features),
+//              then reverse mode through the forward-mode derivative of the
+//              MLP (generic split-K BF16 MFMA GEMM + elementwise kernels),
+//              Adam on FP32 master weights and the BF16 copies.
+#include <stdint.h>
+
+#include "nn_internal.h"
+
+namespace pamd {
+namespace nn {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint32_t bf16_bits(float f)
+{
+    // round to nearest even
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+__device__ __forceinline__ float bf16_float(uint32_t h) { return __uint_as_float(h << 16); }
+__device__ __forceinline__ uint32_t pack2(float a, float b) { return bf16_bits(a) | (bf16_bits(b) << 16); }
+__device__ __forceinline__ void unpack8(const uint4& v, float* o)
+{
+    o[0] = __uint_as_float(v.x << 16);
+    o[1] = __uint_as_float(v.x & 0xFFFF0000u);
+    o[2] = __uint_as_float(v.y << 16);
+    o[3] = __uint_as_float(v.y & 0xFFFF0000u);
+    o[4] = __uint_as_float(v.z << 16);
+    o[5] = __uint_as_float(v.z & 0xFFFF0000u);
+    o[6] = __uint_as_float(v.w << 16);
+    o[7] = __uint_as_float(v.w & 0xFFFF0000u);
+}
+
+// D (16x16) += A (16x32) B (32x16).  Lane l holds A[l % 16][8 (l / 16) + e],
+// B[8 (l / 16) + e][l % 16] (e = 0..7) and D[4 (l / 16) + e][l % 16] (e = 0..3).
+__device__ __forceinline__ f32x4 mfma(const uint4& a, const uint4& b, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                     0, 0, 0);
+}
+
+__device__ __forceinline__ void silu_d(float h, float& a, float& d1)
+{
+    const float sg = 1.0f / (1.0f + __expf(-h));
+    a = h * sg;
+    d1 = sg * (1.0f + h * (1.0f - sg));
+}
+__device__ __forceinline__ void silu_dd(float h, float& a, float& d1, float& d2)
+{
+    const float sg = 1.0f / (1.0f + __expf(-h));
+    a = h * sg;
+    d1 = sg * (1.0f + h * (1.0f - sg));
+    d2 = sg * (1.0f - sg) * (2.0f + h * (1.0f - 2.0f * sg));
+}
+
+constexpr float kL2e = 1.44269504088896341f;   // log2(e)
+constexpr float kEm1 = 0.367879441171442322f;  // e^-1
+
+// phi_k(r) for k = 8c .. 8c + 7 from u_k = (r - mu_k) / s:
+//   phi_{k+1} = phi_k q_k,  q_k = exp(u_k - 1/2),  q_{k+1} = q_k / e.
+// Each chunk starts from two exponentials, so no chunk can underflow before
+// its values become representable; u is clamped to +-40, where every value of
+// the chunk is below 1e-100 and the products stay finite.
+template <typename Body>
+__device__ __forceinline__ void rbf_chunks(float u0, Body&& body)
+{
+#pragma unroll
+    for (int ch = 0; ch < kRbf / 8; ++ch) {
+        const float uc = fminf(fmaxf(u0 - (float)(8 * ch), -40.f), 40.f);
+        float g = __builtin_amdgcn_exp2f(-0.5f * kL2e * uc * uc);
+        float q = __builtin_amdgcn_exp2f(kL2e * (uc - 0.5f));
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            body(8 * ch + e, g);
+            g *= q;
+            q *= kEm1;
+        }
+    }
+}
+
+__device__ __forceinline__ int64_t io_count(const ConfIO& io) { return io.ctl ? io.ctl->R_cur : io.count; }
+__device__ __forceinline__ const float* io_x(const ConfIO& io) { return io.ctl ? io.xbase[io.ctl->cur] : io.xbase[0]; }
+
+// ---------------------------------------------------------------------------
+// features (MODE 0) and their directional derivative along delta (MODE 1):
+//   MODE 1: v_i[t, k] = sum_j phi_k'(r_ij) (x_i - x_j) . (delta_i - delta_j) / r_ij
+// Block: floor(256 / n) configurations, one lane per (configuration, atom).
+// Output rows (c n + i) of 256 BF16 values.
+// ---------------------------------------------------------------------------
+template <int MODE>
+__global__ __launch_bounds__(256) void k_nn_feat(Topo tp, ConfIO io, const float* delta, uint16_t* out)
+{
+    __shared__ float sx[768];
+    __shared__ float sd[MODE == 1 ? 768 : 1];
+    const int n = tp.n;
+    const int rpb = 256 / n;
+    const int64_t count = io_count(io);
+    const float* X = io_x(io);
+    const int tid = threadIdx.x;
+    const int rl = tid / n;
+    const int i = tid - rl * n;
+    const bool on = rl < rpb;
+    uint32_t ex0 = 0, ex1 = 0, ex2 = 0;
+    if (on) {
+        ex0 = tp.excl[i][0];
+        ex1 = tp.excl[i][1];
+        ex2 = tp.excl[i][2];
+    }
+    const float inv_s = 1.0f / kSig;
+    const float u_off = kMu0 / kSig;
+    for (int64_t c0 = (int64_t)blockIdx.x * rpb; c0 < count; c0 += (int64_t)gridDim.x * rpb) {
+        __syncthreads();
+        for (int q = tid; q < rpb * n * 3; q += 256) {
+            const int cl = q / (3 * n);
+            const int rem = q - cl * 3 * n;
+            const int a = rem / 3, comp = rem - 3 * a;
+            const int64_t c = c0 + cl;
+            float v = 0.f, dv = 0.f;
+            if (c < count) {
+                v = X[c * io.xs_conf + comp * io.xs_comp + a * io.xs_atom];
+                if constexpr (MODE == 1)
+                    dv = delta[(c * n + a) * 3 + comp];
+            }
+            sx[q] = v;
+            if constexpr (MODE == 1)
+                sd[q] = dv;
+        }
+        __syncthreads();
+        const int64_t c = c0 + rl;
+        if (!on || c >= count)
+            continue;
+        const float* px = sx + rl * 3 * n;
+        const float xi = px[3 * i], yi = px[3 * i + 1], zi = px[3 * i + 2];
+        const float* pd = sd + (MODE == 1 ? rl * 3 * n : 0);
+        float di0 = 0.f, di1 = 0.f, di2 = 0.f;
+        if constexpr (MODE == 1) {
+            di0 = pd[3 * i];
+            di1 = pd[3 * i + 1];
+            di2 = pd[3 * i + 2];
+        }
+        uint4* orow = reinterpret_cast<uint4*>(out + (size_t)(c * n + i) * kFeat);
+        for (int t = 0; t < kTypes; ++t) {
+            float acc[kRbf];
+#pragma unroll
+            for (int k = 0; k < kRbf; ++k)
+                acc[k] = 0.f;
+            for (int p = tp.tstart[t]; p < tp.tstart[t + 1]; ++p) {
+                const int j = tp.order[p];
+                const uint32_t word = j < 32 ? ex0 : (j < 64 ? ex1 : ex2);
+                const bool excluded = (word >> (j & 31)) & 1u;
+                const float dx = xi - px[3 * j], dy = yi - px[3 * j + 1], dz = zi - px[3 * j + 2];
+                const float r2 = dx * dx + dy * dy + dz * dz;
+                if constexpr (MODE == 0) {
+                    const float w = excluded ? 0.f : 1.f;
+                    const float u0 = __builtin_sqrtf(r2) * inv_s - u_off;
+                    rbf_chunks(u0, [&](int k, float phi) { acc[k] = fmaf(w, phi, acc[k]); });
+                } else {
+                    const float rinv = excluded ? 0.f : __builtin_amdgcn_rsqf(r2);
+                    const float w = (dx * (di0 - pd[3 * j]) + dy * (di1 - pd[3 * j + 1]) + dz * (di2 - pd[3 * j + 2])) *
+                                    rinv;
+                    const float u0 = r2 * rinv * inv_s - u_off;
+                    const float cw = -w * inv_s;   // phi_k' = -(u_k / s) phi_k
+                    rbf_chunks(u0, [&](int k, float phi) { acc[k] = fmaf(phi, cw * (u0 - (float)k), acc[k]); });
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                uint4 v;
+                v.x = pack2(acc[8 * q], acc[8 * q + 1]);
+                v.y = pack2(acc[8 * q + 2], acc[8 * q + 3]);
+                v.z = pack2(acc[8 * q + 4], acc[8 * q + 5]);
+                v.w = pack2(acc[8 * q + 6], acc[8 * q + 7]);
+                orow[4 * t + q] = v;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// fused MLP: per 64-row tile, energies e (FP32) and dE/dG (BF16).
+// Four waves; layer outputs are split over the waves by column, activations
+// pass through LDS (rows padded by 16 bytes against bank conflicts), weight
+// fragments come from the (L2-resident) BF16 copies.
+// ---------------------------------------------------------------------------
+constexpr int kTM = 64;
+constexpr int kLdX = kFeat + 8;
+constexpr int kLdH = kH + 8;
+
+__global__ __launch_bounds__(256) void k_nn_mlp(Weights w, const uint16_t* G, uint16_t* gG, float* e_out,
+                                                const RunCtl* ctl, int64_t rows_fixed, int n)
+{
+    __shared__ __align__(16) uint16_t Xs[kTM * kLdX];
+    __shared__ __align__(16) uint16_t Ys[kTM * kLdH];
+    __shared__ __align__(16) uint16_t Zs[kTM * kLdH];
+    __shared__ float es[4][kTM];
+    const int64_t M = ctl ? ctl->R_cur * (int64_t)n : rows_fixed;
+    const int64_t row0 = (int64_t)blockIdx.x * kTM;
+    if (row0 >= M)
+        return;
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63, l16 = lane & 15, g4 = lane >> 4;
+
+    for (int q = tid; q < kTM * 32; q += 256) {
+        const int r = q >> 5, ch = q & 31;
+        uint4 v = {0u, 0u, 0u, 0u};
+        if (row0 + r < M)
+            v = *reinterpret_cast<const uint4*>(G + (size_t)(row0 + r) * kFeat + ch * 8);
+        *reinterpret_cast<uint4*>(Xs + r * kLdX + ch * 8) = v;
+    }
+    __syncthreads();
+
+    // layer 1: h1 = G W1 + b1, this wave's columns 32 wave .. 32 wave + 31
+    float s1[4][2][4];
+    {
+        f32x4 acc[4][2];
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+            for (int ct = 0; ct < 2; ++ct)
+                acc[rt][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+        for (int ks = 0; ks < kFeat / 32; ++ks) {
+            uint4 b[2];
+#pragma unroll
+            for (int ct = 0; ct < 2; ++ct)
+                b[ct] = *reinterpret_cast<const uint4*>(w.W1T + (size_t)(32 * wave + 16 * ct + l16) * kFeat + 32 * ks +
+                                                        8 * g4);
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt) {
+                const uint4 a = *reinterpret_cast<const uint4*>(Xs + (16 * rt + l16) * kLdX + 32 * ks + 8 * g4);
+#pragma unroll
+                for (int ct = 0; ct < 2; ++ct)
+                    acc[rt][ct] = mfma(a, b[ct], acc[rt][ct]);
+            }
+        }
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) {
+            const int col = 32 * wave + 16 * ct + l16;
+            const float bias = w.b1[col];
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int row = 16 * rt + 4 * g4 + e;
+                    float a1;
+                    silu_d(acc[rt][ct][e] + bias, a1, s1[rt][ct][e]);
+                    Ys[row * kLdH + col] = (uint16_t)bf16_bits(a1);
+                }
+        }
+    }
+    __syncthreads();
+
+    // layer 2: h2 = a1 W2 + b2; e partial = a2 . w3; g2 = w3 silu'(h2)
+    {
+        f32x4 acc[4][2];
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+            for (int ct = 0; ct < 2; ++ct)
+                acc[rt][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < kH / 32; ++ks) {
+            uint4 b[2];
+#pragma unroll
+            for (int ct = 0; ct < 2; ++ct)
+                b[ct] = *reinterpret_cast<const uint4*>(w.W2T + (size_t)(32 * wave + 16 * ct + l16) * kH + 32 * ks +
+                                                        8 * g4);
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt) {
+                const uint4 a = *reinterpret_cast<const uint4*>(Ys + (16 * rt + l16) * kLdH + 32 * ks + 8 * g4);
+#pragma unroll
+                for (int ct = 0; ct < 2; ++ct)
+                    acc[rt][ct] = mfma(a, b[ct], acc[rt][ct]);
+            }
+        }
+        float ep[4][4];
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                ep[rt][e] = 0.f;
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) {
+            const int col = 32 * wave + 16 * ct + l16;
+            const float bias = w.b2[col], w3c = w.w3[col];
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int row = 16 * rt + 4 * g4 + e;
+                    float a2, s2;
+                    silu_d(acc[rt][ct][e] + bias, a2, s2);
+                    ep[rt][e] += a2 * w3c;
+                    Zs[row * kLdH + col] = (uint16_t)bf16_bits(w3c * s2);
+                }
+        }
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                float v = ep[rt][e];
+#pragma unroll
+                for (int o = 8; o >= 1; o >>= 1)
+                    v += __shfl_xor(v, o, 16);
+                if (l16 == 0)
+                    es[wave][16 * rt + 4 * g4 + e] = v;
+            }
+    }
+    __syncthreads();
+
+    // g1 = (g2 W2^T) * silu'(h1): the same columns as this wave's layer-1 output
+    {
+        f32x4 acc[4][2];
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+            for (int ct = 0; ct < 2; ++ct)
+                acc[rt][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < kH / 32; ++ks) {
+            uint4 b[2];
+#pragma unroll
+            for (int ct = 0; ct < 2; ++ct)
+                b[ct] = *reinterpret_cast<const uint4*>(w.W2 + (size_t)(32 * wave + 16 * ct + l16) * kH + 32 * ks +
+                                                        8 * g4);
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt) {
+                const uint4 a = *reinterpret_cast<const uint4*>(Zs + (16 * rt + l16) * kLdH + 32 * ks + 8 * g4);
+#pragma unroll
+                for (int ct = 0; ct < 2; ++ct)
+                    acc[rt][ct] = mfma(a, b[ct], acc[rt][ct]);
+            }
+        }
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) {
+            const int col = 32 * wave + 16 * ct + l16;
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int row = 16 * rt + 4 * g4 + e;
+                    Ys[row * kLdH + col] = (uint16_t)bf16_bits(acc[rt][ct][e] * s1[rt][ct][e]);
+                }
+        }
+    }
+    __syncthreads();
+
+    // dE/dG = g1 W1^T: this wave's columns 64 wave .. 64 wave + 63, staged in Xs
+    {
+        f32x4 acc[4][4];
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+            for (int ct = 0; ct < 4; ++ct)
+                acc[rt][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < kH / 32; ++ks) {
+            uint4 b[4];
+#pragma unroll
+            for (int ct = 0; ct < 4; ++ct)
+                b[ct] = *reinterpret_cast<const uint4*>(w.W1 + (size_t)(64 * wave + 16 * ct + l16) * kH + 32 * ks +
+                                                        8 * g4);
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt) {
+                const uint4 a = *reinterpret_cast<const uint4*>(Ys + (16 * rt + l16) * kLdH + 32 * ks + 8 * g4);
+#pragma unroll
+                for (int ct = 0; ct < 4; ++ct)
+                    acc[rt][ct] = mfma(a, b[ct], acc[rt][ct]);
+            }
+        }
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) {
+            const int col = 64 * wave + 16 * ct + l16;
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    Xs[(16 * rt + 4 * g4 + e) * kLdX + col] = (uint16_t)bf16_bits(acc[rt][ct][e]);
+        }
+    }
+    __syncthreads();
+    for (int q = tid; q < kTM * 32; q += 256) {
+        const int r = q >> 5, ch = q & 31;
+        if (row0 + r < M)
+            *reinterpret_cast<uint4*>(gG + (size_t)(row0 + r) * kFeat + ch * 8) =
+                *reinterpret_cast<const uint4*>(Xs + r * kLdX + ch * 8);
+    }
+    if (tid < kTM && row0 + tid < M)
+        e_out[row0 + tid] = es[0][tid] + es[1][tid] + es[2][tid] + es[3][tid] + w.b3[0];
+}
+
+// ---------------------------------------------------------------------------
+// forces from dE/dG (and, optionally, configuration energies from the row
+// energies).  Pass 1: lane (c, i) fills A[c][i][j] = dE_i / dr_ij for every j;
+// pass 2: F_i = -sum_j (A_ij + A_ji) (x_i - x_j) / r_ij.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_nn_force(Topo tp, ConfIO io, const uint16_t* gG, const float* e_row,
+                                                  float* E_out)
+{
+    extern __shared__ __align__(16) float fsm[];
+    const int n = tp.n;
+    const int rpb = 256 / n;
+    float* sx = fsm;                  // [rpb][n][3]
+    float* A = sx + rpb * n * 3;      // [rpb][n][n]
+    float* es = A + rpb * n * n;      // [256]
+    const int64_t count = io_count(io);
+    const float* X = io_x(io);
+    const int tid = threadIdx.x;
+    const int rl = tid / n;
+    const int i = tid - rl * n;
+    const bool on = rl < rpb;
+    uint32_t ex0 = 0, ex1 = 0, ex2 = 0;
+    if (on) {
+        ex0 = tp.excl[i][0];
+        ex1 = tp.excl[i][1];
+        ex2 = tp.excl[i][2];
+    }
+    const float inv_s = 1.0f / kSig;
+    const float u_off = kMu0 / kSig;
+    for (int64_t c0 = (int64_t)blockIdx.x * rpb; c0 < count; c0 += (int64_t)gridDim.x * rpb) {
+        __syncthreads();
+        for (int q = tid; q < rpb * n * 3; q += 256) {
+            const int cl = q / (3 * n);
+            const int rem = q - cl * 3 * n;
+            const int a = rem / 3, comp = rem - 3 * a;
+            const int64_t c = c0 + cl;
+            sx[q] = (c < count) ? X[c * io.xs_conf + comp * io.xs_comp + a * io.xs_atom] : 0.f;
+        }
+        __syncthreads();
+        const int64_t c = c0 + rl;
+        const bool act = on && c < count;
+        const float* px = sx + rl * 3 * n;
+        float xi = 0.f, yi = 0.f, zi = 0.f;
+        if (act) {
+            xi = px[3 * i];
+            yi = px[3 * i + 1];
+            zi = px[3 * i + 2];
+            const uint4* grow = reinterpret_cast<const uint4*>(gG + (size_t)(c * n + i) * kFeat);
+            float* Ai = A + (rl * n + i) * n;
+            for (int t = 0; t < kTypes; ++t) {
+                if (tp.tstart[t] == tp.tstart[t + 1])
+                    continue;
+                float gg[kRbf];
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    unpack8(grow[4 * t + q], gg + 8 * q);
+                for (int p = tp.tstart[t]; p < tp.tstart[t + 1]; ++p) {
+                    const int j = tp.order[p];
+                    const uint32_t word = j < 32 ? ex0 : (j < 64 ? ex1 : ex2);
+                    const bool excluded = (word >> (j & 31)) & 1u;
+                    const float dx = xi - px[3 * j], dy = yi - px[3 * j + 1], dz = zi - px[3 * j + 2];
+                    const float u0 = __builtin_sqrtf(dx * dx + dy * dy + dz * dz) * inv_s - u_off;
+                    float S = 0.f;
+                    rbf_chunks(u0, [&](int k, float phi) { S = fmaf(phi * gg[k], u0 - (float)k, S); });
+                    Ai[j] = excluded ? 0.f : -inv_s * S;
+                }
+            }
+        }
+        __syncthreads();
+        float eacc = 0.f;
+        if (act) {
+            const float* Ai = A + (rl * n + i) * n;
+            const float* Ab = A + rl * n * n;
+            float fx = 0.f, fy = 0.f, fz = 0.f;
+            for (int j = 0; j < n; ++j) {
+                const float s = Ai[j] + Ab[j * n + i];
+                const float dx = xi - px[3 * j], dy = yi - px[3 * j + 1], dz = zi - px[3 * j + 2];
+                const float r2 = dx * dx + dy * dy + dz * dz;
+                const float g = (j == i) ? 0.f : s * __builtin_amdgcn_rsqf(r2);
+                fx -= g * dx;
+                fy -= g * dy;
+                fz -= g * dz;
+            }
+            float* f = io.fout + c * io.fs_conf + i * io.fs_atom;
+            f[0] = fx;
+            f[io.fs_comp] = fy;
+            f[2 * io.fs_comp] = fz;
+            if (E_out)
+                eacc = e_row[c * n + i];
+        }
+        if (E_out) {
+            es[tid] = eacc;
+            __syncthreads();
+            if (act && i == 0) {
+                float s = 0.f;
+                for (int a = 0; a < n; ++a)
+                    s += es[rl * n + a];
+                E_out[c] = s;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// training: generic BF16 GEMM with FP32 output, split over K by blockIdx.z
+//   C_z[m][n] = sum_{k in chunk z} A(m, k) B(k, n),
+//   A(m, k) = A[m sam + k sak],  B(k, n) = B[k sbk + n sbn]
+// 64x64 tiles, four waves of 32x32, operands staged k-contiguous in LDS.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_gemm(const uint16_t* A, int64_t sam, int64_t sak, const uint16_t* B,
+                                              int64_t sbk, int64_t sbn, float* C, int64_t M, int64_t N, int64_t K,
+                                              int64_t kchunk)
+{
+    __shared__ __align__(16) uint16_t As[64 * 40];
+    __shared__ __align__(16) uint16_t Bs[64 * 40];
+    const int64_t m0 = (int64_t)blockIdx.y * 64, n0 = (int64_t)blockIdx.x * 64;
+    const int64_t kb = (int64_t)blockIdx.z * kchunk;
+    const int64_t ke = (K < kb + kchunk) ? K : kb + kchunk;
+    C += (size_t)blockIdx.z * M * N;
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63, l16 = lane & 15, g4 = lane >> 4;
+    const int wm = wave >> 1, wn = wave & 1;
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct)
+            acc[rt][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int sr = tid >> 2, sk = (tid & 3) * 8;
+    for (int64_t k0 = kb; k0 < ke; k0 += 32) {
+        __syncthreads();
+        {
+            uint16_t va[8], vb[8];
+            const int64_t m = m0 + sr, nn = n0 + sr;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int64_t k = k0 + sk + e;
+                va[e] = (m < M && k < ke) ? A[m * sam + k * sak] : (uint16_t)0;
+                vb[e] = (nn < N && k < ke) ? B[k * sbk + nn * sbn] : (uint16_t)0;
+            }
+            uint4 pa, pb;
+            pa.x = va[0] | ((uint32_t)va[1] << 16);
+            pa.y = va[2] | ((uint32_t)va[3] << 16);
+            pa.z = va[4] | ((uint32_t)va[5] << 16);
+            pa.w = va[6] | ((uint32_t)va[7] << 16);
+            pb.x = vb[0] | ((uint32_t)vb[1] << 16);
+            pb.y = vb[2] | ((uint32_t)vb[3] << 16);
+            pb.z = vb[4] | ((uint32_t)vb[5] << 16);
+            pb.w = vb[6] | ((uint32_t)vb[7] << 16);
+            *reinterpret_cast<uint4*>(As + sr * 40 + sk) = pa;
+            *reinterpret_cast<uint4*>(Bs + sr * 40 + sk) = pb;
+        }
+        __syncthreads();
+        uint4 a[2], b[2];
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt)
+            a[rt] = *reinterpret_cast<const uint4*>(As + (32 * wm + 16 * rt + l16) * 40 + 8 * g4);
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct)
+            b[ct] = *reinterpret_cast<const uint4*>(Bs + (32 * wn + 16 * ct + l16) * 40 + 8 * g4);
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+            for (int ct = 0; ct < 2; ++ct)
+                acc[rt][ct] = mfma(a[rt], b[ct], acc[rt][ct]);
+    }
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t row = m0 + 32 * wm + 16 * rt + 4 * g4 + e;
+                const int64_t col = n0 + 32 * wn + 16 * ct + l16;
+                if (row < M && col < N)
+                    C[row * N + col] = acc[rt][ct][e];
+            }
+}
+
+// out[i] = alpha * sum_z part[z len + i]
+__global__ void k_reduce(const float* part, int nz, int64_t len, float alpha, float* out)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += (int64_t)gridDim.x * blockDim.x) {
+        float s = 0.f;
+        for (int z = 0; z < nz; ++z)
+            s += part[(size_t)z * len + i];
+        out[i] = alpha * s;
+    }
+}
+
+// partial column sums of X [M][128]: part[b][col] over the rows of block b
+__global__ __launch_bounds__(256) void k_colsum(const float* X, int64_t M, float* part)
+{
+    __shared__ float sh[256];
+    const int col = threadIdx.x & (kH - 1), half = threadIdx.x >> 7;
+    const int64_t per = (M + gridDim.x - 1) / gridDim.x;
+    const int64_t r0 = (int64_t)blockIdx.x * per;
+    const int64_t r1 = (r0 + per < M) ? r0 + per : M;
+    float s = 0.f;
+    for (int64_t r = r0 + half; r < r1; r += 2)
+        s += X[r * kH + col];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    if (half == 0)
+        part[(size_t)blockIdx.x * kH + col] = sh[col] + sh[col + kH];
+}
+
+// after [h1 | dh1] = [G ; V] W1 (rows 0..M-1 and M..2M-1 of HD)
+__global__ void k_tr_e1(int64_t M, const float* HD, const float* b1, uint16_t* AD, float* S1, float* T1)
+{
+    const int64_t len = M * kH;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < len; q += (int64_t)gridDim.x * blockDim.x) {
+        const int col = (int)(q & (kH - 1));
+        float a, d1, d2;
+        silu_dd(HD[q] + b1[col], a, d1, d2);
+        const float dh = HD[len + q];
+        AD[q] = (uint16_t)bf16_bits(a);            // a1
+        AD[len + q] = (uint16_t)bf16_bits(d1 * dh); // da1
+        S1[q] = d1;
+        T1[q] = d2 * dh;
+    }
+}
+
+// after [h2 | dh2] = [a1 ; da1] W2: adjoints of the directional derivative
+//   rows 0..M-1:  hbar2 = w3 silu''(h2) dh2,  rows M..2M-1:  dhdot2 = w3 silu'(h2)
+__global__ void k_tr_e2(int64_t M, const float* HD, const float* b2, const float* w3, uint16_t* D2, float* HB2,
+                        float* DA2)
+{
+    const int64_t len = M * kH;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < len; q += (int64_t)gridDim.x * blockDim.x) {
+        const int col = (int)(q & (kH - 1));
+        float a, d1, d2;
+        silu_dd(HD[q] + b2[col], a, d1, d2);
+        const float dh = HD[len + q];
+        const float hb = w3[col] * d2 * dh;
+        D2[q] = (uint16_t)bf16_bits(hb);
+        D2[len + q] = (uint16_t)bf16_bits(w3[col] * d1);
+        HB2[q] = hb;
+        DA2[q] = d1 * dh;
+    }
+}
+
+// after [abar1 | dadot1] = [hbar2 ; dhdot2] W2^T
+//   rows 0..M-1:  hbar1 = abar1 silu'(h1) + dadot1 silu''(h1) dh1,  rows M..:  dhdot1 = dadot1 silu'(h1)
+__global__ void k_tr_e3(int64_t M, const float* AB, const float* S1, const float* T1, uint16_t* D1, float* HB1)
+{
+    const int64_t len = M * kH;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < len; q += (int64_t)gridDim.x * blockDim.x) {
+        const float ab = AB[q], dd = AB[len + q];
+        const float hb = ab * S1[q] + dd * T1[q];
+        D1[q] = (uint16_t)bf16_bits(hb);
+        D1[len + q] = (uint16_t)bf16_bits(dd * S1[q]);
+        HB1[q] = hb;
+    }
+}
+
+// force-matching loss: delta = dL/dF = 2 (F - F*) / len, part[b] = block sum of (F - F*)^2 / len
+__global__ __launch_bounds__(256) void k_nn_loss(const float* F, const float* Ft, int64_t len, float* delta,
+                                                 float* part)
+{
+    __shared__ float sh[256];
+    const float inv = 1.0f / (float)len;
+    float s = 0.f;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < len; q += (int64_t)gridDim.x * blockDim.x) {
+        const float d = F[q] - Ft[q];
+        delta[q] = 2.0f * d * inv;
+        s += d * d;
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o)
+            sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        part[blockIdx.x] = sh[0] * inv;
+}
+
+__global__ void k_adam(float* p, const float* g, float* m, float* v, int n, float lr, float b1, float b2, float eps,
+                       float bc1, float bc2)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / bc1) / (__builtin_sqrtf(vi / bc2) + eps);
+}
+
+// BF16 copies of W1, W2 and their transposes from the FP32 master vector
+__global__ void k_nn_refresh(const float* p, uint16_t* W1, uint16_t* W1T, uint16_t* W2, uint16_t* W2T)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < kFeat * kH) {
+        const int f = q / kH, h = q - f * kH;
+        const uint16_t b = (uint16_t)bf16_bits(p[oW1 + q]);
+        W1[q] = b;
+        W1T[h * kFeat + f] = b;
+    }
+    if (q < kH * kH) {
+        const int a = q / kH, c = q - a * kH;
+        const uint16_t b = (uint16_t)bf16_bits(p[oW2 + q]);
+        W2[q] = b;
+        W2T[c * kH + a] = b;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+static int grid_of(int64_t work, int per_block, int cap)
+{
+    int64_t g = (work + per_block - 1) / per_block;
+    if (g < 1)
+        g = 1;
+    return (int)(g < cap ? g : cap);
+}
+
+size_t force_lds_bytes(int n)
+{
+    const int rpb = 256 / n;
+    return (size_t)(rpb * n * 3 + rpb * n * n + 256) * sizeof(float);
+}
+
+hipError_t nn_setup()
+{
+    static bool done = false;
+    if (done)
+        return hipSuccess;
+    hipError_t e = hipFuncSetAttribute((const void*)k_nn_force, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)force_lds_bytes(kMaxN));
+    if (e == hipSuccess)
+        done = true;
+    return e;
+}
+
+hipError_t launch_features(const Topo& tp, const ConfIO& io, int64_t count_max, const float* delta, uint16_t* out,
+                           hipStream_t s)
+{
+    const int rpb = 256 / tp.n;
+    const int grid = grid_of(count_max, rpb, 1 << 20);
+    if (delta)
+        hipLaunchKernelGGL(k_nn_feat<1>, dim3(grid), dim3(256), 0, s, tp, io, delta, out);
+    else
+        hipLaunchKernelGGL(k_nn_feat<0>, dim3(grid), dim3(256), 0, s, tp, io, delta, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp(const Weights& w, const uint16_t* G, uint16_t* gG, float* e, const RunCtl* ctl,
+                      int64_t rows_max, int n, hipStream_t s)
+{
+    const int grid = grid_of(rows_max, kTM, 1 << 30);
+    hipLaunchKernelGGL(k_nn_mlp, dim3(grid), dim3(256), 0, s, w, G, gG, e, ctl, rows_max, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_force(const Topo& tp, const ConfIO& io, int64_t count_max, const uint16_t* gG, const float* e_row,
+                        float* E_out, hipStream_t s)
+{
+    hipError_t e = nn_setup();
+    if (e != hipSuccess)
+        return e;
+    const int rpb = 256 / tp.n;
+    const int grid = grid_of(count_max, rpb, 1 << 20);
+    hipLaunchKernelGGL(k_nn_force, dim3(grid), dim3(256), force_lds_bytes(tp.n), s, tp, io, gG, e_row, E_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm(const uint16_t* A, int64_t sam, int64_t sak, const uint16_t* B, int64_t sbk, int64_t sbn,
+                       float* C, int64_t M, int64_t N, int64_t K, int nz, hipStream_t s)
+{
+    int64_t kchunk = (K + nz - 1) / nz;
+    kchunk = (kchunk + 31) / 32 * 32;
+    const dim3 grid((unsigned)((N + 63) / 64), (unsigned)((M + 63) / 64), (unsigned)nz);
+    hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, s, A, sam, sak, B, sbk, sbn, C, M, N, K, kchunk);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(const float* part, int nz, int64_t len, float alpha, float* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_reduce, dim3(grid_of(len, 256, 4096)), dim3(256), 0, s, part, nz, len, alpha, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_colsum(const float* X, int64_t M, float* part, int nb, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_colsum, dim3(nb), dim3(256), 0, s, X, M, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_train_e1(int64_t M, const float* HD, const float* b1, uint16_t* AD, float* S1, float* T1,
+                           hipStream_t s)
+{
+    hipLaunchKernelGGL(k_tr_e1, dim3(grid_of(M * kH, 256, 8192)), dim3(256), 0, s, M, HD, b1, AD, S1, T1);
+    return hipGetLastError();
+}
+hipError_t launch_train_e2(int64_t M, const float* HD, const float* b2, const float* w3, uint16_t* D2, float* HB2,
+                           float* DA2, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_tr_e2, dim3(grid_of(M * kH, 256, 8192)), dim3(256), 0, s, M, HD, b2, w3, D2, HB2, DA2);
+    return hipGetLastError();
+}
+hipError_t launch_train_e3(int64_t M, const float* AB, const float* S1, const float* T1, uint16_t* D1, float* HB1,
+                           hipStream_t s)
+{
+    hipLaunchKernelGGL(k_tr_e3, dim3(grid_of(M * kH, 256, 8192)), dim3(256), 0, s, M, AB, S1, T1, D1, HB1);
+    return hipGetLastError();
+}
+
+hipError_t launch_loss(const float* F, const float* Ft, int64_t len, float* delta, float* part, int nb, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_nn_loss, dim3(nb), dim3(256), 0, s, F, Ft, len, delta, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int n, float lr, float b1, float b2, float eps,
+                       float bc1, float bc2, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_adam, dim3((n + 255) / 256), dim3(256), 0, s, p, g, m, v, n, lr, b1, b2, eps, bc1, bc2);
+    return hipGetLastError();
+}
+
+hipError_t launch_refresh(const float* p, uint16_t* W1, uint16_t* W1T, uint16_t* W2, uint16_t* W2T, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_nn_refresh, dim3((kFeat * kH + 255) / 256), dim3(256), 0, s, p, W1, W1T, W2, W2T);
+    return hipGetLastError();
+}
+
+}  // namespace nn
+}  // namespace pamd

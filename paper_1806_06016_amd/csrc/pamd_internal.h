@@ -42,6 +42,9 @@ struct alignas(64) RunCtl {
     int32_t pad[3];
 };
 
+// operations of one r-RESPA kernel pass (k_respa), applied in this order
+enum : int { kRespaInnerKick = 1, kRespaOuterEnd = 2, kRespaCollide = 4, kRespaOuterStart = 8, kRespaDrift = 16 };
+
 // Per-run device pointers and constants (passed by value to kernels).
 template <typename real>
 struct RunDev {

@@ -12,6 +12,7 @@
 #include <string>
 #include <vector>
 
+#include "nn_internal.h"
 #include "pamd.h"
 #include "pamd_internal.h"
 
@@ -32,6 +33,10 @@ hipError_t launch_md_finalize(const RunDev<float>& d, int n, hipStream_t s);
 hipError_t launch_md_finalize(const RunDev<double>& d, int n, hipStream_t s);
 hipError_t launch_observables(const RunDev<float>& d, hipStream_t s);
 hipError_t launch_observables(const RunDev<double>& d, hipStream_t s);
+hipError_t launch_respa(const RunDev<float>& d, const float* fnn, int ops, uint32_t step_off, double dt_outer,
+                        uint32_t p24_outer, int blocks, int waves, hipStream_t s);
+hipError_t launch_export(const RunDev<float>& d, int64_t r0, int64_t count, float* xo, float* fo, int waves,
+                         hipStream_t s);
 }  // namespace pamd
 
 using namespace pamd;
@@ -69,6 +74,8 @@ struct Run {
     RunDev<double> d{};
     HostTables tab;
     double mtot = 0;
+    double nu = 0;                   // Andersen collision frequency
+    pamd::nn::MtsBuffers mts;        // r-RESPA buffers (surrogate attached)
 };
 
 }  // namespace
@@ -85,6 +92,8 @@ struct pamd_ctx {
     int failed = 0;
     int n_cu = 0, waves = 0, blocks = 0, gather_blocks = 0;
     size_t lds = 0;
+    pamd_nn* nn = nullptr;   // learned surrogate of the r-RESPA inner force (null: plain MD)
+    int mts_ratio = 0;       // inner steps per outer step
 };
 
 namespace {
@@ -531,8 +540,67 @@ pamd_status pamd_init(const pamd_system* sys, int32_t n_runs, const pamd_params*
     for (int r = 0; r < n_runs; ++r) {
         c->runs[r].f.waves_per_block = waves;
         c->runs[r].d.waves_per_block = waves;
+        c->runs[r].nu = p[r].nu;
     }
     return c->fp32 ? init_runs<float>(c, sys, s) : init_runs<double>(c, sys, s);
+}
+
+// F_NN at the current positions of every replica of `run` into run.mts.fnn
+static pamd_status nn_force(pamd_ctx* c, Run& run, hipStream_t s)
+{
+    const RunDev<float>& d = run.f;
+    nn::ConfIO io{};
+    io.xbase[0] = d.slab[0];
+    io.xbase[1] = d.slab[1];
+    io.fout = run.mts.fnn.as<float>();
+    io.ctl = d.ctl;
+    io.xs_conf = 6 * (int64_t)d.npad;
+    io.xs_comp = d.npad;
+    io.xs_atom = 1;
+    io.fs_conf = 3 * (int64_t)d.npad;
+    io.fs_comp = d.npad;
+    io.fs_atom = 1;
+    const pamd_nn* nn = c->nn;
+    HIPCHK(c, nn::launch_features(nn->topo, io, d.R_cap, nullptr, run.mts.G.as<uint16_t>(), s));
+    HIPCHK(c, nn::launch_mlp(nn->w, run.mts.G.as<uint16_t>(), run.mts.gG.as<uint16_t>(), run.mts.e.as<float>(), d.ctl,
+                             d.R_cap * d.n, d.n, s));
+    HIPCHK(c, nn::launch_force(nn->topo, io, d.R_cap, run.mts.gG.as<uint16_t>(), run.mts.e.as<float>(), nullptr, s));
+    return PAMD_OK;
+}
+
+// n_steps / M r-RESPA outer steps of `run` (M = c->mts_ratio), then the
+// exact potential energies.  The last inner half kick, both outer impulses,
+// the collisions and the next step's first drift all act at the same
+// positions and share one k_respa pass.
+static pamd_status respa_steps(pamd_ctx* c, Run& run, int n_steps, hipStream_t s)
+{
+    const RunDev<float>& d = run.f;
+    const int M = c->mts_ratio;
+    const int n_outer = n_steps / M;
+    const double Dt = M * d.dt;
+    const uint32_t p24 = (uint32_t)llround((1.0 - exp(-run.nu * Dt)) * 16777216.0);
+    const float* fnn = run.mts.fnn.as<float>();
+    pamd_status st = PAMD_OK;
+    if (n_outer > 0) {
+        if ((st = nn_force(c, run, s)) != PAMD_OK)
+            return st;
+        HIPCHK(c, launch_respa(d, fnn, kRespaOuterStart | kRespaDrift, 0, Dt, p24, c->blocks, c->waves, s));
+        for (int o = 0; o < n_outer; ++o) {
+            for (int q = 0; q < M; ++q) {
+                if ((st = nn_force(c, run, s)) != PAMD_OK)
+                    return st;
+                if (q < M - 1)
+                    HIPCHK(c, launch_respa(d, fnn, kRespaInnerKick | kRespaDrift, 0, Dt, p24, c->blocks, c->waves, s));
+            }
+            int ops = kRespaInnerKick | kRespaOuterEnd | kRespaCollide;
+            if (o < n_outer - 1)
+                ops |= kRespaOuterStart | kRespaDrift;
+            HIPCHK(c, launch_respa(d, fnn, ops, (uint32_t)(o * M), Dt, p24, c->blocks, c->waves, s));
+        }
+    }
+    HIPCHK(c, launch_energy(d, c->blocks, c->waves, s));
+    HIPCHK(c, launch_md_finalize(d, n_steps, s));
+    return PAMD_OK;
 }
 
 pamd_status pamd_md_steps(pamd_ctx* c, int32_t n_steps, void* stream)
@@ -543,6 +611,16 @@ pamd_status pamd_md_steps(pamd_ctx* c, int32_t n_steps, void* stream)
     if (n_steps < 0)
         return fail(c, PAMD_ERR_ARG, "n_steps < 0");
     hipStream_t s = as_stream(stream);
+    if (c->nn) {
+        if (n_steps % c->mts_ratio != 0)
+            return fail(c, PAMD_ERR_ARG, "n_steps must be a multiple of the r-RESPA outer ratio");
+        for (auto& run : c->runs) {
+            st = respa_steps(c, run, n_steps, s);
+            if (st != PAMD_OK)
+                return st;
+        }
+        return PAMD_OK;
+    }
     for (auto& run : c->runs) {
         if (c->fp32) {
             HIPCHK(c, launch_md(run.f, n_steps, c->blocks, c->waves, s));
@@ -886,12 +964,71 @@ pamd_status pamd_graph_launch(pamd_ctx* c, int32_t slot, void* stream)
     return PAMD_OK;
 }
 
+pamd_status pamd_export_configs(pamd_ctx* c, int32_t run, int64_t r0, int64_t count, float* d_x, float* d_F_nb,
+                                void* stream)
+{
+    pamd_status st = check_ctx(c);
+    if (st != PAMD_OK)
+        return st;
+    if (!c->fp32)
+        return fail(c, PAMD_ERR_ARG, "configuration export needs an FP32 context");
+    if (run < 0 || run >= c->n_runs)
+        return fail(c, PAMD_ERR_ARG, "run index out of range");
+    const RunDev<float>& d = c->runs[run].f;
+    if (r0 < 0 || count < 0 || r0 + count > d.R_cap || (count > 0 && (!d_x || !d_F_nb)))
+        return fail(c, PAMD_ERR_ARG, "replica range or output arrays invalid");
+    if (count == 0)
+        return PAMD_OK;
+    HIPCHK(c, launch_export(d, r0, count, d_x, d_F_nb, c->waves, as_stream(stream)));
+    return PAMD_OK;
+}
+
+pamd_status pamd_set_mts(pamd_ctx* c, pamd_nn* nn, int32_t outer_ratio, void* stream)
+{
+    pamd_status st = check_ctx(c);
+    if (st != PAMD_OK)
+        return st;
+    hipStream_t s = as_stream(stream);
+    HIPCHK(c, hipStreamSynchronize(s));
+    if (!nn) {
+        for (auto& run : c->runs)
+            for (nn::DevBuf* b : {&run.mts.G, &run.mts.gG, &run.mts.e, &run.mts.fnn})
+                b->release();
+        c->nn = nullptr;
+        c->mts_ratio = 0;
+        return PAMD_OK;
+    }
+    if (!c->fp32)
+        return fail(c, PAMD_ERR_ARG, "r-RESPA with the surrogate needs an FP32 context");
+    if (outer_ratio < 1)
+        return fail(c, PAMD_ERR_ARG, "outer_ratio must be >= 1");
+    for (auto& run : c->runs)
+        if (run.f.n != nn->topo.n)
+            return fail(c, PAMD_ERR_ARG, "surrogate atom count differs from a run's");
+    for (auto& run : c->runs) {
+        const RunDev<float>& d = run.f;
+        const size_t rows = (size_t)d.R_cap * d.n;
+        HIPCHK(c, run.mts.G.need(rows * nn::kFeat * 2, s));
+        HIPCHK(c, run.mts.gG.need(rows * nn::kFeat * 2, s));
+        HIPCHK(c, run.mts.e.need(rows * 4, s));
+        HIPCHK(c, run.mts.fnn.need((size_t)d.R_cap * 3 * d.npad * 4, s));
+    }
+    c->nn = nn;
+    c->mts_ratio = outer_ratio;
+    return PAMD_OK;
+}
+
 void pamd_destroy(pamd_ctx* c)
 {
     if (!c)
         return;
     for (int g = 0; g < kGraphSlots; ++g)
         drop_graph(c, g);
+    if (c->nn)
+        (void)hipDeviceSynchronize();
+    for (auto& run : c->runs)
+        for (nn::DevBuf* b : {&run.mts.G, &run.mts.gG, &run.mts.e, &run.mts.fnn})
+            b->release();
     delete c;
 }
 

@@ -66,7 +66,13 @@ class pamd_run_scalars(C.Structure):
 EXPORTS = ["pamd_query_sizes", "pamd_init", "pamd_md_steps", "pamd_resample", "pamd_observables",
            "pamd_graph_capture", "pamd_graph_launch", "pamd_set_schedule",
            "pamd_get_forces", "pamd_get_state", "pamd_set_state", "pamd_get_counts",
-           "pamd_launch_info", "pamd_destroy", "pamd_last_error"]
+           "pamd_launch_info", "pamd_destroy", "pamd_last_error",
+           "pamd_nn_create", "pamd_nn_set_weights", "pamd_nn_get_weights", "pamd_nn_forces",
+           "pamd_nn_loss_grad", "pamd_nn_train_step", "pamd_nn_destroy", "pamd_nn_last_error",
+           "pamd_export_configs", "pamd_set_mts"]
+NN_PARAMS = 49665
+NN_FEATURES, NN_HIDDEN, NN_TYPES = 256, 128, 8
+_NO_STATUS = ("pamd_destroy", "pamd_last_error", "pamd_nn_destroy", "pamd_nn_last_error")
 
 _lib = None
 
@@ -102,8 +108,21 @@ def load_library(path: str = LIB_PATH):
     lib.pamd_destroy.restype = None
     lib.pamd_last_error.argtypes = [vp]
     lib.pamd_last_error.restype = C.c_char_p
-    for name in EXPORTS[:-2]:
-        getattr(lib, name).restype = i32
+    lib.pamd_nn_create.argtypes = [vp, vp, P(vp)]
+    lib.pamd_nn_set_weights.argtypes = [vp, vp, vp]
+    lib.pamd_nn_get_weights.argtypes = [vp, vp, vp]
+    lib.pamd_nn_forces.argtypes = [vp, i64, vp, vp, vp, vp]
+    lib.pamd_nn_loss_grad.argtypes = [vp, i64, vp, vp, vp, vp, vp]
+    lib.pamd_nn_train_step.argtypes = [vp, i64, vp, vp, C.c_float, vp, vp]
+    lib.pamd_nn_destroy.argtypes = [vp]
+    lib.pamd_nn_destroy.restype = None
+    lib.pamd_nn_last_error.argtypes = [vp]
+    lib.pamd_nn_last_error.restype = C.c_char_p
+    lib.pamd_export_configs.argtypes = [vp, i32, i64, i64, vp, vp, vp]
+    lib.pamd_set_mts.argtypes = [vp, vp, i32, vp]
+    for name in EXPORTS:
+        if name not in _NO_STATUS:
+            getattr(lib, name).restype = i32
     _lib = lib
     return lib
 
@@ -299,6 +318,26 @@ class Pamd:
         self._check(self.lib.pamd_set_state(self.ctx, run, _ptr(x), _ptr(v), _ptr(Ep), _ptr(an), C.byref(sc),
                                             self._s()), self.ctx)
 
+    # -- learned multiple-time-step surrogate ------------------------------------
+    def export_configs(self, run: int = 0, r0: int = 0, count: Optional[int] = None):
+        """Positions and exact nonbonded forces of replicas [r0, r0 + count) as
+        CUDA float32 tensors [count, n, 3] (FP32 contexts)."""
+        torch = self.torch
+        n = self.n_atoms[run]
+        if count is None:
+            count = self.get_state(run, want_xv=False)["R"] - r0
+        x = torch.empty((count, n, 3), dtype=torch.float32, device="cuda")
+        f = torch.empty((count, n, 3), dtype=torch.float32, device="cuda")
+        self._check(self.lib.pamd_export_configs(self.ctx, run, int(r0), int(count), x.data_ptr(), f.data_ptr(),
+                                                 self._s()), self.ctx)
+        return x, f
+
+    def set_mts(self, nn: Optional["PamdNN"], outer_ratio: int = 4) -> None:
+        """Attach surrogate `nn` (r-RESPA, outer step outer_ratio * dt) or detach (None)."""
+        self._mts_nn = nn
+        self._check(self.lib.pamd_set_mts(self.ctx, nn.handle if nn is not None else None, int(outer_ratio),
+                                          self._s()), self.ctx)
+
     def get_counts(self, run: int = 0) -> np.ndarray:
         c = np.zeros(self.R_cap, np.int32)
         n = C.c_int64()
@@ -309,6 +348,93 @@ class Pamd:
         if getattr(self, "ctx", None):
             self.lib.pamd_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def pack_params(w: Dict[str, np.ndarray]) -> np.ndarray:
+    """Flat FP32 parameter vector (W1, b1, W2, b2, w3, b3) from a weight dict."""
+    v = np.concatenate([np.asarray(w[k], np.float64).ravel() for k in ("W1", "b1", "W2", "b2", "w3", "b3")])
+    assert v.size == NN_PARAMS
+    return np.ascontiguousarray(v, np.float32)
+
+
+def unpack_params(v: np.ndarray) -> Dict[str, np.ndarray]:
+    v = np.asarray(v)
+    F, H = NN_FEATURES, NN_HIDDEN
+    o = np.cumsum([0, F * H, H, H * H, H, H, 1])
+    return {"W1": v[o[0]:o[1]].reshape(F, H), "b1": v[o[1]:o[2]], "W2": v[o[2]:o[3]].reshape(H, H),
+            "b2": v[o[3]:o[4]], "w3": v[o[4]:o[5]], "b3": v[o[5]:o[6]]}
+
+
+class PamdNN:
+    """The learned surrogate of one molecule (pamd_nn_* calls).  Configuration
+    arrays are CUDA float32 tensors [n_conf, n, 3]."""
+
+    def __init__(self, sysd, atom_type: Sequence[int], stream=None):
+        import torch
+        self.torch = torch
+        self.lib = load_library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("the PAMD library needs a ROCm GPU")
+        self._keep: list = []
+        self._sys = make_system_struct(sysd, self._keep)
+        self.n = int(sysd.n_atoms)
+        t = np.ascontiguousarray(np.asarray(atom_type, np.int32))
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = C.c_void_p()
+        st = self.lib.pamd_nn_create(C.byref(self._sys), _ptr(t), C.byref(h))
+        if st != PAMD_OK:
+            raise PamdError(st, "pamd_nn_create failed")
+        self.handle = h
+
+    def _s(self):
+        return C.c_void_p(self.stream.cuda_stream)
+
+    def _check(self, st: int):
+        if st != PAMD_OK:
+            raise PamdError(st, self.lib.pamd_nn_last_error(self.handle).decode())
+
+    def set_weights(self, w) -> None:
+        v = pack_params(w) if isinstance(w, dict) else np.ascontiguousarray(w, np.float32)
+        self._check(self.lib.pamd_nn_set_weights(self.handle, _ptr(v), self._s()))
+
+    def get_weights(self) -> Dict[str, np.ndarray]:
+        v = np.zeros(NN_PARAMS, np.float32)
+        self._check(self.lib.pamd_nn_get_weights(self.handle, _ptr(v), self._s()))
+        return unpack_params(v)
+
+    def forces(self, x):
+        torch = self.torch
+        assert x.is_cuda and x.dtype == torch.float32 and x.is_contiguous()
+        B = x.shape[0]
+        F = torch.empty_like(x)
+        E = torch.empty(B, dtype=torch.float32, device=x.device)
+        self._check(self.lib.pamd_nn_forces(self.handle, B, x.data_ptr(), F.data_ptr(), E.data_ptr(), self._s()))
+        return E, F
+
+    def loss_grad(self, x, F_target, want_grad: bool = True):
+        torch = self.torch
+        assert x.is_contiguous() and F_target.is_contiguous() and x.shape == F_target.shape
+        loss = torch.empty(1, dtype=torch.float32, device=x.device)
+        g = torch.empty(NN_PARAMS, dtype=torch.float32, device=x.device) if want_grad else None
+        self._check(self.lib.pamd_nn_loss_grad(self.handle, x.shape[0], x.data_ptr(), F_target.data_ptr(),
+                                               loss.data_ptr(), None if g is None else g.data_ptr(), self._s()))
+        return loss, g
+
+    def train_step(self, x, F_target, lr: float, loss=None) -> None:
+        assert x.is_contiguous() and F_target.is_contiguous() and x.shape == F_target.shape
+        self._check(self.lib.pamd_nn_train_step(self.handle, x.shape[0], x.data_ptr(), F_target.data_ptr(),
+                                                float(lr), None if loss is None else loss.data_ptr(), self._s()))
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            self.lib.pamd_nn_destroy(self.handle)
+            self.handle = None
 
     def __del__(self):
         try:
