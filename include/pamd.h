@@ -250,7 +250,7 @@ const char* pamd_last_error(const pamd_ctx* ctx);
 #define PAMD_NN_FEATURES 256
 #define PAMD_NN_HIDDEN 128
 /* flat parameter vector: W1 [256][128], b1 [128], W2 [128][128], b2 [128], w3 [128], b3 [1] */
-#define PAMD_NN_PARAMS 49665
+#define PAMD_NN_PARAMS 49537
 
 typedef struct pamd_nn pamd_nn;
 

@@ -70,7 +70,7 @@ EXPORTS = ["pamd_query_sizes", "pamd_init", "pamd_md_steps", "pamd_resample", "p
            "pamd_nn_create", "pamd_nn_set_weights", "pamd_nn_get_weights", "pamd_nn_forces",
            "pamd_nn_loss_grad", "pamd_nn_train_step", "pamd_nn_destroy", "pamd_nn_last_error",
            "pamd_export_configs", "pamd_set_mts"]
-NN_PARAMS = 49665
+NN_PARAMS = 49537
 NN_FEATURES, NN_HIDDEN, NN_TYPES = 256, 128, 8
 _NO_STATUS = ("pamd_destroy", "pamd_last_error", "pamd_nn_destroy", "pamd_nn_last_error")
 

@@ -95,3 +95,19 @@ def test_binding_fails_loudly_without_library(tmp_path):
             B.load_library(str(tmp_path / "nope.so"))
     finally:
         B._lib = saved
+
+
+def test_surrogate_parameter_count_matches_layout():
+    """PAMD_NN_PARAMS = |W1| + |b1| + |W2| + |b2| + |w3| + |b3| for the
+    256 -> 128 -> 128 -> 1 network, in the header and the binding."""
+    import numpy as np
+    txt = open(os.path.join(ROOT, "include", "pamd.h")).read()
+    vals = {k: int(v) for k, v in re.findall(r"#define (PAMD_NN_\w+) (\d+)", txt)}
+    F, H = vals["PAMD_NN_FEATURES"], vals["PAMD_NN_HIDDEN"]
+    assert vals["PAMD_NN_PARAMS"] == F * H + H + H * H + H + H + 1
+    from paper_1806_06016_amd import pamd as B
+    assert B.NN_PARAMS == vals["PAMD_NN_PARAMS"] and B.NN_FEATURES == F and B.NN_HIDDEN == H
+    w = {"W1": np.zeros((F, H)), "b1": np.zeros(H), "W2": np.zeros((H, H)), "b2": np.zeros(H),
+         "w3": np.arange(H, dtype=float), "b3": np.ones(1)}
+    back = B.unpack_params(B.pack_params(w))
+    assert all(np.array_equal(back[k], w[k]) for k in w)

@@ -151,16 +151,21 @@ def test_export_configs_nonbonded_forces(B):
     p.close()
 
 
-def _respa_case(B, w, n_outer, seed=41):
+def _respa_case(B, w, n_outer, M, seed=41):
+    """Both sides start from the same relaxed state: 300 plain MD steps on
+    the GPU from the built conformation (a perturbed start has clashes whose
+    repulsion a 4 fs outer impulse cannot integrate stably, and unstable
+    trajectories diverge at rounding level).  With an untrained or zero
+    surrogate the outer impulse carries the whole stiff nonbonded force, so
+    the parity cases use an outer step of 2 inner steps."""
     sysd = S.c2_system()
-    R, T, dt, nu, M = 45, 700.0, 0.001, 1.0, 4
+    R, T, dt, nu = 45, 700.0, 0.001, 1.0
     osys = O.OracleSystem(sysd)
-    x = _confs(sysd, R, 0.005, 9)
-    v = O.init_velocities(osys, R, T, seed=3)
     p = B.Pamd([sysd], R_target=R, T0=T, dt=dt, nu=nu, seed=seed, precision=B.PAMD_FP32)
-    p.set_state(0, x, v, T=T, step=200)
+    p.md_steps(300)
     st = p.get_state(0)
-    xo, vo = st["x"].copy(), st["v"].copy()
+    xo, vo, step0 = st["x"].copy(), st["v"].copy(), st["step"]
+    print("start: max |F_nb|", np.abs(O.energy_forces(osys, xo, O.T_LJ | O.T_COUL)[1]).max(), flush=True)
     nn = B.PamdNN(sysd, sysd.atype)
     if w is not None:
         nn.set_weights(w)
@@ -172,30 +177,30 @@ def _respa_case(B, w, n_outer, seed=41):
         f = lambda xx: np.zeros_like(xx)  # noqa: E731
     else:
         f = lambda xx: NN.energy_forces(xx, sysd.atype, pairs, w)[1]  # noqa: E731
-    Ep, Ek = NN.respa_steps(osys, sysd, xo, vo, n_outer, M, dt, T, nu, seed, 200, f)
+    Ep, Ek = NN.respa_steps(osys, sysd, xo, vo, n_outer, M, dt, T, nu, seed, step0, f)
     p.set_mts(None)
     p.close()
     nn.close()
+    assert g["step"] == step0 + n_outer * M
     return g, xo, vo, Ep, Ek
 
 
 def test_respa_without_surrogate_matches_oracle(B):
     """F_NN = 0: the whole nonbonded force acts in the outer impulses."""
-    print("r-RESPA, zero surrogate, 3 outer steps", flush=True)
-    g, xo, vo, Ep, Ek = _respa_case(B, None, 3)
+    print("r-RESPA, zero surrogate, 5 outer steps of 2", flush=True)
+    g, xo, vo, Ep, Ek = _respa_case(B, None, 5, 2)
     err = np.abs(g["x"] - xo).max()
-    print("max |dx|", err)
+    print("max |dx|", err, "max |dE_pot| / |E_pot|", np.max(np.abs(g["E_pot"] - Ep) / np.abs(Ep)))
     assert err < 1e-4
-    assert g["step"] == 200 + 12
-    assert np.abs(g["E_pot"] - Ep).max() <= 1e-3 * np.abs(Ep).mean()
+    assert np.all(np.abs(g["E_pot"] - Ep) <= 1e-3 * np.abs(Ep))
     assert np.allclose(g["E_kin"], Ek, rtol=1e-3)
 
 
 def test_respa_with_surrogate_matches_oracle(B):
-    print("r-RESPA, surrogate, 2 outer steps", flush=True)
-    g, xo, vo, Ep, Ek = _respa_case(B, NN.init_weights(13), 2)
+    print("r-RESPA, surrogate, 4 outer steps", flush=True)
+    g, xo, vo, Ep, Ek = _respa_case(B, NN.init_weights(13), 4, 2)
     err = np.abs(g["x"] - xo).max()
     print("max |dx|", err)
     # 8 steps of 1 fs: (0.008 ps)^2 x |dF_NN| (<~ 2e-2 x 1e3) / 1 amu ~ 1e-3 nm at worst
     assert err < 1e-3
-    assert np.abs(g["E_pot"] - Ep).max() <= 1e-2 * np.abs(Ep).mean()
+    assert np.all(np.abs(g["E_pot"] - Ep) <= 1e-2 * np.abs(Ep))
