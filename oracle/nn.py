@@ -29,6 +29,8 @@ from typing import Callable, Dict, Optional
 
 import numpy as np
 
+from pamd_inputs.weights import surrogate_weights
+
 from . import oracle as O
 
 N_TYPES = 8
@@ -47,16 +49,8 @@ def nn_pairs(sysd):
 
 
 def init_weights(seed: int = 0, scale: float = 1.0) -> Dict[str, np.ndarray]:
-    """Seeded Glorot-style initial weights."""
-    rng = np.random.default_rng(seed)
-    return {
-        "W1": rng.normal(0, scale * math.sqrt(2.0 / (N_FEAT + H1)), (N_FEAT, H1)),
-        "b1": np.zeros(H1),
-        "W2": rng.normal(0, scale * math.sqrt(2.0 / (H1 + H2)), (H1, H2)),
-        "b2": np.zeros(H2),
-        "w3": rng.normal(0, scale * math.sqrt(2.0 / (H2 + 1)), (H2,)),
-        "b3": np.zeros(1),
-    }
+    """Seeded Glorot-style initial weights (the shared input generator)."""
+    return surrogate_weights(seed, scale)
 
 
 def _silu(x):

@@ -32,12 +32,16 @@ constexpr float kMu0 = 0.1f;
 constexpr float kSig = 1.1f / 31.0f;
 
 // the molecule as the surrogate sees it (passed by value)
+// Kernels work in "sorted" atom order: position p holds atom order[p], atoms
+// sorted by type, so the partners of type t are the contiguous positions
+// tstart[t] .. tstart[t + 1] - 1.
 struct Topo {
     int32_t n;
-    int32_t tstart[kTypes + 1];   // partners of type t: order[tstart[t] .. tstart[t + 1])
-    uint8_t order[kMaxN];         // atom indices sorted by type
-    uint8_t atype[kMaxN];
-    uint32_t excl[kMaxN][3];      // bit j of atom i: pair (i, j) carries no feature (self, 1-2, 1-3)
+    int32_t tstart[kTypes + 1];
+    uint8_t order[kMaxN];         // atom at sorted position p
+    uint8_t atype[kMaxN];         // type of atom a (natural order)
+    uint32_t excl[kMaxN][3];      // bit q of position p: the pair (order[p], order[q]) carries no
+                                  // feature (self, 1-2, 1-3)
 };
 
 // BF16 weight copies (row-major) and FP32 vectors used by the kernels

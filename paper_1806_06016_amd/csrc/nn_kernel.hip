@@ -25,15 +25,17 @@ namespace nn {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ uint32_t bf16_bits(float f)
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// float -> BF16, round to nearest even (one v_cvt_pk_bf16_f32)
+__device__ __forceinline__ uint32_t bf16_bits(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
+__device__ __forceinline__ uint32_t pack2(float a, float b)
 {
-    // round to nearest even
-    uint32_t u = __float_as_uint(f);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return u >> 16;
+    bf16x2 v;
+    v[0] = (__bf16)a;
+    v[1] = (__bf16)b;
+    return __builtin_bit_cast(uint32_t, v);
 }
-__device__ __forceinline__ float bf16_float(uint32_t h) { return __uint_as_float(h << 16); }
-__device__ __forceinline__ uint32_t pack2(float a, float b) { return bf16_bits(a) | (bf16_bits(b) << 16); }
 __device__ __forceinline__ void unpack8(const uint4& v, float* o)
 {
     o[0] = __uint_as_float(v.x << 16);
@@ -56,7 +58,7 @@ __device__ __forceinline__ f32x4 mfma(const uint4& a, const uint4& b, f32x4 c)
 
 __device__ __forceinline__ void silu_d(float h, float& a, float& d1)
 {
-    const float sg = 1.0f / (1.0f + __expf(-h));
+    const float sg = __builtin_amdgcn_rcpf(1.0f + __expf(-h));
     a = h * sg;
     d1 = sg * (1.0f + h * (1.0f - sg));
 }
@@ -69,26 +71,29 @@ __device__ __forceinline__ void silu_dd(float h, float& a, float& d1, float& d2)
 }
 
 constexpr float kL2e = 1.44269504088896341f;   // log2(e)
-constexpr float kEm1 = 0.367879441171442322f;  // e^-1
 
-// phi_k(r) for k = 8c .. 8c + 7 from u_k = (r - mu_k) / s:
-//   phi_{k+1} = phi_k q_k,  q_k = exp(u_k - 1/2),  q_{k+1} = q_k / e.
-// Each chunk starts from two exponentials, so no chunk can underflow before
-// its values become representable; u is clamped to +-40, where every value of
-// the chunk is below 1e-100 and the products stay finite.
+// phi_k(r) = exp(-u_k^2 / 2), u_k = (r - mu_k) / s = u_0 - k, in chunks of 8:
+//   phi_{k0+e} = P_e C_e,  P_0 = exp(-u_c^2 / 2),  P_{e+1} = P_e exp(u_c),
+//   C_e = exp(-e^2 / 2),  u_c = u_0 - k0.
+// body(k, e, P_e) folds C_e into its multiply-add.  Each chunk restarts from
+// two exponentials, so a chunk cannot underflow before its values matter;
+// u_c is clamped to +-40, where the chunk's values are below 1e-100 and the
+// products stay finite (P_e <= exp(e^2 / 2) <= 4.4e10).
+constexpr float kGauss[8] = {1.0f, 0.60653066f, 0.135335283f, 0.0111089965f,
+                             0.000335462628f, 3.72665317e-06f, 1.52299797e-08f, 2.28973485e-11f};
+
 template <typename Body>
 __device__ __forceinline__ void rbf_chunks(float u0, Body&& body)
 {
 #pragma unroll
     for (int ch = 0; ch < kRbf / 8; ++ch) {
         const float uc = fminf(fmaxf(u0 - (float)(8 * ch), -40.f), 40.f);
-        float g = __builtin_amdgcn_exp2f(-0.5f * kL2e * uc * uc);
-        float q = __builtin_amdgcn_exp2f(kL2e * (uc - 0.5f));
+        float P = __builtin_amdgcn_exp2f(-0.5f * kL2e * uc * uc);
+        const float q = __builtin_amdgcn_exp2f(kL2e * uc);
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-            body(8 * ch + e, g);
-            g *= q;
-            q *= kEm1;
+            body(8 * ch + e, e, P);
+            P *= q;
         }
     }
 }
@@ -99,8 +104,9 @@ __device__ __forceinline__ const float* io_x(const ConfIO& io) { return io.ctl ?
 // ---------------------------------------------------------------------------
 // features (MODE 0) and their directional derivative along delta (MODE 1):
 //   MODE 1: v_i[t, k] = sum_j phi_k'(r_ij) (x_i - x_j) . (delta_i - delta_j) / r_ij
-// Block: floor(256 / n) configurations, one lane per (configuration, atom).
-// Output rows (c n + i) of 256 BF16 values.
+// Block: floor(256 / n) configurations, one lane per (configuration, atom),
+// atoms in the type-sorted order of Topo.  Output rows (c n + a) of 256 BF16
+// values for atom a.
 // ---------------------------------------------------------------------------
 template <int MODE>
 __global__ __launch_bounds__(256) void k_nn_feat(Topo tp, ConfIO io, const float* delta, uint16_t* out)
@@ -113,32 +119,47 @@ __global__ __launch_bounds__(256) void k_nn_feat(Topo tp, ConfIO io, const float
     const float* X = io_x(io);
     const int tid = threadIdx.x;
     const int rl = tid / n;
-    const int i = tid - rl * n;
+    const int i = tid - rl * n;          // sorted position of this lane's atom
     const bool on = rl < rpb;
     uint32_t ex0 = 0, ex1 = 0, ex2 = 0;
+    int atom = 0;
     if (on) {
         ex0 = tp.excl[i][0];
         ex1 = tp.excl[i][1];
         ex2 = tp.excl[i][2];
+        atom = tp.order[i];
     }
     const float inv_s = 1.0f / kSig;
     const float u_off = kMu0 / kSig;
     for (int64_t c0 = (int64_t)blockIdx.x * rpb; c0 < count; c0 += (int64_t)gridDim.x * rpb) {
         __syncthreads();
-        for (int q = tid; q < rpb * n * 3; q += 256) {
-            const int cl = q / (3 * n);
-            const int rem = q - cl * 3 * n;
-            const int a = rem / 3, comp = rem - 3 * a;
-            const int64_t c = c0 + cl;
-            float v = 0.f, dv = 0.f;
-            if (c < count) {
-                v = X[c * io.xs_conf + comp * io.xs_comp + a * io.xs_atom];
-                if constexpr (MODE == 1)
-                    dv = delta[(c * n + a) * 3 + comp];
+        {
+            // rpb n 3 <= 768: three loads per thread, all in flight at once
+            float v[3], dv[3];
+#pragma unroll
+            for (int it = 0; it < 3; ++it) {
+                const int q = tid + 256 * it;
+                const int cl = q / (3 * n);
+                const int rem = q - cl * 3 * n;
+                const int ps = rem / 3, comp = rem - 3 * ps;
+                const int64_t c = c0 + cl;
+                v[it] = dv[it] = 0.f;
+                if (q < rpb * n * 3 && c < count) {
+                    const int a = tp.order[ps];
+                    v[it] = X[c * io.xs_conf + comp * io.xs_comp + a * io.xs_atom];
+                    if constexpr (MODE == 1)
+                        dv[it] = delta[(c * n + a) * 3 + comp];
+                }
             }
-            sx[q] = v;
-            if constexpr (MODE == 1)
-                sd[q] = dv;
+#pragma unroll
+            for (int it = 0; it < 3; ++it) {
+                const int q = tid + 256 * it;
+                if (q < rpb * n * 3) {
+                    sx[q] = v[it];
+                    if constexpr (MODE == 1)
+                        sd[q] = dv[it];
+                }
+            }
         }
         __syncthreads();
         const int64_t c = c0 + rl;
@@ -153,29 +174,31 @@ __global__ __launch_bounds__(256) void k_nn_feat(Topo tp, ConfIO io, const float
             di1 = pd[3 * i + 1];
             di2 = pd[3 * i + 2];
         }
-        uint4* orow = reinterpret_cast<uint4*>(out + (size_t)(c * n + i) * kFeat);
+        uint4* orow = reinterpret_cast<uint4*>(out + (size_t)(c * n + atom) * kFeat);
         for (int t = 0; t < kTypes; ++t) {
             float acc[kRbf];
 #pragma unroll
             for (int k = 0; k < kRbf; ++k)
                 acc[k] = 0.f;
-            for (int p = tp.tstart[t]; p < tp.tstart[t + 1]; ++p) {
-                const int j = tp.order[p];
+#pragma unroll 2
+            for (int j = tp.tstart[t]; j < tp.tstart[t + 1]; ++j) {
                 const uint32_t word = j < 32 ? ex0 : (j < 64 ? ex1 : ex2);
                 const bool excluded = (word >> (j & 31)) & 1u;
                 const float dx = xi - px[3 * j], dy = yi - px[3 * j + 1], dz = zi - px[3 * j + 2];
                 const float r2 = dx * dx + dy * dy + dz * dz;
                 if constexpr (MODE == 0) {
-                    const float w = excluded ? 0.f : 1.f;
-                    const float u0 = __builtin_sqrtf(r2) * inv_s - u_off;
-                    rbf_chunks(u0, [&](int k, float phi) { acc[k] = fmaf(w, phi, acc[k]); });
+                    // an excluded pair is moved far outside the basis (all values 0)
+                    const float u0 = excluded ? 1e4f : __builtin_sqrtf(r2) * inv_s - u_off;
+                    rbf_chunks(u0, [&](int k, int e, float P) { acc[k] = fmaf(P, kGauss[e], acc[k]); });
                 } else {
                     const float rinv = excluded ? 0.f : __builtin_amdgcn_rsqf(r2);
                     const float w = (dx * (di0 - pd[3 * j]) + dy * (di1 - pd[3 * j + 1]) + dz * (di2 - pd[3 * j + 2])) *
                                     rinv;
                     const float u0 = r2 * rinv * inv_s - u_off;
                     const float cw = -w * inv_s;   // phi_k' = -(u_k / s) phi_k
-                    rbf_chunks(u0, [&](int k, float phi) { acc[k] = fmaf(phi, cw * (u0 - (float)k), acc[k]); });
+                    rbf_chunks(u0, [&](int k, int e, float P) {
+                        acc[k] = fmaf(P * kGauss[e], cw * (u0 - (float)k), acc[k]);
+                    });
                 }
             }
 #pragma unroll
@@ -201,13 +224,15 @@ constexpr int kTM = 64;
 constexpr int kLdX = kFeat + 8;
 constexpr int kLdH = kH + 8;
 
-__global__ __launch_bounds__(256) void k_nn_mlp(Weights w, const uint16_t* G, uint16_t* gG, float* e_out,
+__global__ __launch_bounds__(256, 3) void k_nn_mlp(Weights w, const uint16_t* G, uint16_t* gG, float* e_out,
                                                 const RunCtl* ctl, int64_t rows_fixed, int n)
 {
+    // Xs: G tile, then (dead after layer 1) g2, then the dE/dG output tile;
+    // Ys: a1, then g1.  52 KB in all: three workgroups per CU.
     __shared__ __align__(16) uint16_t Xs[kTM * kLdX];
     __shared__ __align__(16) uint16_t Ys[kTM * kLdH];
-    __shared__ __align__(16) uint16_t Zs[kTM * kLdH];
     __shared__ float es[4][kTM];
+    uint16_t* Zs = Xs;
     const int64_t M = ctl ? ctl->R_cur * (int64_t)n : rows_fixed;
     const int64_t row0 = (int64_t)blockIdx.x * kTM;
     if (row0 >= M)
@@ -215,12 +240,21 @@ __global__ __launch_bounds__(256) void k_nn_mlp(Weights w, const uint16_t* G, ui
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63, l16 = lane & 15, g4 = lane >> 4;
 
-    for (int q = tid; q < kTM * 32; q += 256) {
-        const int r = q >> 5, ch = q & 31;
-        uint4 v = {0u, 0u, 0u, 0u};
-        if (row0 + r < M)
-            v = *reinterpret_cast<const uint4*>(G + (size_t)(row0 + r) * kFeat + ch * 8);
-        *reinterpret_cast<uint4*>(Xs + r * kLdX + ch * 8) = v;
+    {
+        // all eight 16-byte loads of this thread in flight before the first LDS store
+        uint4 v[kTM * 32 / 256];
+#pragma unroll
+        for (int it = 0; it < kTM * 32 / 256; ++it) {
+            const int q = tid + 256 * it, r = q >> 5, ch = q & 31;
+            v[it] = uint4{0u, 0u, 0u, 0u};
+            if (row0 + r < M)
+                v[it] = *reinterpret_cast<const uint4*>(G + (size_t)(row0 + r) * kFeat + ch * 8);
+        }
+#pragma unroll
+        for (int it = 0; it < kTM * 32 / 256; ++it) {
+            const int q = tid + 256 * it, r = q >> 5, ch = q & 31;
+            *reinterpret_cast<uint4*>(Xs + r * kLdX + ch * 8) = v[it];
+        }
     }
     __syncthreads();
 
@@ -233,7 +267,7 @@ __global__ __launch_bounds__(256) void k_nn_mlp(Weights w, const uint16_t* G, ui
 #pragma unroll
             for (int ct = 0; ct < 2; ++ct)
                 acc[rt][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 2
+#pragma unroll
         for (int ks = 0; ks < kFeat / 32; ++ks) {
             uint4 b[2];
 #pragma unroll
@@ -422,24 +456,37 @@ __global__ __launch_bounds__(256) void k_nn_force(Topo tp, ConfIO io, const uint
     const float* X = io_x(io);
     const int tid = threadIdx.x;
     const int rl = tid / n;
-    const int i = tid - rl * n;
+    const int i = tid - rl * n;          // sorted position of this lane's atom
     const bool on = rl < rpb;
     uint32_t ex0 = 0, ex1 = 0, ex2 = 0;
+    int atom = 0;
     if (on) {
         ex0 = tp.excl[i][0];
         ex1 = tp.excl[i][1];
         ex2 = tp.excl[i][2];
+        atom = tp.order[i];
     }
     const float inv_s = 1.0f / kSig;
     const float u_off = kMu0 / kSig;
     for (int64_t c0 = (int64_t)blockIdx.x * rpb; c0 < count; c0 += (int64_t)gridDim.x * rpb) {
         __syncthreads();
-        for (int q = tid; q < rpb * n * 3; q += 256) {
-            const int cl = q / (3 * n);
-            const int rem = q - cl * 3 * n;
-            const int a = rem / 3, comp = rem - 3 * a;
-            const int64_t c = c0 + cl;
-            sx[q] = (c < count) ? X[c * io.xs_conf + comp * io.xs_comp + a * io.xs_atom] : 0.f;
+        {
+            float v[3];
+#pragma unroll
+            for (int it = 0; it < 3; ++it) {
+                const int q = tid + 256 * it;
+                const int cl = q / (3 * n);
+                const int rem = q - cl * 3 * n;
+                const int ps = rem / 3, comp = rem - 3 * ps;
+                const int64_t c = c0 + cl;
+                v[it] = (q < rpb * n * 3 && c < count)
+                            ? X[c * io.xs_conf + comp * io.xs_comp + tp.order[ps] * io.xs_atom]
+                            : 0.f;
+            }
+#pragma unroll
+            for (int it = 0; it < 3; ++it)
+                if (tid + 256 * it < rpb * n * 3)
+                    sx[tid + 256 * it] = v[it];
         }
         __syncthreads();
         const int64_t c = c0 + rl;
@@ -450,24 +497,48 @@ __global__ __launch_bounds__(256) void k_nn_force(Topo tp, ConfIO io, const uint
             xi = px[3 * i];
             yi = px[3 * i + 1];
             zi = px[3 * i + 2];
-            const uint4* grow = reinterpret_cast<const uint4*>(gG + (size_t)(c * n + i) * kFeat);
+            const uint4* grow = reinterpret_cast<const uint4*>(gG + (size_t)(c * n + atom) * kFeat);
             float* Ai = A + (rl * n + i) * n;
+            // the 64-byte segment of the next type is loaded while this one is used
+            uint4 nxt[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                nxt[q] = grow[q];
             for (int t = 0; t < kTypes; ++t) {
-                if (tp.tstart[t] == tp.tstart[t + 1])
-                    continue;
-                float gg[kRbf];
+                uint4 cur[4];
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
-                    unpack8(grow[4 * t + q], gg + 8 * q);
-                for (int p = tp.tstart[t]; p < tp.tstart[t + 1]; ++p) {
-                    const int j = tp.order[p];
+                    cur[q] = nxt[q];
+                if (t + 1 < kTypes) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        nxt[q] = grow[4 * (t + 1) + q];
+                }
+                if (tp.tstart[t] == tp.tstart[t + 1])
+                    continue;
+                // c0[k] = dE/dG[t, k] C_e, c1[k] = k c0[k]:
+                //   dE_i/dr_ij = -(1/s) sum_k dE/dG[t, k] phi_k (u_0 - k) = -(1/s) (u_0 S0 - S1)
+                float c0[kRbf], c1[kRbf];
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    unpack8(cur[q], c0 + 8 * q);
+#pragma unroll
+                for (int k = 0; k < kRbf; ++k) {
+                    c0[k] *= kGauss[k & 7];
+                    c1[k] = c0[k] * (float)k;
+                }
+#pragma unroll 2
+                for (int j = tp.tstart[t]; j < tp.tstart[t + 1]; ++j) {
                     const uint32_t word = j < 32 ? ex0 : (j < 64 ? ex1 : ex2);
                     const bool excluded = (word >> (j & 31)) & 1u;
                     const float dx = xi - px[3 * j], dy = yi - px[3 * j + 1], dz = zi - px[3 * j + 2];
-                    const float u0 = __builtin_sqrtf(dx * dx + dy * dy + dz * dz) * inv_s - u_off;
-                    float S = 0.f;
-                    rbf_chunks(u0, [&](int k, float phi) { S = fmaf(phi * gg[k], u0 - (float)k, S); });
-                    Ai[j] = excluded ? 0.f : -inv_s * S;
+                    const float u0 = excluded ? 1e4f : __builtin_sqrtf(dx * dx + dy * dy + dz * dz) * inv_s - u_off;
+                    float S0 = 0.f, S1 = 0.f;
+                    rbf_chunks(u0, [&](int k, int e, float P) {
+                        S0 = fmaf(P, c0[k], S0);
+                        S1 = fmaf(P, c1[k], S1);
+                    });
+                    Ai[j] = excluded ? 0.f : -inv_s * (u0 * S0 - S1);
                 }
             }
         }
@@ -486,12 +557,12 @@ __global__ __launch_bounds__(256) void k_nn_force(Topo tp, ConfIO io, const uint
                 fy -= g * dy;
                 fz -= g * dz;
             }
-            float* f = io.fout + c * io.fs_conf + i * io.fs_atom;
+            float* f = io.fout + c * io.fs_conf + atom * io.fs_atom;
             f[0] = fx;
             f[io.fs_comp] = fy;
             f[2 * io.fs_comp] = fz;
             if (E_out)
-                eacc = e_row[c * n + i];
+                eacc = e_row[c * n + atom];
         }
         if (E_out) {
             es[tid] = eacc;

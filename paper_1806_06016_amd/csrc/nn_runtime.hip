@@ -102,6 +102,7 @@ pamd_status pamd_nn_create(const pamd_system* sys, const int32_t* atom_type, pam
         adj[sys->bond_idx[2 * b]].push_back(sys->bond_idx[2 * b + 1]);
         adj[sys->bond_idx[2 * b + 1]].push_back(sys->bond_idx[2 * b]);
     }
+    std::vector<std::vector<char>> excl(n, std::vector<char>(n, 0));
     for (int i = 0; i < n; ++i) {
         std::vector<int> dist(n, -1);
         std::vector<int> q{i};
@@ -114,8 +115,12 @@ pamd_status pamd_nn_create(const pamd_system* sys, const int32_t* atom_type, pam
                 }
         for (int j = 0; j < n; ++j)
             if (dist[j] >= 0 && dist[j] <= 2)
-                tp.excl[i][j >> 5] |= 1u << (j & 31);
+                excl[i][j] = 1;
     }
+    for (int p = 0; p < n; ++p)
+        for (int q = 0; q < n; ++q)
+            if (excl[order[p]][order[q]])
+                tp.excl[p][q >> 5] |= 1u << (q & 31);
     // device parameters (zero) and BF16 copies
     hipError_t e = hipMalloc(&nn->params, sizeof(float) * 4 * kParams);
     if (e == hipSuccess)

@@ -611,7 +611,7 @@ pamd_status pamd_md_steps(pamd_ctx* c, int32_t n_steps, void* stream)
     if (n_steps < 0)
         return fail(c, PAMD_ERR_ARG, "n_steps < 0");
     hipStream_t s = as_stream(stream);
-    if (c->nn) {
+    if (c->nn && n_steps > 0) {
         if (n_steps % c->mts_ratio != 0)
             return fail(c, PAMD_ERR_ARG, "n_steps must be a multiple of the r-RESPA outer ratio");
         for (auto& run : c->runs) {

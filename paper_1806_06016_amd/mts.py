@@ -1,0 +1,223 @@
+"""Training and evaluation of the learned r-RESPA surrogate, all on the GPU
+through the C ABI (argument marshalling and bookkeeping only here).
+
+    python -m paper_1806_06016_amd.mts [--quick]
+
+1. Training data: a population of the 75-atom peptide annealed from 700 K to
+   300 K over 41 geometric temperatures (resampling as in the main path),
+   snapshots of every replica every theta/4 MD steps: positions and exact
+   nonbonded forces (pamd_export_configs).
+2. Training: force-matching loss, Adam with a cosine-decayed step size,
+   random batches of 256 configurations, 10 % held out.
+3. Evaluation at equal physical time, NVE from a 300 K population: energy
+   drift (RMS of E_tot(t) - E_tot(0) over replicas and samples) and
+   throughput (replica time steps of dt per second and simulated time per
+   second) for plain velocity Verlet at dt = 1 and 2 fs, r-RESPA with the
+   trained surrogate (inner 1 fs, outer 2 and 4 fs) and r-RESPA with a zero
+   surrogate (the whole nonbonded force in the outer impulse).
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+from typing import Dict, Optional
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+from paper_1806_06016_amd import pamd as B  # noqa: E402
+from pamd_inputs import systems as S  # noqa: E402
+from pamd_inputs.weights import surrogate_weights  # noqa: E402
+
+
+def geometric(T0: float, T1: float, n: int):
+    return [T0 * (T1 / T0) ** (i / (n - 1)) for i in range(n)]
+
+
+def collect(sysd, R: int, temps, theta: int, snaps_per_T: int, seed: int, dt: float = 0.001):
+    """Annealed population snapshots -> (x, F_nb) CUDA float32 [n_conf, n, 3]."""
+    import torch
+    p = B.Pamd([sysd], R_target=R, T0=temps[0], dt=dt, nu=1.0, seed=seed, precision=B.PAMD_FP32)
+    p.md_steps(theta)
+    xs, fs = [], []
+    for i, T in enumerate(temps):
+        if i > 0:
+            p.resample([T])
+        for _ in range(snaps_per_T):
+            p.md_steps(theta // snaps_per_T)
+            x, f = p.export_configs(0, 0, None)
+            xs.append(x)
+            fs.append(f)
+    state = p.get_state(0)
+    p.close()
+    torch.cuda.synchronize()
+    return torch.cat(xs), torch.cat(fs), state
+
+
+def train(nn, x, f, steps: int, batch: int = 256, lr0: float = 1e-3, seed: int = 0, val_frac: float = 0.1):
+    import torch
+    n = x.shape[0]
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    perm = torch.randperm(n, generator=g, device="cuda")
+    nv = max(1, int(val_frac * n))
+    vi, ti = perm[:nv], perm[nv:]
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    hist = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for it in range(steps):
+        lr = 0.5 * lr0 * (1.0 + math.cos(math.pi * it / steps))
+        idx = ti[torch.randint(0, ti.numel(), (batch,), generator=g, device="cuda")]
+        nn.train_step(x[idx].contiguous(), f[idx].contiguous(), max(lr, 1e-7), loss)
+        if it % max(1, steps // 20) == 0 or it == steps - 1:
+            hist.append((it, float(loss.item())))
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+
+    def mean_loss(ids):
+        s, m = 0.0, 0
+        for c0 in range(0, ids.numel(), 4096):
+            c = ids[c0:c0 + 4096]
+            lv, _ = nn.loss_grad(x[c].contiguous(), f[c].contiguous(), want_grad=False)
+            s += float(lv.item()) * c.numel()
+            m += c.numel()
+        return s / m
+
+    val = mean_loss(vi)
+    f2 = float((f[vi] ** 2).mean().item())
+    return dict(train_seconds=el, steps=steps, batch=batch, history=hist, val_loss=val,
+                val_rel_force_rms=math.sqrt(val / f2), n_train=int(ti.numel()), n_val=int(nv))
+
+
+def nve_run(sysd, x0, v0, dt: float, nn=None, M: int = 1, window_ps: float = 10.0, sample_ps: float = 0.1,
+            seed: int = 7) -> Dict:
+    """NVE (nu = 0) from (x0, v0): drift of E_tot and wall time of the MD."""
+    import torch
+    R = x0.shape[0]
+    p = B.Pamd([sysd], R_target=R, T0=300.0, dt=dt, nu=0.0, seed=seed, precision=B.PAMD_FP32)
+    p.set_state(0, x0, v0, T=300.0)
+    if nn is not None:
+        p.set_mts(nn, M)
+    p.md_steps(0)
+    st = p.get_state(0)
+    E0 = st["E_pot"] + st["E_kin"]
+    n_sample = int(round(window_ps / sample_ps))
+    k = int(round(sample_ps / dt))
+    if nn is not None:
+        k = max(M, k // M * M)
+    dev = []
+    s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ms = 0.0
+    unstable = False
+    for _ in range(n_sample):
+        s0.record(p.stream)
+        p.md_steps(k)
+        s1.record(p.stream)
+        try:
+            st = p.get_state(0)
+        except B.PamdError as e:
+            if e.code != B.PAMD_ERR_NONFINITE:
+                raise
+            unstable = True          # some replica's energy became non-finite
+            break
+        ms += s0.elapsed_time(s1)
+        E = st["E_pot"] + st["E_kin"]
+        dev.append(E - E0)
+    done = len(dev) * k
+    out = dict(dt_fs=dt * 1000.0, outer_fs=(M * dt * 1000.0 if nn is not None else dt * 1000.0),
+               replicas=R, steps=done, md_ms=ms, unstable=unstable)
+    if unstable or not dev:
+        out["rms_drift_kJmol"] = float("inf")
+    else:
+        out["rms_drift_kJmol"] = float(np.sqrt(np.mean(np.array(dev) ** 2)))
+    if done > 0 and ms > 0:
+        out["replica_steps_per_s"] = R * done / (ms / 1000.0)
+        out["replica_ps_per_s"] = out["replica_steps_per_s"] * dt
+    p.close()
+    return out
+
+
+def throughput(sysd, x0, v0, dt: float, nn=None, M: int = 1, R: int = 100000, steps: int = 400) -> Dict:
+    """Replica time steps per second at population size R (inputs resident)."""
+    import torch
+    rep = int(math.ceil(R / x0.shape[0]))
+    x = np.concatenate([x0] * rep)[:R]
+    v = np.concatenate([v0] * rep)[:R]
+    p = B.Pamd([sysd], R_target=R, T0=300.0, dt=dt, nu=1.0, seed=3, precision=B.PAMD_FP32)
+    p.set_state(0, x, v, T=300.0)
+    if nn is not None:
+        p.set_mts(nn, M)
+    p.md_steps(steps // 4 // max(M, 1) * max(M, 1) or max(M, 1))
+    torch.cuda.synchronize()
+    s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s0.record(p.stream)
+    p.md_steps(steps)
+    s1.record(p.stream)
+    s1.synchronize()
+    ms = s0.elapsed_time(s1)
+    p.close()
+    return dict(R=R, steps=steps, ms=ms, replica_steps_per_s=R * steps / (ms / 1000.0),
+                replica_ps_per_s=R * steps * dt / (ms / 1000.0))
+
+
+def main(argv=None):
+    import torch
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--quick", action="store_true", help="small data / training / windows")
+    ap.add_argument("--replicas", type=int, default=10000, help="population of the data collection")
+    ap.add_argument("--train-steps", type=int, default=20000)
+    ap.add_argument("--window-ps", type=float, default=10.0)
+    ap.add_argument("--save", default="", help="write the trained parameters (.npy)")
+    a = ap.parse_args(argv)
+    if a.quick:
+        a.replicas, a.train_steps, a.window_ps = 1000, 300, 1.0
+    B.load_library()
+    sysd = S.c2_system()
+    temps = geometric(700.0, 300.0, 41)
+    t0 = time.perf_counter()
+    x, f, st = collect(sysd, a.replicas, temps, 1000, 4, seed=11)
+    t_collect = time.perf_counter() - t0
+    print(f"collected {x.shape[0]} configurations in {t_collect:.1f} s", flush=True)
+    nn = B.PamdNN(sysd, sysd.atype)
+    nn.set_weights(surrogate_weights(2024, 0.5))
+    tr = train(nn, x, f, a.train_steps)
+    print(f"trained: val relative force RMS {tr['val_rel_force_rms']:.3f} in {tr['train_seconds']:.1f} s",
+          flush=True)
+    if a.save:
+        np.save(a.save, B.pack_params(nn.get_weights()))
+    del x, f
+    torch.cuda.empty_cache()
+    # NVE starts: 256 replicas of the final 300 K population
+    R0 = 256
+    x0, v0 = st["x"][:R0], st["v"][:R0]
+    zero = B.PamdNN(sysd, sysd.atype)
+    cases = [("vv_1fs", 0.001, None, 1), ("vv_2fs", 0.002, None, 1),
+             ("respa_nn_2fs", 0.001, nn, 2), ("respa_nn_4fs", 0.001, nn, 4),
+             ("respa_zero_2fs", 0.001, zero, 2), ("respa_zero_4fs", 0.001, zero, 4)]
+    res = {}
+    for name, dt, net, M in cases:
+        d = nve_run(sysd, x0, v0, dt, net, M, window_ps=a.window_ps)
+        thr = throughput(sysd, x0, v0, dt, net, M, R=20000 if a.quick else 100000)
+        d["throughput"] = thr
+        res[name] = d
+        print(name, json.dumps({k: v for k, v in d.items() if k != "throughput"}),
+              "throughput", json.dumps(thr), flush=True)
+    line = dict(metric="replica_ps_per_s", data="synthetic", config=dict(workload="peptide75 MTS surrogate",
+                collect_replicas=a.replicas, temperatures=41), training=tr, cases=res,
+                collect_seconds=t_collect)
+    print(json.dumps(line))
+    nn.close()
+    zero.close()
+
+
+if __name__ == "__main__":
+    main()
