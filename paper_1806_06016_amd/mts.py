@@ -169,15 +169,54 @@ def throughput(sysd, x0, v0, dt: float, nn=None, M: int = 1, R: int = 100000, st
                 replica_ps_per_s=R * steps * dt / (ms / 1000.0))
 
 
+def kernel_timing(R: int, reps: int = 5) -> Dict:
+    """Surrogate inference on R perturbed peptide configurations and training
+    steps on batches of 256 (seeded weights): the workload of the kernel
+    profiles."""
+    import torch
+    sysd = S.c2_system()
+    nn = B.PamdNN(sysd, sysd.atype)
+    nn.set_weights(surrogate_weights(3))
+    rng = np.random.default_rng(1)
+    x = torch.tensor(sysd.x_init[None] + rng.normal(0, 0.01, (R,) + sysd.x_init.shape), dtype=torch.float32,
+                     device="cuda")
+    for _ in range(2):
+        E, F = nn.forces(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        E, F = nn.forces(x)
+    torch.cuda.synchronize()
+    fwd = (time.perf_counter() - t0) / reps
+    xb, fb = x[:256].contiguous(), (1.1 * F[:256]).contiguous()
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    for _ in range(5):
+        nn.train_step(xb, fb, 1e-4, loss)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(20):
+        nn.train_step(xb, fb, 1e-4, loss)
+    torch.cuda.synchronize()
+    tr = (time.perf_counter() - t0) / 20
+    nn.close()
+    return dict(R=R, forces_ms=fwd * 1e3, ns_per_replica=fwd * 1e9 / R, train_step_ms_batch256=tr * 1e3)
+
+
 def main(argv=None):
     import torch
     ap = argparse.ArgumentParser()
+    ap.add_argument("--kernels", type=int, default=0, metavar="R",
+                    help="only time surrogate inference on R configurations and training steps")
     ap.add_argument("--quick", action="store_true", help="small data / training / windows")
     ap.add_argument("--replicas", type=int, default=10000, help="population of the data collection")
     ap.add_argument("--train-steps", type=int, default=20000)
     ap.add_argument("--window-ps", type=float, default=10.0)
     ap.add_argument("--save", default="", help="write the trained parameters (.npy)")
     a = ap.parse_args(argv)
+    if a.kernels > 0:
+        B.load_library()
+        print(json.dumps(kernel_timing(a.kernels)))
+        return
     if a.quick:
         a.replicas, a.train_steps, a.window_ps = 1000, 300, 1.0
     B.load_library()
