@@ -60,7 +60,11 @@ enum {
 enum { PAMD_FP64 = 0, PAMD_FP32 = 1 };
 enum { PAMD_DIELECTRIC_VACUUM = 0, PAMD_DIELECTRIC_4R = 1 };
 
-#define PAMD_MAX_ATOMS 80    /* 16-lane tiles of atoms held in registers: N <= 5 x 16 */
+#define PAMD_MAX_ATOMS 320   /* FP32; FP64 runs take at most 32 atoms */
+#define PAMD_TILE_ATOMS 80   /* contexts whose molecules all have at most this many atoms use the
+                                register-tile MD kernel (one replica per 16 lanes, run by run);
+                                a context holding a larger molecule runs every run in one
+                                persistent launch with one replica per wavefront */
 #define PAMD_FORCE_CHUNK 256 /* replicas per pamd_get_forces call */
 
 /*

@@ -254,11 +254,13 @@ __device__ __forceinline__ void add3(real* frc, int a, real fx, real fy, real fz
     }
 }
 
-template <typename real, bool ENERGY>
+// W: lanes per pass (16 in the register-tile layout, 64 in the wide layout);
+// the host packs the records in passes of W
+template <typename real, bool ENERGY, int W = kRow>
 __device__ __forceinline__ void bonded_terms(const RunDev<real>& d, const real* pos, real* frc, int l16, double& eacc)
 {
     // bonds: U = 1/2 k (r - r0)^2
-    for (int t0 = 0; t0 < d.nb; t0 += kRow) {
+    for (int t0 = 0; t0 < d.nb; t0 += W) {
         const int t = t0 + l16;
         const int4 ix = d.bidx[t];
         if (ix.x >= 0) {
@@ -280,7 +282,7 @@ __device__ __forceinline__ void bonded_terms(const RunDev<real>& d, const real* 
         }
     }
     // angles: U = 1/2 k (theta - theta0)^2, theta = atan2(|u x w|, u.w)
-    for (int t0 = 0; t0 < d.na; t0 += kRow) {
+    for (int t0 = 0; t0 < d.na; t0 += W) {
         const int t = t0 + l16;
         const int4 ix = d.aidx[t];
         if (ix.x >= 0) {
@@ -320,7 +322,7 @@ __device__ __forceinline__ void bonded_terms(const RunDev<real>& d, const real* 
         }
     }
     // dihedrals: U = k (1 + cos(n phi - delta)) = k + kc cos(n phi), kc = k cos(delta), delta in {0, pi}
-    for (int t0 = 0; t0 < d.nd; t0 += kRow) {
+    for (int t0 = 0; t0 < d.nd; t0 += W) {
         const int t = t0 + l16;
         const int4 ix = d.didx[t];
         if (ix.x >= 0) {
@@ -920,6 +922,334 @@ __global__ __launch_bounds__(1024) void k_export(RunDev<float> d, int64_t r0, in
 }
 
 // ---------------------------------------------------------------------------
+// wide layout: one replica per wavefront (molecules up to 320 atoms, and every
+// run of a context that holds one).  Atom a lives on lane a % 64, slot a / 64.
+// All-pairs nonbonded forces without Newton's third law: lane i walks every
+// partner j (position from the wave's LDS stage, parameters from the run's
+// per-atom table, exclusion / 1-4 bits 32 partners at a time), so no lane
+// ever writes another lane's force; the pair energy is halved.
+// ---------------------------------------------------------------------------
+struct WideRegs {
+    float x[kWideSlots], y[kWideSlots], z[kWideSlots];
+    float vx[kWideSlots], vy[kWideSlots], vz[kWideSlots];
+    float fx[kWideSlots], fy[kWideSlots], fz[kWideSlots];
+    float sg[kWideSlots], se[kWideSlots], qs[kWideSlots];   // own atoms' pair parameters
+};
+
+template <int DIEL, bool ENERGY>
+__device__ __forceinline__ void wide_evaluate(WideRegs& r, const RunDev<float>& d, float* pos, float* frc, int lane,
+                                              int nsl, double& eacc)
+{
+    const int n = d.n;
+    if constexpr (!ENERGY) {
+#pragma unroll
+        for (int s = 0; s < kWideSlots; ++s) {
+            r.fx[s] = 0.f;
+            r.fy[s] = 0.f;
+            r.fz[s] = 0.f;
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < kWideSlots; ++s) {
+        const int a = kWide * s + lane;
+        if (s < nsl && a < n) {
+            pos[3 * a] = r.x[s];
+            pos[3 * a + 1] = r.y[s];
+            pos[3 * a + 2] = r.z[s];
+        }
+    }
+    wave_sync();
+    bonded_terms<float, ENERGY, kWide>(d, pos, frc, lane, eacc);
+    const float s14lj = d.s14lj, s14c = d.s14c;
+    for (int c = 0; c < d.nchunk; ++c) {
+        uint32_t ex[kWideSlots], s4[kWideSlots];
+#pragma unroll
+        for (int s = 0; s < kWideSlots; ++s) {
+            const int a = kWide * s + lane;
+            ex[s] = ~0u;
+            s4[s] = 0u;
+            if (s < nsl && a < n) {
+                const uint2 m = d.pmask[(size_t)a * d.nchunk + c];
+                ex[s] = m.x;
+                s4[s] = m.y;
+            }
+        }
+        const int j1 = (32 * c + 32 < n) ? 32 * c + 32 : n;
+        for (int j = 32 * c; j < j1; ++j) {
+            const float xj = pos[3 * j], yj = pos[3 * j + 1], zj = pos[3 * j + 2];
+            const float4 pj = d.apar4[j];
+            const uint32_t bit = 1u << (j & 31);
+#pragma unroll
+            for (int s = 0; s < kWideSlots; ++s) {
+                if (s < nsl) {
+                    const float dx = r.x[s] - xj, dy = r.y[s] - yj, dz = r.z[s] - zj;
+                    const float r2 = dx * dx + dy * dy + dz * dz;
+                    const float ir2 = rcp_(r2);
+                    const float sig = r.sg[s] + pj.x;
+                    const float t = sig * sig * ir2;
+                    const float t3 = t * t * t;
+                    const float e4 = r.se[s] * pj.y;      // 4 eps_ij
+                    const float C = r.qs[s] * pj.z;       // Coulomb factor of the pair
+                    const bool is14 = (s4[s] & bit) != 0u;
+                    const float slj = is14 ? s14lj : 1.f;
+                    const float sc = is14 ? s14c : 1.f;
+                    const bool skip = (ex[s] & bit) != 0u;
+                    if constexpr (ENERGY) {
+                        const float ulj = e4 * t3 * (t3 - 1.f);
+                        const float uc = (DIEL == 1) ? 0.5f * C * ir2 : C * rsq_(r2);
+                        const float u = slj * ulj + sc * uc;
+                        eacc += skip ? 0.0 : 0.5 * (double)u;
+                    } else {
+                        // force on i = g (x_i - x_j)
+                        const float flj = e4 * t3 * (12.f * t3 - 6.f) * ir2;
+                        const float fc = (DIEL == 1) ? C * ir2 * ir2 : C * ir2 * rsq_(r2);
+                        float g = slj * flj + sc * fc;
+                        g = skip ? 0.f : g;
+                        r.fx[s] += g * dx;
+                        r.fy[s] += g * dy;
+                        r.fz[s] += g * dz;
+                    }
+                }
+            }
+        }
+    }
+    if constexpr (!ENERGY) {
+        wave_sync();
+#pragma unroll
+        for (int s = 0; s < kWideSlots; ++s) {
+            const int a = kWide * s + lane;
+            if (s < nsl && a < n) {
+                r.fx[s] += frc[3 * a];
+                r.fy[s] += frc[3 * a + 1];
+                r.fz[s] += frc[3 * a + 2];
+                frc[3 * a] = 0.f;
+                frc[3 * a + 1] = 0.f;
+                frc[3 * a + 2] = 0.f;
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1)
+        v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ void wide_load(WideRegs& r, const RunDev<float>& d, const float* slab, int lane, int nsl)
+{
+    const int npad = kWide * nsl;
+#pragma unroll
+    for (int s = 0; s < kWideSlots; ++s) {
+        const int a = kWide * s + lane;
+        if (s < nsl && a < d.n) {
+            r.x[s] = slab[a];
+            r.y[s] = slab[npad + a];
+            r.z[s] = slab[2 * npad + a];
+            r.vx[s] = slab[3 * npad + a];
+            r.vy[s] = slab[4 * npad + a];
+            r.vz[s] = slab[5 * npad + a];
+            const float4 p = d.apar4[a];
+            r.sg[s] = p.x;
+            r.se[s] = p.y;
+            r.qs[s] = p.z;
+        } else {
+            // padding atoms: fixed, far apart, every pair excluded by the masks
+            r.x[s] = (float)(1000 + 10 * a);
+            r.y[s] = 1000.f;
+            r.z[s] = 1000.f;
+            r.vx[s] = r.vy[s] = r.vz[s] = 0.f;
+            r.sg[s] = r.se[s] = r.qs[s] = 0.f;
+        }
+    }
+}
+
+__device__ __forceinline__ void wide_store(const WideRegs& r, const RunDev<float>& d, float* slab, int lane, int nsl)
+{
+    const int npad = kWide * nsl;
+#pragma unroll
+    for (int s = 0; s < kWideSlots; ++s) {
+        const int a = kWide * s + lane;
+        if (s < nsl && a < d.n) {
+            slab[a] = r.x[s];
+            slab[npad + a] = r.y[s];
+            slab[2 * npad + a] = r.z[s];
+            slab[3 * npad + a] = r.vx[s];
+            slab[4 * npad + a] = r.vy[s];
+            slab[5 * npad + a] = r.vz[s];
+        }
+    }
+}
+
+// Persistent MD of every run of the context in one launch: a device counter
+// hands out (run, replica) items, runs in decreasing order of pair work
+// (`order`), replicas of a run in slot order.  n_steps velocity-Verlet steps
+// with Andersen collisions, then E_pot (FP64 sum) and E_kin of the final state.
+template <int DIEL>
+__global__ __launch_bounds__(512) void k_md_wide(const RunDev<float>* runs, const int32_t* order, int n_runs,
+                                                  int32_t* counter, int nmax, int n_steps)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    float* pos = reinterpret_cast<float*>(smem) + (size_t)wave * 6 * nmax;
+    float* frc = pos + 3 * nmax;
+    for (int i = lane; i < 3 * nmax; i += kWide)
+        frc[i] = 0.f;
+    for (;;) {
+        int g = 0;
+        if (lane == 0)
+            g = atomicAdd(counter, 1);
+        g = __builtin_amdgcn_readfirstlane(g);
+        int k = -1;
+        int64_t rep = g;
+        for (int q = 0; q < n_runs; ++q) {
+            const int run = order[q];
+            const int64_t R = runs[run].ctl->R_cur;
+            if (rep < R) {
+                k = run;
+                break;
+            }
+            rep -= R;
+        }
+        k = __builtin_amdgcn_readfirstlane(k);
+        if (k < 0)
+            break;
+        const RunDev<float>& d = runs[k];
+        const int nsl = (d.n + kWide - 1) / kWide;
+        const int npad = kWide * nsl;
+        const RunCtl* ctl = d.ctl;
+        const int cur = ctl->cur;
+        const uint32_t step0 = ctl->step;
+        const float kT = (float)(d.kB * ctl->T_cur);
+        const float dt = (float)d.dt;
+        const float two_over_dt = (float)(2.0 / d.dt);
+        float* slab = d.slab[cur] + (size_t)rep * 6 * npad;
+        float hdtm[kWideSlots];
+#pragma unroll
+        for (int s = 0; s < kWideSlots; ++s) {
+            const int a = kWide * s + lane;
+            hdtm[s] = (s < nsl && a < d.n) ? (float)(0.5 * d.dt / d.mass[a]) : 0.f;
+        }
+        WideRegs r;
+        wide_load(r, d, slab, lane, nsl);
+        double unused = 0.0;
+        for (int st = 0; st <= n_steps; ++st) {
+            wide_evaluate<DIEL, false>(r, d, pos, frc, lane, nsl, unused);
+            if (st > 0) {
+#pragma unroll
+                for (int s = 0; s < kWideSlots; ++s) {
+                    r.vx[s] += hdtm[s] * r.fx[s];
+                    r.vy[s] += hdtm[s] * r.fy[s];
+                    r.vz[s] += hdtm[s] * r.fz[s];
+                }
+                if (d.p24 != 0u) {
+                    const uint32_t gstep = step0 + (uint32_t)(st - 1);
+#pragma unroll
+                    for (int s = 0; s < kWideSlots; ++s) {
+                        const int a = kWide * s + lane;
+                        if (s < nsl && a < d.n) {
+                            const u32x4 w = philox10((uint32_t)rep, gstep, (uint32_t)((a & 15) + 16 * (a >> 6)),
+                                                     kStreamCollide, d.key0, d.key1);
+                            const int q = (a >> 4) & 3;
+                            const uint32_t wq = q == 0 ? w.v[0] : q == 1 ? w.v[1] : q == 2 ? w.v[2] : w.v[3];
+                            if ((wq >> 8) < d.p24) {
+                                const u32x4 wv = philox10((uint32_t)rep, gstep, (uint32_t)a, kStreamVelocity, d.key0,
+                                                          d.key1);
+                                float zz[3];
+                                normals3(wv, zz);
+                                const float sd = sqrt_(kT * hdtm[s] * two_over_dt);
+                                r.vx[s] = sd * zz[0];
+                                r.vy[s] = sd * zz[1];
+                                r.vz[s] = sd * zz[2];
+                            }
+                        }
+                    }
+                }
+            }
+            if (st < n_steps) {
+#pragma unroll
+                for (int s = 0; s < kWideSlots; ++s) {
+                    r.vx[s] += hdtm[s] * r.fx[s];
+                    r.vy[s] += hdtm[s] * r.fy[s];
+                    r.vz[s] += hdtm[s] * r.fz[s];
+                    r.x[s] += dt * r.vx[s];
+                    r.y[s] += dt * r.vy[s];
+                    r.z[s] += dt * r.vz[s];
+                }
+            }
+        }
+        double ep = 0.0, ek = 0.0;
+        wide_evaluate<DIEL, true>(r, d, pos, frc, lane, nsl, ep);
+#pragma unroll
+        for (int s = 0; s < kWideSlots; ++s) {
+            const int a = kWide * s + lane;
+            if (s < nsl && a < d.n) {
+                const double vx = r.vx[s], vy = r.vy[s], vz = r.vz[s];
+                ek += 0.5 * d.mass[a] * (vx * vx + vy * vy + vz * vz);
+            }
+        }
+        ep = wave_sum(ep);
+        ek = wave_sum(ek);
+        wide_store(r, d, slab, lane, nsl);
+        if (lane == 0) {
+            d.epot[cur][rep] = ep;
+            d.ekin[rep] = ek;
+            if (!isfinite(ep))
+                atomicCAS(&d.ctl->error, 0, 4);
+        }
+    }
+}
+
+// reset of the batch work counter and every run's step counter after k_md_wide
+__global__ void k_wide_finalize(RunDev<float>* runs, int n_runs, int32_t* counter, int n_steps)
+{
+    if (threadIdx.x != 0)
+        return;
+    *counter = 0;
+    for (int q = 0; q < n_runs; ++q) {
+        runs[q].ctl->step += (uint32_t)n_steps;
+        runs[q].ctl->work = 0;
+    }
+}
+
+// forces and energies of replicas [r0, r0 + count) of one wide-layout run
+template <int DIEL>
+__global__ __launch_bounds__(512) void k_forces_wide(RunDev<float> d, int64_t r0, int count, int nmax)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    float* pos = reinterpret_cast<float*>(smem) + (size_t)wave * 6 * nmax;
+    float* frc = pos + 3 * nmax;
+    for (int i = lane; i < 3 * nmax; i += kWide)
+        frc[i] = 0.f;
+    const int k = blockIdx.x * (blockDim.x >> 6) + wave;
+    if (k >= count)
+        return;
+    const int nsl = (d.n + kWide - 1) / kWide;
+    const float* slab = d.slab[d.ctl->cur] + (size_t)(r0 + k) * 6 * kWide * nsl;
+    WideRegs r;
+    wide_load(r, d, slab, lane, nsl);
+    double unused = 0.0, ep = 0.0;
+    wide_evaluate<DIEL, false>(r, d, pos, frc, lane, nsl, unused);
+    wide_evaluate<DIEL, true>(r, d, pos, frc, lane, nsl, ep);
+    ep = wave_sum(ep);
+    double* o = d.dbg + (size_t)k * d.npad * 4;
+#pragma unroll
+    for (int s = 0; s < kWideSlots; ++s) {
+        const int a = kWide * s + lane;
+        if (s < nsl && a < d.n) {
+            o[4 * a] = (double)r.fx[s];
+            o[4 * a + 1] = (double)r.fy[s];
+            o[4 * a + 2] = (double)r.fz[s];
+        }
+    }
+    if (lane == 0)
+        o[3] = ep;
+}
+
+// ---------------------------------------------------------------------------
 // host-side dispatch
 // ---------------------------------------------------------------------------
 template <typename real>
@@ -1073,6 +1403,50 @@ hipError_t launch_export(const RunDev<float>& d, int64_t r0, int64_t count, floa
     PAMD_DISPATCH(float, d.nslot, d.dielectric, CALL)
 #undef CALL
 }
+size_t wide_lds_bytes(int nmax, int waves) { return (size_t)waves * 6 * nmax * sizeof(float); }
+
+hipError_t wide_setup(int diel, int nmax, int waves, int* blocks_per_cu)
+{
+    const size_t lds = wide_lds_bytes(nmax, waves);
+    const void* md = diel ? (const void*)k_md_wide<1> : (const void*)k_md_wide<0>;
+    const void* fo = diel ? (const void*)k_forces_wide<1> : (const void*)k_forces_wide<0>;
+    for (const void* f : {md, fo}) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, md, waves * 64, lds);
+}
+
+hipError_t launch_md_wide(const RunDev<float>* runs, const int32_t* order, int n_runs, int32_t* counter, int nmax,
+                          int n_steps, int diel, int blocks, int waves, hipStream_t s)
+{
+    const size_t lds = wide_lds_bytes(nmax, waves);
+    if (diel)
+        hipLaunchKernelGGL(k_md_wide<1>, dim3(blocks), dim3(waves * 64), lds, s, runs, order, n_runs, counter, nmax,
+                           n_steps);
+    else
+        hipLaunchKernelGGL(k_md_wide<0>, dim3(blocks), dim3(waves * 64), lds, s, runs, order, n_runs, counter, nmax,
+                           n_steps);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_wide_finalize, dim3(1), dim3(64), 0, s, const_cast<RunDev<float>*>(runs), n_runs, counter,
+                       n_steps);
+    return hipGetLastError();
+}
+
+hipError_t launch_forces_wide(const RunDev<float>& d, int64_t r0, int count, int nmax, int waves, hipStream_t s)
+{
+    const size_t lds = wide_lds_bytes(nmax, waves);
+    const int blocks = (count + waves - 1) / waves;
+    if (d.dielectric)
+        hipLaunchKernelGGL(k_forces_wide<1>, dim3(blocks), dim3(waves * 64), lds, s, d, r0, count, nmax);
+    else
+        hipLaunchKernelGGL(k_forces_wide<0>, dim3(blocks), dim3(waves * 64), lds, s, d, r0, count, nmax);
+    return hipGetLastError();
+}
+
 hipError_t md_occupancy(int precision_fp32, int nslot, int diel, int n, int waves, int* blocks_per_cu)
 {
     if (precision_fp32) {

@@ -10,6 +10,11 @@ constexpr int kRowsPerWave = 4;     // replicas per wave64
 constexpr int kMaxSlots = 5;        // 16-atom blocks held in registers (N <= 80)
 constexpr int kWaveSize = 64;
 constexpr int kMaxSched = 4096;  // temperatures a device schedule can hold
+// wide layout (molecules of up to 320 atoms, and every run of a context that
+// holds one): one replica per wavefront, atom a on lane a % 64, slot a / 64
+constexpr int kWide = 64;
+constexpr int kWideSlots = 5;
+constexpr int kWideMaxAtoms = kWide * kWideSlots;
 
 // Number of tile steps of the all-pairs schedule for `nslot` blocks of 16 atoms:
 // each diagonal block takes 8 row rotations (k = 1..8, k = 8 half-masked),
@@ -79,6 +84,14 @@ struct RunDev {
     uint32_t key0, key1;    // Philox key
     int32_t dielectric;
     int32_t waves_per_block;
+    // wide layout only: per-atom (sigma / 2, 2 sqrt(eps), q sqrt(k_e c), 0) with
+    // c = 1/2 for eps = 4r and 1 in vacuum, and per (atom, 32-atom chunk) the
+    // bit masks (excluded pair incl. self, scaled 1-4 pair)
+    const float4* apar4;    // [n]
+    const uint2* pmask;     // [n][nchunk]
+    int32_t nchunk;
+    int32_t wide;
+    float s14lj, s14c;
 };
 
 }  // namespace pamd

@@ -37,6 +37,11 @@ hipError_t launch_respa(const RunDev<float>& d, const float* fnn, int ops, uint3
                         uint32_t p24_outer, int blocks, int waves, hipStream_t s);
 hipError_t launch_export(const RunDev<float>& d, int64_t r0, int64_t count, float* xo, float* fo, int waves,
                          hipStream_t s);
+size_t wide_lds_bytes(int nmax, int waves);
+hipError_t wide_setup(int diel, int nmax, int waves, int* blocks_per_cu);
+hipError_t launch_md_wide(const RunDev<float>* runs, const int32_t* order, int n_runs, int32_t* counter, int nmax,
+                          int n_steps, int diel, int blocks, int waves, hipStream_t s);
+hipError_t launch_forces_wide(const RunDev<float>& d, int64_t r0, int count, int nmax, int waves, hipStream_t s);
 }  // namespace pamd
 
 using namespace pamd;
@@ -62,6 +67,9 @@ struct Carver {
 // host copies of the per-run tables (FP64; cast to the kernel precision on upload)
 struct HostTables {
     int n = 0, npad = 0, nslot = 0;
+    int wide = 0, nchunk = 0;
+    std::vector<double> atomp;           // wide layout: [n][4] per-atom pair parameters
+    std::vector<uint32_t> pmask;         // wide layout: [n][nchunk][2] exclusion / 1-4 bits
     std::vector<double> ab, c;           // [steps][16][2], [steps][16]
     std::vector<int32_t> bidx, aidx, didx;  // int4 records
     std::vector<double> bpar, apar, dpar;
@@ -94,6 +102,11 @@ struct pamd_ctx {
     size_t lds = 0;
     pamd_nn* nn = nullptr;   // learned surrogate of the r-RESPA inner force (null: plain MD)
     int mts_ratio = 0;       // inner steps per outer step
+    // wide layout: every run in one persistent k_md_wide launch
+    int wide = 0, nmax = 0, diel = 0;
+    RunDev<float>* d_runs = nullptr;   // device copies of the runs' descriptors
+    int32_t* d_order = nullptr;        // runs in decreasing pair work
+    int32_t* d_counter = nullptr;      // work-queue counter
 };
 
 namespace {
@@ -116,6 +129,18 @@ pamd_status fail(pamd_ctx* c, pamd_status st, const std::string& msg)
     } while (0)
 
 int nslot_of(int n) { return (n + kRow - 1) / kRow; }
+int npad_of(int n, int wide) { return wide ? (n + kWide - 1) / kWide * kWide : nslot_of(n) * kRow; }
+
+// the wide layout serves contexts with a molecule above the register-tile limit
+int wide_mode(const pamd_system* sys, int n_runs, int fp32)
+{
+    if (!fp32)
+        return 0;
+    for (int r = 0; r < n_runs; ++r)
+        if (sys[r].n_atoms > PAMD_TILE_ATOMS)
+            return 1;
+    return 0;
+}
 
 // graph distance (capped at 4) between every pair of atoms of the bond graph
 std::vector<int> graph_distance(int n, int nb, const int32_t* bidx)
@@ -147,6 +172,8 @@ pamd_status validate(pamd_ctx* c, const pamd_system& s, const pamd_params& p, in
 {
     if (s.n_atoms < 1 || s.n_atoms > PAMD_MAX_ATOMS)
         return fail(c, PAMD_ERR_ARG, "n_atoms must be in 1.." + std::to_string(PAMD_MAX_ATOMS));
+    if (!fp32 && s.n_atoms > PAMD_TILE_ATOMS)
+        return fail(c, PAMD_ERR_ARG, "molecules above " + std::to_string(PAMD_TILE_ATOMS) + " atoms need FP32");
     if (!fp32 && s.n_atoms > 2 * kRow)
         return fail(c, PAMD_ERR_ARG, "FP64 precision supports at most 32 atoms");
     if (!s.mass || !s.charge || !s.sigma || !s.epsilon || !s.x_init)
@@ -186,13 +213,13 @@ pamd_status validate(pamd_ctx* c, const pamd_system& s, const pamd_params& p, in
     return PAMD_OK;
 }
 
-// Pack terms of k atoms into passes of 16 lanes such that no two terms of a
+// Pack terms of k atoms into passes of W lanes such that no two terms of a
 // pass share an atom in the same role (position in the term); a term may be
 // stored reversed (a bond, angle or dihedral read backwards is the same
 // term).  Empty lanes get index -1.  Returns the packed records
 // (4 indices + 2 parameters per slot).
 void pack_terms(int count, int k, const int32_t* idx, const double* p0, const double* p1,
-                std::vector<int32_t>& rec, std::vector<double>& par)
+                std::vector<int32_t>& rec, std::vector<double>& par, int W)
 {
     std::vector<std::vector<std::vector<int>>> passes;   // pass -> terms -> atoms (oriented)
     std::vector<std::vector<int>> pass_term;
@@ -203,7 +230,7 @@ void pack_terms(int count, int k, const int32_t* idx, const double* p0, const do
         for (int o = 0; o < 2 && !placed; ++o) {
             const std::vector<int>& cand = o == 0 ? fwd : rev;
             for (size_t b = 0; b < passes.size() && !placed; ++b) {
-                if (passes[b].size() >= (size_t)kRow)
+                if (passes[b].size() >= (size_t)W)
                     continue;
                 bool ok = true;
                 for (const auto& other : passes[b])
@@ -221,12 +248,12 @@ void pack_terms(int count, int k, const int32_t* idx, const double* p0, const do
             pass_term.push_back({t});
         }
     }
-    const size_t slots = std::max<size_t>(1, passes.size()) * kRow;
+    const size_t slots = std::max<size_t>(1, passes.size()) * W;
     rec.assign(slots * 4, -1);
     par.assign(slots * 2, 0.0);
     for (size_t b = 0; b < passes.size(); ++b)
         for (size_t q = 0; q < passes[b].size(); ++q) {
-            const size_t sl = b * kRow + q;
+            const size_t sl = b * W + q;
             for (int r = 0; r < 4; ++r)
                 rec[sl * 4 + r] = r < k ? passes[b][q][r] : 0;
             par[sl * 2] = p0[pass_term[b][q]];
@@ -238,14 +265,16 @@ void pack_terms(int count, int k, const int32_t* idx, const double* p0, const do
 // the diagonal block (rotations k = 1..8; k = 8 only on lanes 0..7), then for
 // k = 0..15 the blocks I < J.  Lane l of step (I, J, k) pairs atom 16 I + l
 // with atom 16 J + ((l - k) mod 16).
-void build_tables(const pamd_system& s, HostTables& t)
+void build_tables(const pamd_system& s, HostTables& t, int wide)
 {
     const int n = s.n_atoms;
     t.n = n;
+    t.wide = wide;
     t.nslot = nslot_of(n);
-    t.npad = t.nslot * kRow;
+    t.npad = npad_of(n, wide);
     const std::vector<int> dist = graph_distance(n, s.n_bonds, s.bond_idx);
-    const int steps = tile_steps(t.nslot);
+    const int steps = wide ? 0 : tile_steps(t.nslot);
+    const int W = wide ? kWide : kRow;
     t.ab.assign((size_t)steps * 16 * 2, 0.0);
     t.c.assign((size_t)steps * 16, 0.0);
     auto coef = [&](int st, int l, int i, int j) {
@@ -266,7 +295,7 @@ void build_tables(const pamd_system& s, HostTables& t)
         t.c[(size_t)st * 16 + l] = (s.dielectric == PAMD_DIELECTRIC_4R) ? 2.0 * qq / 4.0 : qq;
     };
     int st = 0;
-    for (int J = 0; J < t.nslot; ++J) {
+    for (int J = 0; J < (wide ? 0 : t.nslot); ++J) {
         for (int k = 1; k <= 8; ++k, ++st)
             for (int l = 0; l < 16; ++l)
                 if (!(k == 8 && l >= 8))
@@ -276,14 +305,35 @@ void build_tables(const pamd_system& s, HostTables& t)
                 for (int l = 0; l < 16; ++l)
                     coef(st, l, 16 * I + l, 16 * J + ((l - k) & 15));
     }
-    pack_terms(s.n_bonds, 2, s.bond_idx, s.bond_k, s.bond_r0, t.bidx, t.bpar);
-    pack_terms(s.n_angles, 3, s.angle_idx, s.angle_k, s.angle_theta0, t.aidx, t.apar);
+    if (wide) {
+        // per-atom factors of the pair parameters: sigma_ij = sg_i + sg_j,
+        // 4 eps_ij = se_i se_j, Coulomb factor = qs_i qs_j
+        const double cf = (s.dielectric == PAMD_DIELECTRIC_4R) ? 0.5 : 1.0;
+        t.nchunk = (n + 31) / 32;
+        t.atomp.assign((size_t)n * 4, 0.0);
+        t.pmask.assign((size_t)n * t.nchunk * 2, 0u);
+        for (int i = 0; i < n; ++i) {
+            t.atomp[4 * i] = 0.5 * s.sigma[i];
+            t.atomp[4 * i + 1] = 2.0 * sqrt(s.epsilon[i]);
+            t.atomp[4 * i + 2] = s.charge[i] * sqrt(s.coulomb_k * cf);
+            for (int j = 0; j < n; ++j) {
+                const int g = dist[(size_t)i * n + j];
+                const size_t w = ((size_t)i * t.nchunk + j / 32) * 2;
+                if (i == j || g <= 2)
+                    t.pmask[w] |= 1u << (j & 31);
+                else if (g == 3)
+                    t.pmask[w + 1] |= 1u << (j & 31);
+            }
+        }
+    }
+    pack_terms(s.n_bonds, 2, s.bond_idx, s.bond_k, s.bond_r0, t.bidx, t.bpar, W);
+    pack_terms(s.n_angles, 3, s.angle_idx, s.angle_k, s.angle_theta0, t.aidx, t.apar, W);
     std::vector<double> kc(s.n_dihedrals), nm(s.n_dihedrals);
     for (int q = 0; q < s.n_dihedrals; ++q) {
         kc[q] = s.dih_k[q] * (cos(s.dih_delta[q]) > 0 ? 1.0 : -1.0);   // k cos(delta), delta in {0, pi}
         nm[q] = (double)s.dih_n[q];
     }
-    pack_terms(s.n_dihedrals, 4, s.dih_idx, kc.data(), nm.data(), t.didx, t.dpar);
+    pack_terms(s.n_dihedrals, 4, s.dih_idx, kc.data(), nm.data(), t.didx, t.dpar, W);
     t.mass.assign(t.npad, 0.0);
     t.mtot = 0;
     for (int a = 0; a < n; ++a) {
@@ -294,13 +344,15 @@ void build_tables(const pamd_system& s, HostTables& t)
 }
 
 template <typename real>
-void carve(Carver& st, Carver& wk, const pamd_system& s, const pamd_params& p, int run, RunDev<real>& d)
+void carve(Carver& st, Carver& wk, const pamd_system& s, const pamd_params& p, int run, RunDev<real>& d, int wide)
 {
     const int n = s.n_atoms;
     const int nslot = nslot_of(n);
-    const int npad = nslot * kRow;
+    const int npad = npad_of(n, wide);
     const int64_t Rc = p.R_cap;
-    const int steps = tile_steps(nslot);
+    const int steps = wide ? 0 : tile_steps(nslot);
+    const int W = wide ? kWide : kRow;
+    const int nchunk = (n + 31) / 32;
     for (int b = 0; b < 2; ++b)
         d.slab[b] = st.take<real>((size_t)Rc * 6 * npad);
     for (int b = 0; b < 2; ++b)
@@ -314,15 +366,15 @@ void carve(Carver& st, Carver& wk, const pamd_system& s, const pamd_params& p, i
     d.fam = wk.take<uint8_t>(p.R_target);
     d.nb_ab = wk.take<real>((size_t)steps * 32);
     d.nb_c = wk.take<real>((size_t)steps * 16);
-    // packed term slots (passes of 16 lanes)
+    // packed term slots (passes of W lanes)
     std::vector<int32_t> rec;
     std::vector<double> par;
     std::vector<double> zeros(std::max({s.n_bonds, s.n_angles, s.n_dihedrals, 1}), 0.0);
-    pack_terms(s.n_bonds, 2, s.bond_idx, zeros.data(), zeros.data(), rec, par);
+    pack_terms(s.n_bonds, 2, s.bond_idx, zeros.data(), zeros.data(), rec, par, W);
     const int nb_slots = (int)(rec.size() / 4);
-    pack_terms(s.n_angles, 3, s.angle_idx, zeros.data(), zeros.data(), rec, par);
+    pack_terms(s.n_angles, 3, s.angle_idx, zeros.data(), zeros.data(), rec, par, W);
     const int na_slots = (int)(rec.size() / 4);
-    pack_terms(s.n_dihedrals, 4, s.dih_idx, zeros.data(), zeros.data(), rec, par);
+    pack_terms(s.n_dihedrals, 4, s.dih_idx, zeros.data(), zeros.data(), rec, par, W);
     const int nd_slots = (int)(rec.size() / 4);
     d.bidx = wk.take<int4>(nb_slots);
     d.bpar = wk.take<real>((size_t)nb_slots * 2);
@@ -354,6 +406,12 @@ void carve(Carver& st, Carver& wk, const pamd_system& s, const pamd_params& p, i
     d.key0 = (uint32_t)(p.seed & 0xFFFFFFFFu);
     d.key1 = (uint32_t)(p.seed >> 32) + (uint32_t)run;
     d.dielectric = s.dielectric;
+    d.wide = wide;
+    d.nchunk = wide ? nchunk : 0;
+    d.apar4 = wide ? wk.take<float4>(n) : nullptr;
+    d.pmask = wide ? wk.take<uint2>((size_t)n * nchunk) : nullptr;
+    d.s14lj = (float)s.scale14_lj;
+    d.s14c = (float)s.scale14_coul;
 }
 
 template <typename real>
@@ -379,8 +437,18 @@ hipError_t upload(const RunDev<real>& d, const HostTables& t, hipStream_t s)
         return hipStreamSynchronize(s);
     };
     hipError_t e;
-    if ((e = up(d.nb_ab, t.ab)) != hipSuccess) return e;
-    if ((e = up(d.nb_c, t.c)) != hipSuccess) return e;
+    if (!t.ab.empty() && (e = up(d.nb_ab, t.ab)) != hipSuccess) return e;
+    if (!t.c.empty() && (e = up(d.nb_c, t.c)) != hipSuccess) return e;
+    if (t.wide) {
+        std::vector<float> ap(t.atomp.begin(), t.atomp.end());
+        if ((e = hipMemcpyAsync((void*)d.apar4, ap.data(), ap.size() * sizeof(float), hipMemcpyHostToDevice, s)) !=
+            hipSuccess)
+            return e;
+        if ((e = hipMemcpyAsync((void*)d.pmask, t.pmask.data(), t.pmask.size() * sizeof(uint32_t),
+                                hipMemcpyHostToDevice, s)) != hipSuccess)
+            return e;
+        if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+    }
     if ((e = upi(d.bidx, t.bidx)) != hipSuccess) return e;
     if ((e = up(d.bpar, t.bpar)) != hipSuccess) return e;
     if ((e = upi(d.aidx, t.aidx)) != hipSuccess) return e;
@@ -393,20 +461,34 @@ hipError_t upload(const RunDev<real>& d, const HostTables& t, hipStream_t s)
 }
 
 pamd_status layout(const pamd_system* sys, int32_t n_runs, const pamd_params* p, void* d_state, void* d_work,
-                   std::vector<Run>* runs, size_t* sb, size_t* wb)
+                   std::vector<Run>* runs, size_t* sb, size_t* wb, pamd_ctx* c)
 {
     Carver st(d_state), wk(d_work);
+    const int fp32 = p[0].precision == PAMD_FP32;
+    const int wide = wide_mode(sys, n_runs, fp32);
     for (int r = 0; r < n_runs; ++r) {
-        if (p[0].precision == PAMD_FP32) {
+        if (fp32) {
             RunDev<float> d{};
-            carve<float>(st, wk, sys[r], p[r], r, d);
+            carve<float>(st, wk, sys[r], p[r], r, d, wide);
             if (runs)
                 (*runs)[r].f = d;
         } else {
             RunDev<double> d{};
-            carve<double>(st, wk, sys[r], p[r], r, d);
+            carve<double>(st, wk, sys[r], p[r], r, d, 0);
             if (runs)
                 (*runs)[r].d = d;
+        }
+    }
+    if (wide) {
+        // descriptors, run order and work counter of the batched launch
+        RunDev<float>* dr = wk.take<RunDev<float>>(n_runs);
+        int32_t* order = wk.take<int32_t>(n_runs);
+        int32_t* counter = wk.take<int32_t>(1);
+        if (c) {
+            c->wide = 1;
+            c->d_runs = dr;
+            c->d_order = order;
+            c->d_counter = counter;
         }
     }
     *sb = (st.off + kAlign - 1) / kAlign * kAlign;
@@ -467,7 +549,7 @@ pamd_status pamd_query_sizes(const pamd_system* sys, int32_t n_runs, const pamd_
         if (st != PAMD_OK)
             return st;
     }
-    return layout(sys, n_runs, p, nullptr, nullptr, nullptr, state_bytes, work_bytes);
+    return layout(sys, n_runs, p, nullptr, nullptr, nullptr, state_bytes, work_bytes, nullptr);
 }
 
 template <typename real>
@@ -475,10 +557,24 @@ static pamd_status init_runs(pamd_ctx* c, const pamd_system* sys, hipStream_t s)
 {
     for (int r = 0; r < c->n_runs; ++r) {
         Run& run = c->runs[r];
-        build_tables(sys[r], run.tab);
+        build_tables(sys[r], run.tab, c->wide);
         run.mtot = run.tab.mtot;
         HIPCHK(c, upload<real>(dev<real>(run), run.tab, s));
         HIPCHK(c, launch_init(dev<real>(run), s));
+    }
+    if (c->wide) {
+        // the batched launch's descriptors and its largest-first run order
+        std::vector<RunDev<float>> rd(c->n_runs);
+        std::vector<int32_t> order(c->n_runs);
+        for (int r = 0; r < c->n_runs; ++r) {
+            rd[r] = c->runs[r].f;
+            order[r] = r;
+        }
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int a, int b) { return sys[a].n_atoms > sys[b].n_atoms; });
+        HIPCHK(c, hipMemcpyAsync(c->d_runs, rd.data(), rd.size() * sizeof(RunDev<float>), hipMemcpyHostToDevice, s));
+        HIPCHK(c, hipMemcpyAsync(c->d_order, order.data(), order.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        HIPCHK(c, hipMemsetAsync(c->d_counter, 0, sizeof(int32_t), s));
     }
     HIPCHK(c, hipStreamSynchronize(s));
     return PAMD_OK;
@@ -505,7 +601,7 @@ pamd_status pamd_init(const pamd_system* sys, int32_t n_runs, const pamd_params*
     c->n_runs = n_runs;
     c->fp32 = p[0].precision == PAMD_FP32;
     c->runs.resize(n_runs);
-    layout(sys, n_runs, p, d_state, d_work, &c->runs, &sb, &wb);
+    layout(sys, n_runs, p, d_state, d_work, &c->runs, &sb, &wb, c);
     hipStream_t s = as_stream(stream);
 
     int dev_id = 0;
@@ -522,16 +618,31 @@ pamd_status pamd_init(const pamd_system* sys, int32_t n_runs, const pamd_params*
         ns_max = std::max(ns_max, nslot_of(sys[r].n_atoms));
     }
     int waves = p[0].waves_per_block;
-    if (waves == 0) {
-        waves = 16;
-        while (waves > 1 && md_lds(c->fp32, ns_max, n_max, waves) > (size_t)max_lds)
-            --waves;
-    }
-    c->lds = md_lds(c->fp32, ns_max, n_max, waves);
-    if (c->lds > (size_t)max_lds)
-        return fail(c, PAMD_ERR_ARG, "system too large for the LDS of one workgroup");
     int bpc = 0;
-    HIPCHK(c, md_occupancy(c->fp32, ns_max, sys[0].dielectric, n_max, waves, &bpc));
+    c->nmax = n_max;
+    c->diel = sys[0].dielectric;
+    if (c->wide) {
+        // one replica per wavefront; at most 8 waves (512 threads) per workgroup
+        for (int r = 1; r < n_runs; ++r)
+            if (sys[r].dielectric != sys[0].dielectric)
+                return fail(c, PAMD_ERR_ARG, "runs of one batched launch must share the dielectric model");
+        if (waves == 0 || waves > 8)
+            waves = 8;
+        while (waves > 1 && wide_lds_bytes(n_max, waves) > (size_t)max_lds)
+            --waves;
+        c->lds = wide_lds_bytes(n_max, waves);
+        HIPCHK(c, wide_setup(c->diel, n_max, waves, &bpc));
+    } else {
+        if (waves == 0) {
+            waves = 16;
+            while (waves > 1 && md_lds(c->fp32, ns_max, n_max, waves) > (size_t)max_lds)
+                --waves;
+        }
+        c->lds = md_lds(c->fp32, ns_max, n_max, waves);
+        if (c->lds > (size_t)max_lds)
+            return fail(c, PAMD_ERR_ARG, "system too large for the LDS of one workgroup");
+        HIPCHK(c, md_occupancy(c->fp32, ns_max, sys[0].dielectric, n_max, waves, &bpc));
+    }
     if (bpc < 1)
         return fail(c, PAMD_ERR_ARG, "MD kernel cannot be resident with this launch shape");
     c->waves = waves;
@@ -611,6 +722,11 @@ pamd_status pamd_md_steps(pamd_ctx* c, int32_t n_steps, void* stream)
     if (n_steps < 0)
         return fail(c, PAMD_ERR_ARG, "n_steps < 0");
     hipStream_t s = as_stream(stream);
+    if (c->wide) {
+        HIPCHK(c, launch_md_wide(c->d_runs, c->d_order, c->n_runs, c->d_counter, c->nmax, n_steps, c->diel, c->blocks,
+                                 c->waves, s));
+        return PAMD_OK;
+    }
     if (c->nn && n_steps > 0) {
         if (n_steps % c->mts_ratio != 0)
             return fail(c, PAMD_ERR_ARG, "n_steps must be a multiple of the r-RESPA outer ratio");
@@ -694,7 +810,14 @@ static pamd_status get_forces_t(pamd_ctx* c, Run& run, int64_t r0, int32_t count
     if (r0 < 0 || count < 1 || count > PAMD_FORCE_CHUNK || r0 + count > ctl.R_cur)
         return fail(c, PAMD_ERR_ARG, "replica range outside the population or chunk");
     RunDev<real>& d = dev<real>(run);
-    HIPCHK(c, launch_forces(d, r0, count, c->waves, s));
+    if constexpr (sizeof(real) == 4) {
+        if (c->wide)
+            HIPCHK(c, launch_forces_wide(d, r0, count, c->nmax, c->waves, s));
+        else
+            HIPCHK(c, launch_forces(d, r0, count, c->waves, s));
+    } else {
+        HIPCHK(c, launch_forces(d, r0, count, c->waves, s));
+    }
     std::vector<double> buf((size_t)count * d.npad * 4);
     HIPCHK(c, hipMemcpyAsync(buf.data(), d.dbg, buf.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
@@ -970,8 +1093,9 @@ pamd_status pamd_export_configs(pamd_ctx* c, int32_t run, int64_t r0, int64_t co
     pamd_status st = check_ctx(c);
     if (st != PAMD_OK)
         return st;
-    if (!c->fp32)
-        return fail(c, PAMD_ERR_ARG, "configuration export needs an FP32 context");
+    if (!c->fp32 || c->wide)
+        return fail(c, PAMD_ERR_ARG, "configuration export needs an FP32 context of molecules up to " +
+                                         std::to_string(PAMD_TILE_ATOMS) + " atoms");
     if (run < 0 || run >= c->n_runs)
         return fail(c, PAMD_ERR_ARG, "run index out of range");
     const RunDev<float>& d = c->runs[run].f;
@@ -998,8 +1122,9 @@ pamd_status pamd_set_mts(pamd_ctx* c, pamd_nn* nn, int32_t outer_ratio, void* st
         c->mts_ratio = 0;
         return PAMD_OK;
     }
-    if (!c->fp32)
-        return fail(c, PAMD_ERR_ARG, "r-RESPA with the surrogate needs an FP32 context");
+    if (!c->fp32 || c->wide)
+        return fail(c, PAMD_ERR_ARG, "r-RESPA with the surrogate needs an FP32 context of molecules up to " +
+                                         std::to_string(PAMD_TILE_ATOMS) + " atoms");
     if (outer_ratio < 1)
         return fail(c, PAMD_ERR_ARG, "outer_ratio must be >= 1");
     for (auto& run : c->runs)

@@ -18,7 +18,8 @@ LIB_PATH = os.path.join(_HERE, "libpamd.so")
 PAMD_OK, PAMD_ERR_ARG, PAMD_ERR_HIP, PAMD_ERR_CAPACITY, PAMD_ERR_NONFINITE, PAMD_ERR_STATE = range(6)
 PAMD_FP64, PAMD_FP32 = 0, 1
 PAMD_FORCE_CHUNK = 256
-MAX_ATOMS = 80
+MAX_ATOMS = 320
+TILE_ATOMS = 80
 
 
 class PamdError(RuntimeError):

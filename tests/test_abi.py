@@ -80,9 +80,18 @@ def test_query_sizes_is_host_only_and_validates():
     sb2 = B.make_system_struct(bad, keep)
     assert lib.pamd_query_sizes(ctypes.byref(sb2), 1, ctypes.byref(p), ctypes.byref(sb),
                                 ctypes.byref(wb)) == B.PAMD_ERR_ARG
-    big = S.make_peptide(1806, 120)            # more atoms than the register tiles hold
+    big = S.make_peptide(1806, 120)            # above the register tiles: wide layout, 128-atom slabs
     s3 = B.make_system_struct(big, keep)
     assert lib.pamd_query_sizes(ctypes.byref(s3), 1, ctypes.byref(p), ctypes.byref(sb),
+                                ctypes.byref(wb)) == 0
+    assert sb.value >= 2 * 1100 * 6 * 128 * 4
+    p.precision = 0                            # FP64 is limited to 32 atoms
+    assert lib.pamd_query_sizes(ctypes.byref(s3), 1, ctypes.byref(p), ctypes.byref(sb),
+                                ctypes.byref(wb)) == B.PAMD_ERR_ARG
+    p.precision = 1
+    s4 = B.make_system_struct(S.make_peptide(7, 300), keep)
+    s4.n_atoms = B.MAX_ATOMS + 1               # beyond the wide layout
+    assert lib.pamd_query_sizes(ctypes.byref(s4), 1, ctypes.byref(p), ctypes.byref(sb),
                                 ctypes.byref(wb)) == B.PAMD_ERR_ARG
 
 

@@ -1,0 +1,169 @@
+"""GPU: the wide layout (one replica per wavefront) and the batched launch of
+several uneven runs, against the FP64 oracle, through the C ABI.
+
+A context holding a molecule above the register-tile limit runs every run in
+one persistent launch (items handed out largest molecule first).  Same
+tolerances as the register-tile parity tests: per-atom forces within
+1e-4 (|F_a| + F_rms), energies within 1e-5 of sum |terms|, positions within
+1e-4 nm after 100 NVT steps with identical Philox streams, copy numbers
+bit-exact.
+"""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle import oracle as O  # noqa: E402
+from pamd_inputs import systems as S  # noqa: E402
+
+SIZES = (40, 120, 300)
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1806_06016_amd import pamd
+    pamd.load_library()
+    return pamd
+
+
+def _systems():
+    return [S.make_peptide(seed=1806 + k, n_atoms=n) for k, n in enumerate(SIZES)]
+
+
+def _perturbed(sysd, R, scale, seed):
+    rng = np.random.default_rng(seed)
+    return np.ascontiguousarray(sysd.x_init[None] + rng.normal(0, scale, size=(R,) + sysd.x_init.shape))
+
+
+def test_batched_context_uses_the_wide_layout(B):
+    p = B.Pamd(_systems(), R_target=13, T0=700.0, dt=0.001, nu=1.0, seed=3, precision=B.PAMD_FP32)
+    info = p.launch_info()
+    print("launch", info)
+    assert 1 <= info["waves_per_block"] <= 8
+    p.close()
+
+
+def test_wide_forces_and_energies(B):
+    syss = _systems()
+    R = 13
+    print("wide forces", SIZES, flush=True)
+    p = B.Pamd(syss, R_target=R, T0=700.0, dt=0.001, nu=1.0, seed=3, precision=B.PAMD_FP32)
+    for r, sysd in enumerate(syss):
+        x = _perturbed(sysd, R, 0.01, 5 + r)
+        p.set_state(r, x, np.zeros_like(x), T=700.0)
+        F, E = p.get_forces(r)
+        osys = O.OracleSystem(sysd)
+        st = p.get_state(r)
+        Eo, Fo, terms = O.energy_forces(osys, st["x"], want_terms=True)
+        frms = np.sqrt((Fo ** 2).sum(-1).mean(-1))[:, None]
+        ratio = (np.linalg.norm(F - Fo, axis=-1) / (1e-4 * (np.linalg.norm(Fo, axis=-1) + frms))).max()
+        print(f"n={sysd.n_atoms}: force error / bound {ratio:.3f}")
+        assert ratio <= 1.0
+        assert np.all(np.abs(E - Eo) <= 1e-5 * np.abs(terms).sum(1))
+    p.close()
+
+
+def test_wide_trajectories_match_oracle(B):
+    """All runs advance in one launch; each matches its own oracle run
+    (Philox key seed_hi + run)."""
+    syss = _systems()
+    R, T, nu, seed, n_steps = 11, 700.0, 1.0, 77, 100
+    print("wide trajectories", SIZES, flush=True)
+    p = B.Pamd(syss, R_target=R, T0=T, dt=0.001, nu=nu, seed=seed, precision=B.PAMD_FP32)
+    starts = []
+    for r, sysd in enumerate(syss):
+        osys = O.OracleSystem(sysd)
+        x = _perturbed(sysd, R, 0.003, 8 + r)
+        v = O.init_velocities(osys, R, T, seed=3 + r)
+        p.set_state(r, x, v, T=T, step=500)
+        st = p.get_state(r)
+        starts.append((st["x"].copy(), st["v"].copy()))
+    p.md_steps(n_steps)
+    for r, sysd in enumerate(syss):
+        osys = O.OracleSystem(sysd)
+        xo, vo = starts[r]
+        Ep, Ek, col = O.md_steps(osys, xo, vo, n_steps, T, 0.001, nu, seed, step0=500, run=r, want_collisions=True)
+        g = p.get_state(r)
+        err = np.abs(g["x"] - xo).max()
+        print(f"n={sysd.n_atoms}: max |dx| {err:.2e}, collisions {int(col.sum())}")
+        assert col.sum() > 0
+        assert err < 1e-4
+        assert g["step"] == 500 + n_steps
+        assert np.abs(g["E_pot"] - Ep).max() <= 1e-3 * np.abs(Ep).mean()
+        assert np.allclose(g["E_kin"], Ek, rtol=1e-3)
+    p.close()
+
+
+def test_batched_anneal_matches_oracle_per_run(B):
+    """Two temperature steps of every run: per-run resampling (counts bit-exact,
+    ancestors) and MD in the shared launch."""
+    syss = _systems()
+    R, seed, theta = 64, 31, 40
+    temps = [700.0, 690.0, 680.0]
+    print("batched anneal", SIZES, flush=True)
+    p = B.Pamd(syss, R_target=R, T0=temps[0], dt=0.001, nu=1.0, seed=seed, precision=B.PAMD_FP32)
+    p.md_steps(theta)
+    ora = []
+    for r, sysd in enumerate(syss):
+        osys = O.OracleSystem(sysd)
+        x = np.ascontiguousarray(np.broadcast_to(sysd.x_init, (R, sysd.n_atoms, 3)).astype(np.float64))
+        v = O.init_velocities(osys, R, temps[0], seed, run=r)
+        Ep, Ek = O.md_steps(osys, x, v, theta, temps[0], 0.001, 1.0, seed, 0, run=r)
+        assert np.abs(p.get_state(r)["x"] - x).max() < 1e-4
+        ora.append([osys, x, v, Ep, np.arange(R)])
+    step = theta
+    for i in (1, 2):
+        p.resample([temps[i]] * len(syss))
+        p.md_steps(theta)
+        for r, sysd in enumerate(syss):
+            osys, x, v, Ep, anc = ora[r]
+            kB = sysd.kB
+            db = 1 / (kB * temps[i]) - 1 / (kB * temps[i - 1])
+            u = O.resample_uniforms(len(Ep), i, seed, run=r)
+            c, _ = O.copy_counts(Ep, db, R, u)
+            assert (p.get_counts(r) == c).all()
+            x, v, Ep, anc = O.gather(c, [x, v, Ep, anc])
+            x = np.ascontiguousarray(O.recentre(x, osys.mass))
+            v = np.ascontiguousarray(v * math.sqrt(temps[i] / temps[i - 1]))
+            Ep, Ek = O.md_steps(osys, x, v, theta, temps[i], 0.001, 1.0, seed, step, run=r)
+            g = p.get_state(r)
+            assert (g["ancestor"] == anc).all()
+            err = np.abs(g["x"] - x).max()
+            print(f"n={sysd.n_atoms} temperature step {i}: max |dx| {err:.2e}")
+            assert err < 2e-4
+            ora[r] = [osys, x, v, Ep, anc]
+        step += theta
+    p.close()
+
+
+def test_batched_graph_replay_is_identical(B):
+    syss = _systems()
+    R = 48
+
+    def run(use_graph):
+        p = B.Pamd(syss, R_target=R, T0=700.0, dt=0.001, nu=1.0, seed=9, precision=B.PAMD_FP32,
+                   T_final=600.0)
+        p.md_steps(20)
+        if use_graph:
+            p.graph_capture(20, mode="adaptive", slot=0, parts="both")
+            for _ in range(3):
+                p.graph_launch(0)
+        else:
+            for _ in range(3):
+                p.resample(None)
+                p.md_steps(20)
+        out = [p.get_state(r) for r in range(len(syss))]
+        obs = p.observables()
+        p.close()
+        return out, obs
+
+    a, oa = run(False)
+    b, ob = run(True)
+    for r in range(len(syss)):
+        assert np.array_equal(a[r]["x"], b[r]["x"])
+        assert oa[r]["T"] == ob[r]["T"] and oa[r]["sum_lnQ"] == ob[r]["sum_lnQ"]
