@@ -49,9 +49,10 @@ def test_batched_context_uses_the_wide_layout(B):
 
 
 def test_wide_forces_and_energies(B):
-    syss = _systems()
+    """Every molecule size of the batched workload (40 ... 300 atoms), batched."""
+    syss = S.c4_systems()
     R = 13
-    print("wide forces", SIZES, flush=True)
+    print("wide forces", S.C4_SIZES, flush=True)
     p = B.Pamd(syss, R_target=R, T0=700.0, dt=0.001, nu=1.0, seed=3, precision=B.PAMD_FP32)
     for r, sysd in enumerate(syss):
         x = _perturbed(sysd, R, 0.01, 5 + r)
