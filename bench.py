@@ -38,11 +38,11 @@ def algorithmic_flops_per_replica_step(sysd) -> float:
         + 18.0 * n, pairs
 
 
-def measured_traffic():
+def measured_traffic(name: str = "k_md_traffic.txt"):
     """HBM bytes per MD-kernel launch from the committed rocprofv3 counter
     summary, or None when the kernel source changed since it was taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_md_traffic.txt")
+    path = os.path.join(ROOT, "profiles", name)
     src = os.path.join(ROOT, "paper_1806_06016_amd", "csrc", "md_kernel.hip")
     try:
         kv = {}
@@ -176,7 +176,9 @@ def batched(args):
         "md_kernel_ms_avg": md_s / args.steps * 1e3,
         "launch": info,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_VALU_TFLOPS, "traffic": None},
+                     "frac": achieved / PEAK_FP32_VALU_TFLOPS,
+                     "traffic": measured_traffic("k_md_wide_traffic.txt") if R == 4096 and args.theta == 1000
+                     else None},
     }
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline_batched(systems, R, args.cpu_seconds)
