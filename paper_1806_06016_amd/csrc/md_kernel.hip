@@ -924,11 +924,18 @@ __global__ __launch_bounds__(1024) void k_export(RunDev<float> d, int64_t r0, in
 // ---------------------------------------------------------------------------
 // wide layout: one replica per wavefront (molecules up to 320 atoms, and every
 // run of a context that holds one).  Atom a lives on lane a % 64, slot a / 64.
-// All-pairs nonbonded forces without Newton's third law: lane i walks every
-// partner j (position from the wave's LDS stage, parameters from the run's
-// per-atom table, exclusion / 1-4 bits 32 partners at a time), so no lane
-// ever writes another lane's force; the pair energy is halved.
+// All-pairs nonbonded forces with Newton's third law: copies of a slot's atoms
+// rotate around the wavefront (see wide_evaluate); pair parameters are combined
+// on the fly from per-atom factors, exclusion / 1-4 bits come 64 partners at a
+// time.
 // ---------------------------------------------------------------------------
+// lane i receives lane (i + 1) mod 64 (DPP wave_rol:1)
+__device__ __forceinline__ int wave_rol1(int v) { return __builtin_amdgcn_mov_dpp(v, 0x134, 0xF, 0xF, false); }
+__device__ __forceinline__ float wave_rol1(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x134, 0xF, 0xF, false));
+}
+
 struct WideRegs {
     float x[kWideSlots], y[kWideSlots], z[kWideSlots];
     float vx[kWideSlots], vy[kWideSlots], vz[kWideSlots];
@@ -960,55 +967,96 @@ __device__ __forceinline__ void wide_evaluate(WideRegs& r, const RunDev<float>& 
     }
     wave_sync();
     bonded_terms<float, ENERGY, kWide>(d, pos, frc, lane, eacc);
+    // Nonbonded pairs, each unordered pair once: for every partner slot t a
+    // copy of slot t's atoms (position, pair factors, reaction-force sum and
+    // atom index) travels around the wavefront one lane per step (DPP wave
+    // rotation); at step k lane l holds partner atom 64 t + (l + k) mod 64 and
+    // pairs it with its own atoms of slots s <= t (same slot: k = 1..32, the
+    // k = 32 pair kept on one of its two lanes).  The travelling reaction sums
+    // are added to the LDS force stage at the end (distinct atoms per lane).
     const float s14lj = d.s14lj, s14c = d.s14c;
-    for (int c = 0; c < d.nchunk; ++c) {
-        uint32_t ex[kWideSlots], s4[kWideSlots];
 #pragma unroll
-        for (int s = 0; s < kWideSlots; ++s) {
-            const int a = kWide * s + lane;
-            ex[s] = ~0u;
-            s4[s] = 0u;
-            if (s < nsl && a < n) {
-                const uint2 m = d.pmask[(size_t)a * d.nchunk + c];
-                ex[s] = m.x;
-                s4[s] = m.y;
+    for (int t = 0; t < kWideSlots; ++t) {
+        if (t < nsl) {
+            float px = r.x[t], py = r.y[t], pz = r.z[t];
+            float psg = r.sg[t], pse = r.se[t], pqs = r.qs[t];
+            float pfx = 0.f, pfy = 0.f, pfz = 0.f;
+            int pid = lane;
+            // own atoms' exclusion / 1-4 bits over the 64 atoms of slot t
+            uint64_t ex[kWideSlots], s4[kWideSlots];
+#pragma unroll
+            for (int s = 0; s <= t; ++s) {
+                const int a = kWide * s + lane;
+                ex[s] = ~0ull;
+                s4[s] = 0ull;
+                if (a < n) {
+                    uint2 m0 = make_uint2(0u, 0u), m1 = make_uint2(0u, 0u);
+                    if (2 * t < d.nchunk)
+                        m0 = d.pmask[(size_t)a * d.nchunk + 2 * t];
+                    if (2 * t + 1 < d.nchunk)
+                        m1 = d.pmask[(size_t)a * d.nchunk + 2 * t + 1];
+                    ex[s] = ((uint64_t)m1.x << 32) | m0.x;
+                    s4[s] = ((uint64_t)m1.y << 32) | m0.y;
+                }
             }
-        }
-        const int j1 = (32 * c + 32 < n) ? 32 * c + 32 : n;
-        for (int j = 32 * c; j < j1; ++j) {
-            const float xj = pos[3 * j], yj = pos[3 * j + 1], zj = pos[3 * j + 2];
-            const float4 pj = d.apar4[j];
-            const uint32_t bit = 1u << (j & 31);
+            const int kend = (t == 0) ? 33 : kWide;
+            for (int k = 0; k < kend; ++k) {
 #pragma unroll
-            for (int s = 0; s < kWideSlots; ++s) {
-                if (s < nsl) {
-                    const float dx = r.x[s] - xj, dy = r.y[s] - yj, dz = r.z[s] - zj;
-                    const float r2 = dx * dx + dy * dy + dz * dz;
-                    const float ir2 = rcp_(r2);
-                    const float sig = r.sg[s] + pj.x;
-                    const float t = sig * sig * ir2;
-                    const float t3 = t * t * t;
-                    const float e4 = r.se[s] * pj.y;      // 4 eps_ij
-                    const float C = r.qs[s] * pj.z;       // Coulomb factor of the pair
-                    const bool is14 = (s4[s] & bit) != 0u;
-                    const float slj = is14 ? s14lj : 1.f;
-                    const float sc = is14 ? s14c : 1.f;
-                    const bool skip = (ex[s] & bit) != 0u;
-                    if constexpr (ENERGY) {
-                        const float ulj = e4 * t3 * (t3 - 1.f);
-                        const float uc = (DIEL == 1) ? 0.5f * C * ir2 : C * rsq_(r2);
-                        const float u = slj * ulj + sc * uc;
-                        eacc += skip ? 0.0 : 0.5 * (double)u;
-                    } else {
-                        // force on i = g (x_i - x_j)
-                        const float flj = e4 * t3 * (12.f * t3 - 6.f) * ir2;
-                        const float fc = (DIEL == 1) ? C * ir2 * ir2 : C * ir2 * rsq_(r2);
-                        float g = slj * flj + sc * fc;
-                        g = skip ? 0.f : g;
-                        r.fx[s] += g * dx;
-                        r.fy[s] += g * dy;
-                        r.fz[s] += g * dz;
+                for (int s = 0; s <= t; ++s) {
+                    if (s < t || (k >= 1 && k <= 32)) {
+                        bool skip = ((ex[s] >> pid) & 1ull) != 0ull;
+                        if (s == t && k == 32 && pid < lane)
+                            skip = true;
+                        const bool is14 = ((s4[s] >> pid) & 1ull) != 0ull;
+                        const float dx = r.x[s] - px, dy = r.y[s] - py, dz = r.z[s] - pz;
+                        const float r2 = dx * dx + dy * dy + dz * dz;
+                        const float ir2 = rcp_(r2);
+                        const float sig = r.sg[s] + psg;
+                        const float tt = sig * sig * ir2;
+                        const float t3 = tt * tt * tt;
+                        const float e4 = r.se[s] * pse;       // 4 eps_ij
+                        const float C = r.qs[s] * pqs;        // Coulomb factor of the pair
+                        const float slj = is14 ? s14lj : 1.f;
+                        const float sc = is14 ? s14c : 1.f;
+                        if constexpr (ENERGY) {
+                            const float ulj = e4 * t3 * (t3 - 1.f);
+                            const float uc = (DIEL == 1) ? 0.5f * C * ir2 : C * rsq_(r2);
+                            const float u = slj * ulj + sc * uc;
+                            eacc += skip ? 0.0 : (double)u;
+                        } else {
+                            // force on the own atom = g (x_own - x_partner), on the partner -g (...)
+                            const float flj = e4 * t3 * (12.f * t3 - 6.f) * ir2;
+                            const float fc = (DIEL == 1) ? C * ir2 * ir2 : C * ir2 * rsq_(r2);
+                            float g = slj * flj + sc * fc;
+                            g = skip ? 0.f : g;
+                            r.fx[s] += g * dx;
+                            r.fy[s] += g * dy;
+                            r.fz[s] += g * dz;
+                            pfx -= g * dx;
+                            pfy -= g * dy;
+                            pfz -= g * dz;
+                        }
                     }
+                }
+                px = wave_rol1(px);
+                py = wave_rol1(py);
+                pz = wave_rol1(pz);
+                psg = wave_rol1(psg);
+                pse = wave_rol1(pse);
+                pqs = wave_rol1(pqs);
+                if constexpr (!ENERGY) {
+                    pfx = wave_rol1(pfx);
+                    pfy = wave_rol1(pfy);
+                    pfz = wave_rol1(pfz);
+                }
+                pid = wave_rol1(pid);
+            }
+            if constexpr (!ENERGY) {
+                const int j = kWide * t + pid;
+                if (j < n) {
+                    frc[3 * j] += pfx;
+                    frc[3 * j + 1] += pfy;
+                    frc[3 * j + 2] += pfz;
                 }
             }
         }
