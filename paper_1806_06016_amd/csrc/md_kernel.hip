@@ -1136,7 +1136,7 @@ __device__ __forceinline__ void wide_store(const WideRegs& r, const RunDev<float
 // (`order`), replicas of a run in slot order.  n_steps velocity-Verlet steps
 // with Andersen collisions, then E_pot (FP64 sum) and E_kin of the final state.
 template <int DIEL>
-__global__ __launch_bounds__(512) void k_md_wide(const RunDev<float>* runs, const int32_t* order, int n_runs,
+__global__ __launch_bounds__(256, 3) void k_md_wide(const RunDev<float>* runs, const int32_t* order, int n_runs,
                                                   int32_t* counter, int nmax, int n_steps)
 {
     extern __shared__ __align__(16) unsigned char smem[];

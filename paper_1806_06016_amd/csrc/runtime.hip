@@ -622,12 +622,12 @@ pamd_status pamd_init(const pamd_system* sys, int32_t n_runs, const pamd_params*
     c->nmax = n_max;
     c->diel = sys[0].dielectric;
     if (c->wide) {
-        // one replica per wavefront; at most 8 waves (512 threads) per workgroup
+        // one replica per wavefront; at most 4 waves (256 threads) per workgroup
         for (int r = 1; r < n_runs; ++r)
             if (sys[r].dielectric != sys[0].dielectric)
                 return fail(c, PAMD_ERR_ARG, "runs of one batched launch must share the dielectric model");
-        if (waves == 0 || waves > 8)
-            waves = 8;
+        if (waves == 0 || waves > 4)
+            waves = 4;
         while (waves > 1 && wide_lds_bytes(n_max, waves) > (size_t)max_lds)
             --waves;
         c->lds = wide_lds_bytes(n_max, waves);
