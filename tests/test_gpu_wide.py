@@ -8,6 +8,7 @@ tolerances as the register-tile parity tests: per-atom forces within
 1e-4 nm after 100 NVT steps with identical Philox streams, copy numbers
 bit-exact.
 """
+import functools
 import math
 
 import numpy as np
@@ -31,8 +32,18 @@ def B():
     return pamd
 
 
+@functools.lru_cache(maxsize=None)
+def _peptide(seed, n):
+    # the generator's clash repair takes seconds for the larger molecules
+    return S.make_peptide(seed=seed, n_atoms=n)
+
+
 def _systems():
-    return [S.make_peptide(seed=1806 + k, n_atoms=n) for k, n in enumerate(SIZES)]
+    return [_peptide(1806 + k, n) for k, n in enumerate(SIZES)]
+
+
+def _batched_systems():
+    return [_peptide(1806 + k, n) for k, n in enumerate(S.C4_SIZES)]
 
 
 def _perturbed(sysd, R, scale, seed):
@@ -50,7 +61,7 @@ def test_batched_context_uses_the_wide_layout(B):
 
 def test_wide_forces_and_energies(B):
     """Every molecule size of the batched workload (40 ... 300 atoms), batched."""
-    syss = S.c4_systems()
+    syss = _batched_systems()
     R = 13
     print("wide forces", S.C4_SIZES, flush=True)
     p = B.Pamd(syss, R_target=R, T0=700.0, dt=0.001, nu=1.0, seed=3, precision=B.PAMD_FP32)
