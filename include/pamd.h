@@ -173,7 +173,9 @@ pamd_status pamd_md_steps(pamd_ctx* ctx, int32_t n_steps, void* stream);
  * copies of source j take consecutive new slots in increasing j; velocities
  * are scaled by sqrt(T_i / T_{i-1}) and each copy is translated so its centre
  * of mass sits at the origin.  Asynchronous; an over-capacity population
- * leaves the state unchanged and raises PAMD_ERR_CAPACITY at the next sync. */
+ * leaves the state unchanged and raises PAMD_ERR_CAPACITY at the next sync.
+ * PAMD_ERR_STATE (the context stays usable) when no pamd_md_steps call, or
+ * pamd_set_state with energies, has given the population its energies. */
 pamd_status pamd_resample(pamd_ctx* ctx, const double* T_next, const double* d_uniforms,
                           void* stream);
 

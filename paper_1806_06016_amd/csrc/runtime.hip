@@ -100,6 +100,7 @@ struct pamd_ctx {
     int failed = 0;
     int n_cu = 0, waves = 0, blocks = 0, gather_blocks = 0;
     size_t lds = 0;
+    int have_energy = 0;     // some pamd_md_steps (or a state with energies) since init
     pamd_nn* nn = nullptr;   // learned surrogate of the r-RESPA inner force (null: plain MD)
     int mts_ratio = 0;       // inner steps per outer step
     // wide layout: every run in one persistent k_md_wide launch
@@ -721,6 +722,7 @@ pamd_status pamd_md_steps(pamd_ctx* c, int32_t n_steps, void* stream)
         return st;
     if (n_steps < 0)
         return fail(c, PAMD_ERR_ARG, "n_steps < 0");
+    c->have_energy = 1;
     hipStream_t s = as_stream(stream);
     if (c->wide) {
         HIPCHK(c, launch_md_wide(c->d_runs, c->d_order, c->n_runs, c->d_counter, c->nmax, n_steps, c->diel, c->blocks,
@@ -756,6 +758,11 @@ pamd_status pamd_resample(pamd_ctx* c, const double* T_next, const double* d_uni
     pamd_status st = check_ctx(c);
     if (st != PAMD_OK)
         return st;
+    if (!c->have_energy) {
+        // call-order error: the context stays usable
+        c->err = "resample before any MD step: the population has no energies yet";
+        return PAMD_ERR_STATE;
+    }
     hipStream_t s = as_stream(stream);
     for (int r = 0; r < c->n_runs; ++r) {
         Run& run = c->runs[r];
@@ -945,6 +952,7 @@ static pamd_status set_state_t(pamd_ctx* c, Run& run, const double* x, const dou
     HIPCHK(c, hipMemcpyAsync(d.slab[cur], buf.data(), buf.size() * sizeof(real), hipMemcpyHostToDevice, s));
     HIPCHK(c, hipMemcpyAsync(d.epot[cur], e.data(), R * sizeof(double), hipMemcpyHostToDevice, s));
     HIPCHK(c, hipMemcpyAsync(d.anc[cur], an.data(), R * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    c->have_energy = Ep ? 1 : 0;   // without energies the next resampling needs an MD call first
     ctl.R_cur = R;
     ctl.R_new = R;
     ctl.T_cur = sc->T;

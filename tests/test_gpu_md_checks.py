@@ -80,6 +80,18 @@ def test_nve_conserves_momentum(B):
     p.close()
 
 
+def test_resample_before_md_is_a_state_error(B):
+    sysd = S.c1_system()
+    p = B.Pamd([sysd], R_target=16, T0=2.0, dt=0.002, nu=1.0, seed=1, precision=0)
+    with pytest.raises(B.PamdError) as e:
+        p.resample([1.9])
+    assert e.value.code == B.PAMD_ERR_STATE
+    p.md_steps(0)                              # energies now exist
+    p.resample([1.9])
+    assert p.observables()[0]["T"] == 1.9
+    p.close()
+
+
 def test_optional_call_errors(B):
     """r-RESPA needs an FP32 context of molecules within the register tiles, a
     step count that is a multiple of the outer ratio; export likewise."""
