@@ -64,7 +64,7 @@ void ora_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint3
 }
 
 /* stream identities of the counter's fourth word */
-enum { ST_COLLIDE = 0, ST_VELOCITY = 1, ST_RESAMPLE = 2, ST_INIT = 3 };
+enum { ST_COLLIDE = 0, ST_VELOCITY = 1, ST_RESAMPLE = 2, ST_INIT = 3, ST_MULTINOMIAL = 4 };
 
 typedef struct {
     uint32_t seed_lo, seed_hi, run, pad;
@@ -463,6 +463,16 @@ void ora_resample_uniforms(const ora_rng* g, int64_t R, uint32_t temp_index, dou
         uint32_t w[4];
         draw(g, (uint32_t)j, temp_index, 0u, ST_RESAMPLE, w);
         u[j] = u53(w[0], w[1]);
+    }
+}
+
+/* multinomial draws of stream 4: counter (draw k, temperature index, 0, 4) */
+void ora_multinomial_uniforms(const ora_rng* g, int64_t n_draws, uint32_t temp_index, double* u)
+{
+    for (int64_t k = 0; k < n_draws; ++k) {
+        uint32_t w[4];
+        draw(g, (uint32_t)k, temp_index, 0u, ST_MULTINOMIAL, w);
+        u[k] = u53(w[0], w[1]);
     }
 }
 

@@ -78,6 +78,7 @@ def lib():
         _lib.ora_lse.argtypes = [i64, vp, d, vp, vp, vp, vp]
         _lib.ora_lse.restype = i32
         _lib.ora_resample_uniforms.argtypes = [vp, i64, C.c_uint32, vp]
+        _lib.ora_multinomial_uniforms.argtypes = [vp, i64, C.c_uint32, vp]
         _lib.ora_counts.argtypes = [i64, vp, d, d, d, i64, vp, vp, vp]
         _lib.ora_counts.restype = i64
         _lib.ora_weight_variance.argtypes = [i64, vp, d]
@@ -281,6 +282,49 @@ def copy_counts(E: np.ndarray, dbeta: float, R_target: int, u: np.ndarray, m=Non
     return c, tau
 
 
+def multinomial_uniforms(n_draws: int, temp_index: int, seed: int, run: int = 0) -> np.ndarray:
+    """Uniforms of the multinomial draws: Philox stream 4, counter (k, i, 0, 4)."""
+    u = np.zeros(n_draws)
+    g = _rng(seed, run)
+    lib().ora_multinomial_uniforms(C.byref(g), n_draws, temp_index, _p(u))
+    return u
+
+
+def multinomial_counts(E: np.ndarray, dbeta: float, u: np.ndarray, m=None):
+    """The paper's resampling rule (PAMD step 2 and the paragraph after it):
+    len(u) independent draws from the categorical distribution p_j = w_j / sum w
+    (the tau_j / R of the scheme), w_j = exp(-dbeta (E_j - m)).  Draw k picks the
+    first j whose running sum W_j = w_0 + ... + w_j exceeds u_k W_{R-1}; should
+    rounding leave no such j (u_k W_{R-1} == W_{R-1}), the first j with
+    W_j == W_{R-1}.  Returns (c [R], W [R]); sum c = len(u)."""
+    E = np.ascontiguousarray(E, np.float64)
+    if m is None:
+        m = float(E.min())
+    w = np.exp(-dbeta * (E - m))
+    W = np.cumsum(w)                      # left to right
+    t = np.asarray(u, np.float64) * W[-1]
+    j = np.searchsorted(W, t, side="right")
+    tail = j >= len(E)
+    j[tail] = np.searchsorted(W, t[tail], side="left")
+    return np.bincount(j, minlength=len(E)).astype(np.int32), W
+
+
+def resampling_counts(mode: str, E: np.ndarray, dbeta: float, R_target: int, temp_index: int,
+                      seed: int, run: int = 0, m=None, S=None) -> np.ndarray:
+    """Copy numbers of one resampling in the given mode: "nearest" (random
+    rounding of tau_j, stream 2), "multinomial" (R_target draws, stream 4) or
+    "none" (every copy kept once: annealing without resampling)."""
+    if mode == "nearest":
+        u = resample_uniforms(len(E), temp_index, seed, run)
+        return copy_counts(E, dbeta, R_target, u, m, S)[0]
+    if mode == "multinomial":
+        u = multinomial_uniforms(R_target, temp_index, seed, run)
+        return multinomial_counts(E, dbeta, u, m)[0]
+    if mode == "none":
+        return np.ones(len(E), np.int32)
+    raise ValueError(mode)
+
+
 def weight_variance(E: np.ndarray, dbeta: float) -> float:
     E = np.ascontiguousarray(E, np.float64)
     return lib().ora_weight_variance(len(E), _p(E), float(dbeta))
@@ -349,10 +393,13 @@ class AnnealResult:
 def anneal(sysd, R: int, T0: float, schedule: Optional[Sequence[float]], theta: int, theta_eq: int,
            dt: float, nu: float, seed: int, T_final: Optional[float] = None, v_target: float = 0.1,
            x0: Optional[np.ndarray] = None, v0: Optional[np.ndarray] = None, run: int = 0,
-           resampling: bool = True, max_temps: int = 10000) -> AnnealResult:
+           resampling: str = "nearest", max_temps: int = 10000) -> AnnealResult:
     """Plain PAMD run.  schedule: list of temperatures T_0 > T_1 > ... (T_0 = T0),
     or None for the adaptive choice (normalised weight variance = v_target,
-    down to T_final).  x0/v0 optionally give the initial population."""
+    down to T_final).  x0/v0 optionally give the initial population.
+    resampling: "nearest", "multinomial" or "none" (resampling_counts); with
+    "none" every copy is handed over to itself, so the population is R
+    independent annealing runs (the ablation the paper calls "anneal")."""
     osys = OracleSystem(sysd)
     n = osys.n
     kB = osys.kB
@@ -384,14 +431,10 @@ def anneal(sysd, R: int, T0: float, schedule: Optional[Sequence[float]], theta: 
         i += 1
         dbeta = 1.0 / (kB * T_next) - 1.0 / (kB * T_prev)
         m, S, S2, lq = lse(Ep, dbeta)
-        if resampling:
-            u = resample_uniforms(len(Ep), i, seed, run)
-            c, _ = copy_counts(Ep, dbeta, R, u, m, S)
-            x, v, Ep, anc = gather(c, [x, v, Ep, anc])
-            x = np.ascontiguousarray(recentre(x, osys.mass))
-            v = np.ascontiguousarray(v * math.sqrt(T_next / T_prev))
-        else:
-            v = np.ascontiguousarray(v * math.sqrt(T_next / T_prev))
+        c = resampling_counts(resampling, Ep, dbeta, R, i, seed, run, m, S)
+        x, v, Ep, anc = gather(c, [x, v, Ep, anc])
+        x = np.ascontiguousarray(recentre(x, osys.mass))
+        v = np.ascontiguousarray(v * math.sqrt(T_next / T_prev))
         Ep, Ek = md_steps(osys, x, v, theta, T_next, dt, nu, seed, step, run)
         step += theta
         res.T.append(T_next); res.R.append(len(Ep)); res.lnQ.append(lq)
