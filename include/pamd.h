@@ -58,6 +58,14 @@ enum {
 };
 
 enum { PAMD_FP64 = 0, PAMD_FP32 = 1 };
+/* Copy-number rule of PAMD step 2 (pamd_params.resampling):
+ *   NEAREST      c_j = floor(tau_j) + [u_j < frac(tau_j)]: random rounding of the
+ *                expected copy numbers; the population size fluctuates around R.
+ *   MULTINOMIAL  R independent draws from p_j = tau_j / R (the rule the paper states
+ *                after the scheme); the population size stays R.
+ *   NONE         c_j = 1: resampling switched off (the paper's "anneal" ablation);
+ *                the rescale, recentring and ln Q bookkeeping still run. */
+enum { PAMD_RESAMPLE_NEAREST = 0, PAMD_RESAMPLE_MULTINOMIAL = 1, PAMD_RESAMPLE_NONE = 2 };
 enum { PAMD_DIELECTRIC_VACUUM = 0, PAMD_DIELECTRIC_4R = 1 };
 
 #define PAMD_MAX_ATOMS 320   /* FP32; FP64 runs take at most 32 atoms */
@@ -117,6 +125,8 @@ typedef struct pamd_params {
     int32_t waves_per_block;       /* 0: automatic; else 1..16 (autotuner override) */
     double V_target;               /* adaptive schedule: normalised weight variance per step */
     double T_final;                /* adaptive schedule: lowest temperature T_N */
+    int32_t resampling;            /* PAMD_RESAMPLE_*: how pamd_resample draws the copy numbers */
+    int32_t reserved;              /* 0 */
 } pamd_params;
 
 /* Population observables of one run (PAMD step 4), all FP64. */
@@ -167,10 +177,18 @@ pamd_status pamd_md_steps(pamd_ctx* ctx, int32_t n_steps, void* stream);
  * step with normalised weight variance <= V_target, not below T_final), and
  * T_next[r] < 0 takes the next entry of the run's device schedule
  * (pamd_set_schedule; the last entry repeats once it is reached).
- * d_uniforms: device [n_runs][R_cap] doubles in [0,1) for the rounding draws,
- * or NULL to draw them from Philox stream 2.  Copy numbers are
- * c_j = floor(tau_j) + [u_j < frac(tau_j)] with tau_j = R_target w_j / sum w;
- * copies of source j take consecutive new slots in increasing j; velocities
+ * d_uniforms: device [n_runs][R_cap] doubles in [0,1), or NULL to draw them
+ * from Philox.  Copy numbers follow the run's pamd_params.resampling with
+ * tau_j = R_target w_j / sum w, w_j = exp(-dbeta (E_j - min E)):
+ *   NEAREST      c_j = floor(tau_j) + [u_j < frac(tau_j)]; u_j = d_uniforms[r][j]
+ *                or Philox stream 2, counter (j, i, 0, 2);
+ *   MULTINOMIAL  draw k = 0 .. R_target-1 picks the first j with W_j > u_k W_{R-1},
+ *                W_j = w_0 + ... + w_j (FP64 running sums, in chunk order; if
+ *                rounding leaves no such j, the first j with W_j == W_{R-1});
+ *                u_k = d_uniforms[r][k] or Philox stream 4, counter (k, i, 0, 4);
+ *   NONE         c_j = 1;
+ * where i is the index of the new temperature.  Copies of source j take
+ * consecutive new slots in increasing j; velocities
  * are scaled by sqrt(T_i / T_{i-1}) and each copy is translated so its centre
  * of mass sits at the origin.  Asynchronous; an over-capacity population
  * leaves the state unchanged and raises PAMD_ERR_CAPACITY at the next sync.

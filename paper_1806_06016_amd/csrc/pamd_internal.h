@@ -60,6 +60,7 @@ struct RunDev {
     int32_t* anc[2];        // [R_cap]
     int32_t* counts;        // [R_cap]
     int32_t* src_of;        // [R_cap]
+    double* cdf;            // [R_cap] running weight sums W_j (multinomial resampling)
     uint8_t* fam;           // [R_target] family flags
     const double* unif;     // optional caller uniforms for this run
     // topology / parameters
@@ -84,6 +85,7 @@ struct RunDev {
     uint32_t key0, key1;    // Philox key
     int32_t dielectric;
     int32_t waves_per_block;
+    int32_t resampling;     // PAMD_RESAMPLE_*
     // wide layout only: per-atom (sigma / 2, 2 sqrt(eps), q sqrt(k_e c), 0) with
     // c = 1/2 for eps = 4r and 1 in vacuum, and per (atom, 32-atom chunk) the
     // bit masks (excluded pair incl. self, scaled 1-4 pair)

@@ -11,6 +11,8 @@
 //   stream 1  collision velocity of atom a: block a, three normals
 //   stream 2  resampling uniform of slot j: step word = temperature index
 //   stream 3  initial Maxwell-Boltzmann velocity of atom a: block a
+//   stream 4  multinomial resampling: uniform of draw k in the slot word,
+//             step word = temperature index
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -42,7 +44,13 @@ __host__ __device__ __forceinline__ u32x4 philox10(uint32_t c0, uint32_t c1, uin
     return u32x4{{c0, c1, c2, c3}};
 }
 
-enum : uint32_t { kStreamCollide = 0, kStreamVelocity = 1, kStreamResample = 2, kStreamInit = 3 };
+enum : uint32_t {
+    kStreamCollide = 0,
+    kStreamVelocity = 1,
+    kStreamResample = 2,
+    kStreamInit = 3,
+    kStreamMultinomial = 4
+};
 
 // 53-bit uniform in [0, 1) from two words
 __host__ __device__ __forceinline__ double uniform53(uint32_t a, uint32_t b)

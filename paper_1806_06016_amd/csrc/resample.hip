@@ -7,7 +7,10 @@
 //             ln Q_i estimates ln Z(T_i) - ln Z(T_{i-1}) and is summed on the device
 //   adaptive  T_i: largest step whose normalised weight variance R sum p^2 - 1
 //             stays within the target, by bisection on dbeta
-//   counts    c_j = floor(tau_j) + [u_j < frac(tau_j)], tau_j = R_target w_j / S
+//   counts    nearest: c_j = floor(tau_j) + [u_j < frac(tau_j)], tau_j = R_target w_j / S;
+//             multinomial: R_target independent draws from p_j = w_j / S (the rule
+//             stated after the scheme), each an inverse-CDF binary search over
+//             the FP64 running sums W_j; none: c_j = 1
 //   scan      exclusive prefix sum of c -> destination slots, copies of source
 //             j in consecutive slots in increasing j
 //   gather    slab copy into the other ping-pong buffer, velocities scaled by
@@ -18,6 +21,7 @@
 // scheduling.  The gather is HBM bound: one wavefront per destination slab.
 #include <math.h>
 
+#include "pamd.h"
 #include "pamd_internal.h"
 #include "philox.h"
 
@@ -224,6 +228,94 @@ __global__ __launch_bounds__(kBlk) void k_weights(RunDev<real> d, double T_req)
 }
 
 // --------------------------------------------------------------------------
+// Multinomial resampling, part 1: running weight sums W_j = w_0 + ... + w_j
+// in FP64 and zeroed counts.  Thread t sums its chunk left to right; the
+// chunk totals are scanned serially, and W_j = offset_t + (partial sum of the
+// chunk up to j), so W is non-decreasing (rounding is monotone and the last
+// W of a chunk equals the next chunk's offset) and zero weights leave it flat.
+// --------------------------------------------------------------------------
+template <typename real>
+__global__ __launch_bounds__(kBlk) void k_cdf(RunDev<real> d)
+{
+    __shared__ double sh[kBlk];
+    const RunCtl* c = d.ctl;
+    if (c->error)
+        return;
+    const int64_t R = c->R_cur;
+    const double* E = d.epot[c->cur];
+    const double db = c->dbeta, m = c->m;
+    const int64_t chunk = (R + kBlk - 1) / kBlk;
+    const int64_t j0 = (int64_t)threadIdx.x * chunk;
+    const int64_t j1 = (j0 + chunk < R) ? j0 + chunk : R;
+    double part = 0.0;
+    for (int64_t j = j0; j < j1; ++j) {
+        part += exp(-db * (E[j] - m));
+        d.cdf[j] = part;
+        d.counts[j] = 0;
+    }
+    sh[threadIdx.x] = part;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double run = 0.0;
+        for (int t = 0; t < kBlk; ++t) {
+            const double p = sh[t];
+            sh[t] = run;
+            run += p;
+        }
+    }
+    __syncthreads();
+    const double off = sh[threadIdx.x];
+    for (int64_t j = j0; j < j1; ++j)
+        d.cdf[j] = off + d.cdf[j];
+}
+
+// Multinomial resampling, part 2: one thread per draw k < R_target picks the
+// first j with W_j > u_k W_{R-1} (if rounding leaves none, the first j with
+// W_j >= u_k W_{R-1}) by binary search and adds one copy of j.
+template <typename real>
+__global__ __launch_bounds__(256) void k_draw(RunDev<real> d)
+{
+    const RunCtl* c = d.ctl;
+    if (c->error)
+        return;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= d.R_target)
+        return;
+    const int64_t R = c->R_cur;
+    const double* W = d.cdf;
+    double u;
+    if (d.unif) {
+        u = d.unif[k];
+    } else {
+        const u32x4 w = philox10((uint32_t)k, c->temp_index + 1u, 0u, kStreamMultinomial, d.key0, d.key1);
+        u = uniform53(w.v[0], w.v[1]);
+    }
+    const double t = u * W[R - 1];
+    // first j in [0, R) with W_j > t; R when there is none
+    int64_t lo = 0, hi = R;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (W[mid] > t)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    if (lo == R) {
+        // t == W_{R-1}: the first j with W_j >= t
+        lo = 0;
+        hi = R - 1;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (W[mid] >= t)
+                hi = mid;
+            else
+                lo = mid + 1;
+        }
+    }
+    atomicAdd(&d.counts[lo], 1);
+}
+
+// --------------------------------------------------------------------------
 // PAMD step 2b: copy numbers, prefix sum, source of every destination slot
 // --------------------------------------------------------------------------
 template <typename real>
@@ -242,19 +334,29 @@ __global__ __launch_bounds__(kBlk) void k_counts(RunDev<real> d)
     const int64_t j0 = (int64_t)threadIdx.x * chunk;
     const int64_t j1 = (j0 + chunk < R) ? j0 + chunk : R;
     int64_t local = 0;
-    for (int64_t j = j0; j < j1; ++j) {
-        const double tau = Rt * exp(-db * (E[j] - m)) / S;
-        const double fl = floor(tau);
-        double u;
-        if (d.unif) {
-            u = d.unif[j];
-        } else {
-            const u32x4 w = philox10((uint32_t)j, ti, 0u, kStreamResample, d.key0, d.key1);
-            u = uniform53(w.v[0], w.v[1]);
+    if (d.resampling == PAMD_RESAMPLE_MULTINOMIAL) {
+        // counts drawn by k_draw
+        for (int64_t j = j0; j < j1; ++j)
+            local += d.counts[j];
+    } else if (d.resampling == PAMD_RESAMPLE_NONE) {
+        for (int64_t j = j0; j < j1; ++j)
+            d.counts[j] = 1;
+        local = j1 > j0 ? j1 - j0 : 0;
+    } else {
+        for (int64_t j = j0; j < j1; ++j) {
+            const double tau = Rt * exp(-db * (E[j] - m)) / S;
+            const double fl = floor(tau);
+            double u;
+            if (d.unif) {
+                u = d.unif[j];
+            } else {
+                const u32x4 w = philox10((uint32_t)j, ti, 0u, kStreamResample, d.key0, d.key1);
+                u = uniform53(w.v[0], w.v[1]);
+            }
+            const int32_t cj = (int32_t)fl + ((u < tau - fl) ? 1 : 0);
+            d.counts[j] = cj;
+            local += cj;
         }
-        const int32_t cj = (int32_t)fl + ((u < tau - fl) ? 1 : 0);
-        d.counts[j] = cj;
-        local += cj;
     }
     int64_t total = 0;
     int64_t off = block_exscan(local, sh, &total);
@@ -437,6 +539,10 @@ template <typename real>
 hipError_t launch_resample_t(const RunDev<real>& d, double T_req, double mtot, int gather_blocks, hipStream_t s)
 {
     hipLaunchKernelGGL(k_weights<real>, dim3(1), dim3(kBlk), 0, s, d, T_req);
+    if (d.resampling == PAMD_RESAMPLE_MULTINOMIAL) {
+        hipLaunchKernelGGL(k_cdf<real>, dim3(1), dim3(kBlk), 0, s, d);
+        hipLaunchKernelGGL(k_draw<real>, dim3((unsigned)((d.R_target + 255) / 256)), dim3(256), 0, s, d);
+    }
     hipLaunchKernelGGL(k_counts<real>, dim3(1), dim3(kBlk), 0, s, d);
     hipLaunchKernelGGL(k_gather<real>, dim3(gather_blocks), dim3(256), 0, s, d, mtot);
     hipLaunchKernelGGL(k_resample_finalize<real>, dim3(1), dim3(64), 0, s, d);

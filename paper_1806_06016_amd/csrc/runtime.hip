@@ -211,6 +211,8 @@ pamd_status validate(pamd_ctx* c, const pamd_system& s, const pamd_params& p, in
         return fail(c, PAMD_ERR_ARG, "T0, dt, kB must be > 0 and nu >= 0");
     if (p.waves_per_block < 0 || p.waves_per_block > 16)
         return fail(c, PAMD_ERR_ARG, "waves_per_block must be 0..16");
+    if (p.resampling < PAMD_RESAMPLE_NEAREST || p.resampling > PAMD_RESAMPLE_NONE)
+        return fail(c, PAMD_ERR_ARG, "unknown resampling mode");
     return PAMD_OK;
 }
 
@@ -364,6 +366,7 @@ void carve(Carver& st, Carver& wk, const pamd_system& s, const pamd_params& p, i
     d.ctl = wk.take<RunCtl>(1);
     d.counts = wk.take<int32_t>(Rc);
     d.src_of = wk.take<int32_t>(Rc);
+    d.cdf = wk.take<double>(Rc);
     d.fam = wk.take<uint8_t>(p.R_target);
     d.nb_ab = wk.take<real>((size_t)steps * 32);
     d.nb_c = wk.take<real>((size_t)steps * 16);
@@ -407,6 +410,7 @@ void carve(Carver& st, Carver& wk, const pamd_system& s, const pamd_params& p, i
     d.key0 = (uint32_t)(p.seed & 0xFFFFFFFFu);
     d.key1 = (uint32_t)(p.seed >> 32) + (uint32_t)run;
     d.dielectric = s.dielectric;
+    d.resampling = p.resampling;
     d.wide = wide;
     d.nchunk = wide ? nchunk : 0;
     d.apar4 = wide ? wk.take<float4>(n) : nullptr;

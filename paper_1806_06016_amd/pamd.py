@@ -17,6 +17,9 @@ LIB_PATH = os.path.join(_HERE, "libpamd.so")
 
 PAMD_OK, PAMD_ERR_ARG, PAMD_ERR_HIP, PAMD_ERR_CAPACITY, PAMD_ERR_NONFINITE, PAMD_ERR_STATE = range(6)
 PAMD_FP64, PAMD_FP32 = 0, 1
+PAMD_RESAMPLE_NEAREST, PAMD_RESAMPLE_MULTINOMIAL, PAMD_RESAMPLE_NONE = 0, 1, 2
+RESAMPLING_MODES = {"nearest": PAMD_RESAMPLE_NEAREST, "multinomial": PAMD_RESAMPLE_MULTINOMIAL,
+                    "none": PAMD_RESAMPLE_NONE}
 PAMD_FORCE_CHUNK = 256
 MAX_ATOMS = 320
 TILE_ATOMS = 80
@@ -46,6 +49,7 @@ class pamd_params(C.Structure):
         ("R_target", C.c_int64), ("R_cap", C.c_int64), ("T0", C.c_double), ("dt", C.c_double),
         ("nu", C.c_double), ("seed", C.c_uint64), ("precision", C.c_int32),
         ("waves_per_block", C.c_int32), ("V_target", C.c_double), ("T_final", C.c_double),
+        ("resampling", C.c_int32), ("reserved", C.c_int32),
     ]
 
 
@@ -164,7 +168,10 @@ class Pamd:
 
     def __init__(self, systems: Sequence, R_target: int, T0: float, dt: float, nu: float, seed: int,
                  precision: int = PAMD_FP32, R_cap: Optional[int] = None, V_target: float = 0.1,
-                 T_final: Optional[float] = None, waves_per_block: int = 0, stream=None):
+                 T_final: Optional[float] = None, waves_per_block: int = 0, stream=None,
+                 resampling="nearest"):
+        """resampling: "nearest", "multinomial" or "none" for every run, or one
+        mode per run (a sequence)."""
         import torch
         self.torch = torch
         self.lib = load_library()
@@ -190,6 +197,8 @@ class Pamd:
             p.waves_per_block = int(waves_per_block)
             p.V_target = float(V_target)
             p.T_final = float(T_final if T_final is not None else T0)
+            mode = resampling if isinstance(resampling, str) else resampling[r]
+            p.resampling = RESAMPLING_MODES[mode]
             prm.append(p)
         self._prm = P(*prm)
         sb, wb = C.c_size_t(), C.c_size_t()
@@ -229,8 +238,10 @@ class Pamd:
         self._check(self.lib.pamd_md_steps(self.ctx, int(n), self._s()), self.ctx)
 
     def resample(self, T_next: Optional[Sequence[float]] = None, uniforms=None) -> None:
-        """T_next: per-run temperatures (<= 0 or None: adaptive).  uniforms: optional
-        torch float64 CUDA tensor [n_runs, R_cap]."""
+        """T_next: per-run temperatures (0 or None: adaptive, < 0: next entry of
+        the device schedule).  uniforms: optional torch float64 CUDA tensor
+        [n_runs, R_cap]: the rounding uniforms of slot j (mode "nearest") or the
+        uniforms of draws k < R_target (mode "multinomial")."""
         tn = None
         if T_next is not None:
             tn = (C.c_double * self.n_runs)(*[float(t) for t in T_next])

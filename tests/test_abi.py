@@ -75,6 +75,12 @@ def test_query_sizes_is_host_only_and_validates():
     assert lib.pamd_query_sizes(ctypes.byref(s), 1, ctypes.byref(p), ctypes.byref(sb),
                                 ctypes.byref(wb)) == B.PAMD_ERR_ARG
     p.R_cap = 1100
+    for mode, want in [(B.PAMD_RESAMPLE_MULTINOMIAL, 0), (B.PAMD_RESAMPLE_NONE, 0), (3, B.PAMD_ERR_ARG),
+                       (-1, B.PAMD_ERR_ARG)]:
+        p.resampling = mode
+        assert lib.pamd_query_sizes(ctypes.byref(s), 1, ctypes.byref(p), ctypes.byref(sb),
+                                    ctypes.byref(wb)) == want
+    p.resampling = B.PAMD_RESAMPLE_NEAREST
     bad = S.c2_system()
     bad.dih_delta = bad.dih_delta + 0.3        # only 0 / pi phases are supported
     sb2 = B.make_system_struct(bad, keep)
