@@ -64,7 +64,7 @@ void ora_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint3
 }
 
 /* stream identities of the counter's fourth word */
-enum { ST_COLLIDE = 0, ST_VELOCITY = 1, ST_RESAMPLE = 2, ST_INIT = 3, ST_MULTINOMIAL = 4 };
+enum { ST_COLLIDE = 0, ST_VELOCITY = 1, ST_RESAMPLE = 2, ST_INIT = 3, ST_MULTINOMIAL = 4, ST_LANGEVIN = 5 };
 
 typedef struct {
     uint32_t seed_lo, seed_hi, run, pad;
@@ -333,7 +333,7 @@ void ora_init_velocities(const ora_sys* s, const ora_rng* g, int32_t R, const ui
 }
 
 /* ------------------------------------------------------------------------ */
-/* PAMD step 3: theta NVT velocity-Verlet steps with Andersen collisions     */
+/* PAMD step 3: theta NVT velocity-Verlet steps, Andersen or Langevin bath  */
 /* ------------------------------------------------------------------------ */
 typedef struct {
     double dt;
@@ -343,15 +343,26 @@ typedef struct {
     uint32_t step0;          /* global step counter of the first step */
     int32_t n_steps;
     int32_t mask;            /* force-field terms (T_ALL normally) */
+    double gamma;            /* Langevin friction (1/time); used when langevin != 0 */
+    int32_t langevin;        /* 0: Andersen collisions (p24), 1: Langevin bath */
+    int32_t pad;
 } ora_md;
 
 /*
  * x, v: [R][n][3] (in/out).  For every replica independently:
  *   F = F(x)
- *   repeat n_steps:  v += dt/2 F/m ; x += dt v ; F = F(x) ; v += dt/2 F/m ;
- *                    each atom collides with probability p: v_a ~ N(0, kB T / m_a)
+ *   Andersen (velocity Verlet + collisions), repeat n_steps:
+ *     v += dt/2 F/m ; x += dt v ; F = F(x) ; v += dt/2 F/m ;
+ *     each atom collides with probability p: v_a ~ N(0, kB T / m_a)
+ *   Langevin (the B-A-O-A-B splitting of Leimkuhler & Matthews, 2013: velocity
+ *   Verlet whose drift is split around an exact Ornstein-Uhlenbeck step),
+ *   repeat n_steps:
+ *     v += dt/2 F/m ; x += dt/2 v ;
+ *     v = c1 v + c2 sqrt(kB T / m) xi,  c1 = exp(-gamma dt), c2 = sqrt(1 - c1^2),
+ *         xi: three normals of stream 5, counter (slot, step, atom, 5) ;
+ *     x += dt/2 v ; F = F(x) ; v += dt/2 F/m
  *   E_pot = U(x), E_kin = sum 1/2 m v^2 at the end.
- * collisions (optional) counts collided atoms per replica.
+ * collisions (optional) counts collided atoms per replica (Andersen).
  */
 void ora_md_steps(const ora_sys* s, const ora_rng* g, const ora_md* p, int32_t R,
                   const uint32_t* slot, double* x, double* v, double* Epot, double* Ekin,
@@ -368,13 +379,34 @@ void ora_md_steps(const ora_sys* s, const ora_rng* g, const ora_md* p, int32_t R
             uint32_t sl = slot ? slot[r] : (uint32_t)r;
             int64_t ncol = 0;
             ora_energy_forces(s, xr, F, NULL, p->mask);
+            const double c1 = exp(-p->gamma * p->dt);
+            const double c2 = sqrt(1.0 - c1 * c1);
             for (int st = 0; st < p->n_steps; ++st) {
                 uint32_t step = p->step0 + (uint32_t)st;
-                for (int a = 0; a < n; ++a) {
-                    double h = 0.5 * p->dt / s->mass[a];
-                    for (int c = 0; c < 3; ++c) {
-                        vr[3 * a + c] += h * F[3 * a + c];
-                        xr[3 * a + c] += p->dt * vr[3 * a + c];
+                if (p->langevin) {
+                    for (int a = 0; a < n; ++a) {
+                        double h = 0.5 * p->dt / s->mass[a];
+                        double sd = sqrt(p->kB * p->T / s->mass[a]);
+                        uint32_t w[4];
+                        double z[3];
+                        for (int c = 0; c < 3; ++c) {
+                            vr[3 * a + c] += h * F[3 * a + c];
+                            xr[3 * a + c] += 0.5 * p->dt * vr[3 * a + c];
+                        }
+                        draw(g, sl, step, (uint32_t)a, ST_LANGEVIN, w);
+                        normals3(w, z);
+                        for (int c = 0; c < 3; ++c) {
+                            vr[3 * a + c] = c1 * vr[3 * a + c] + c2 * sd * z[c];
+                            xr[3 * a + c] += 0.5 * p->dt * vr[3 * a + c];
+                        }
+                    }
+                } else {
+                    for (int a = 0; a < n; ++a) {
+                        double h = 0.5 * p->dt / s->mass[a];
+                        for (int c = 0; c < 3; ++c) {
+                            vr[3 * a + c] += h * F[3 * a + c];
+                            xr[3 * a + c] += p->dt * vr[3 * a + c];
+                        }
                     }
                 }
                 ora_energy_forces(s, xr, F, NULL, p->mask);
@@ -383,7 +415,7 @@ void ora_md_steps(const ora_sys* s, const ora_rng* g, const ora_md* p, int32_t R
                     for (int c = 0; c < 3; ++c)
                         vr[3 * a + c] += h * F[3 * a + c];
                 }
-                if (p->p24 == 0)
+                if (p->langevin || p->p24 == 0)
                     continue;
                 for (int a = 0; a < n; ++a) {
                     uint32_t w[4];

@@ -58,7 +58,8 @@ class _OraRng(C.Structure):
 
 class _OraMd(C.Structure):
     _fields_ = [("dt", C.c_double), ("kB", C.c_double), ("T", C.c_double), ("p24", C.c_uint32),
-                ("step0", C.c_uint32), ("n_steps", C.c_int32), ("mask", C.c_int32)]
+                ("step0", C.c_uint32), ("n_steps", C.c_int32), ("mask", C.c_int32),
+                ("gamma", C.c_double), ("langevin", C.c_int32), ("pad", C.c_int32)]
 
 
 _lib = None
@@ -229,9 +230,11 @@ def init_velocities(osys: OracleSystem, R: int, T: float, seed: int, run: int = 
 
 def md_steps(osys: OracleSystem, x: np.ndarray, v: np.ndarray, n_steps: int, T: float, dt: float,
              nu: float, seed: int, step0: int, run: int = 0, slots: Optional[np.ndarray] = None,
-             mask: int = T_ALL, p24: Optional[int] = None, want_collisions: bool = False):
-    """PAMD step 3 on every replica (in place on x, v [R, n, 3]).
-    Returns (E_pot [R], E_kin [R][, collisions [R]])."""
+             mask: int = T_ALL, p24: Optional[int] = None, want_collisions: bool = False,
+             thermostat: str = "andersen"):
+    """PAMD step 3 on every replica (in place on x, v [R, n, 3]).  thermostat
+    "andersen" (nu = collision frequency) or "langevin" (nu = friction gamma,
+    B-A-O-A-B splitting).  Returns (E_pot [R], E_kin [R][, collisions [R]])."""
     assert x.flags.c_contiguous and v.flags.c_contiguous and x.dtype == np.float64
     R = x.shape[0]
     g = _rng(seed, run)
@@ -239,6 +242,10 @@ def md_steps(osys: OracleSystem, x: np.ndarray, v: np.ndarray, n_steps: int, T: 
     p.dt = dt; p.kB = osys.kB; p.T = float(T)
     p.p24 = collision_p24(nu, dt) if p24 is None else int(p24)
     p.step0 = int(step0); p.n_steps = int(n_steps); p.mask = mask
+    p.langevin = {"andersen": 0, "langevin": 1}[thermostat]
+    p.gamma = float(nu)
+    if p.langevin:
+        p.p24 = 0
     Ep = np.zeros(R)
     Ek = np.zeros(R)
     col = np.zeros(R, np.int64) if want_collisions else None
@@ -393,7 +400,8 @@ class AnnealResult:
 def anneal(sysd, R: int, T0: float, schedule: Optional[Sequence[float]], theta: int, theta_eq: int,
            dt: float, nu: float, seed: int, T_final: Optional[float] = None, v_target: float = 0.1,
            x0: Optional[np.ndarray] = None, v0: Optional[np.ndarray] = None, run: int = 0,
-           resampling: str = "nearest", max_temps: int = 10000) -> AnnealResult:
+           resampling: str = "nearest", max_temps: int = 10000,
+           thermostat: str = "andersen") -> AnnealResult:
     """Plain PAMD run.  schedule: list of temperatures T_0 > T_1 > ... (T_0 = T0),
     or None for the adaptive choice (normalised weight variance = v_target,
     down to T_final).  x0/v0 optionally give the initial population.
@@ -410,7 +418,7 @@ def anneal(sysd, R: int, T0: float, schedule: Optional[Sequence[float]], theta: 
     v = init_velocities(osys, R, T0, seed, run) if v0 is None else np.ascontiguousarray(v0).copy()
     anc = np.arange(R, dtype=np.int64)
     step = 0
-    Ep, Ek = md_steps(osys, x, v, theta_eq, T0, dt, nu, seed, step, run)
+    Ep, Ek = md_steps(osys, x, v, theta_eq, T0, dt, nu, seed, step, run, thermostat=thermostat)
     step += theta_eq
     res = AnnealResult()
     res.T.append(T0); res.R.append(R); res.lnQ.append(0.0)
@@ -435,7 +443,7 @@ def anneal(sysd, R: int, T0: float, schedule: Optional[Sequence[float]], theta: 
         x, v, Ep, anc = gather(c, [x, v, Ep, anc])
         x = np.ascontiguousarray(recentre(x, osys.mass))
         v = np.ascontiguousarray(v * math.sqrt(T_next / T_prev))
-        Ep, Ek = md_steps(osys, x, v, theta, T_next, dt, nu, seed, step, run)
+        Ep, Ek = md_steps(osys, x, v, theta, T_next, dt, nu, seed, step, run, thermostat=thermostat)
         step += theta
         res.T.append(T_next); res.R.append(len(Ep)); res.lnQ.append(lq)
         res.obs.append(observables(Ep, Ek, anc, n, kB, T_next))
