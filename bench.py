@@ -112,6 +112,16 @@ def cpu_baseline_batched(systems, R_each: int, seconds_target: float = 15.0):
                        f"{ {k: round(r) for k, r in rates.items()} } combined at equal populations")
 
 
+def _attainable(result):
+    """Adds the measured ceiling of FP32 VALU work without packed FP32 (every
+    kernel here is built that way): a kernel of independent FMAs, timed live."""
+    from paper_1806_06016_amd import pamd
+    rate = pamd.fp32_fma_rate()
+    rf = result["roofline"]
+    rf["attainable_unpacked_fp32"] = rate
+    rf["frac_of_attainable"] = rf["achieved"] / rate
+
+
 def batched(args):
     """Eight independent runs of seeded peptides with 40, 75, 75, 120, 150,
     200, 250 and 300 atoms, R = 4096 each, in one persistent launch per MD
@@ -180,9 +190,10 @@ def batched(args):
                      "traffic": measured_traffic("k_md_wide_traffic.txt") if R == 4096 and args.theta == 1000
                      else None},
     }
+    p.close()
+    _attainable(result)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline_batched(systems, R, args.cpu_seconds)
-    p.close()
     return result
 
 
@@ -201,6 +212,10 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (calibrates HBM byte counters)")
+    ap.add_argument("--resampling", choices=("nearest", "multinomial", "none"), default="nearest",
+                    help="copy-number rule of the resampling step (none: annealing without resampling)")
+    ap.add_argument("--thermostat", choices=("andersen", "langevin"), default="andersen",
+                    help="heat bath of the MD steps (langevin: friction 1/ps, B-A-O-A-B)")
     ap.add_argument("--workload", choices=("peptide", "batched"), default="peptide",
                     help="peptide: one 75-atom run at R=1e5 (the headline); batched: 8 uneven peptides "
                          "(40..300 atoms, R=4096 each) in one persistent launch")
@@ -228,7 +243,8 @@ def main():
         tuned = autotune(sysd, PAMD_FP32)
         waves = tuned["waves_per_block"]
     p = Pamd([sysd], R_target=R, T0=T0, dt=dt, nu=nu, seed=seed, precision=PAMD_FP32,
-             V_target=0.1, T_final=T_final, waves_per_block=waves)
+             V_target=0.1, T_final=T_final, waves_per_block=waves, resampling=args.resampling,
+             thermostat=args.thermostat)
     info = p.launch_info()
     stream = torch.cuda.current_stream()
     if args.copy_mb > 0:
@@ -248,15 +264,22 @@ def main():
         p.graph_capture(args.theta, "adaptive", slot=1, parts="md")
 
     ev_md = []
+    ev_rs = []
     R_steps = 0
 
     def temperature_step(record: bool):
         nonlocal R_steps
+        if record:
+            r0 = torch.cuda.Event(enable_timing=True)
+            r1 = torch.cuda.Event(enable_timing=True)
+            r0.record(stream)
         if use_graph:
             p.graph_launch(0)
         else:
             p.resample(None)
         if record:
+            r1.record(stream)
+            ev_rs.append((r0, r1))
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record(stream)
@@ -281,6 +304,11 @@ def main():
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     md_ms = [a.elapsed_time(b) for a, b in ev_md]
+    rs_ms = [a.elapsed_time(b) for a, b in ev_rs]
+    # gather traffic of one resampling: read + write of R 6 x npad FP32 slabs
+    # (npad = 80 for the 75-atom peptide), energies and ancestors
+    slab_bytes = 6 * 80 * 4
+    gather_bytes = R * (2 * slab_bytes + 2 * 8 + 2 * 4)
     md_s = sum(md_ms) / 1e3
     value = R_steps / el
     achieved = flops_rs * R_steps / md_s / 1e12
@@ -298,21 +326,26 @@ def main():
         "dtype": "f32 (FP64 energy sums, weights, Q)",
         "data": "synthetic",
         "config": {"workload": "PAMD, 75-atom synthetic peptide, R=1e5, theta=1000, adaptive T (V=0.1), "
-                               "dt=1 fs, Andersen nu=1/ps",
-                   "replicas": R, "theta": args.theta, "atoms": sysd.n_atoms, "pairs": pairs,
+                               "dt=1 fs, " + ("Andersen nu=1/ps" if args.thermostat == "andersen"
+                                              else "Langevin gamma=1/ps (B-A-O-A-B)"),
+                   "resampling": args.resampling, "thermostat": args.thermostat, "replicas": R, "theta": args.theta, "atoms": sysd.n_atoms, "pairs": pairs,
                    "T_range": [obs_log[0]["T"], obs_log[-1]["T"]]},
         "pair_interactions_per_s": value * pairs,
         "md_kernel_ms_avg": float(np.mean(md_ms)),
         "md_replica_steps_per_s": R_steps / md_s,
+        "resampling": {"mode": args.resampling, "ms_avg": float(np.mean(rs_ms)),
+                       "gather_bytes": gather_bytes,
+                       "GB_per_s_whole_step": gather_bytes / (float(np.mean(rs_ms)) * 1e-3) / 1e9},
         "launch": dict(info, graph=use_graph, autotune=tuned),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_VALU_TFLOPS,
                      "traffic": measured_traffic() if R == 100000 and args.theta == 1000 else None,
                      "flops_per_replica_step": flops_rs},
     }
+    p.close()
+    _attainable(result)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(sysd, args.cpu_seconds)
-    p.close()
     print(json.dumps(result))
 
 

@@ -66,6 +66,16 @@ enum { PAMD_FP64 = 0, PAMD_FP32 = 1 };
  *   NONE         c_j = 1: resampling switched off (the paper's "anneal" ablation);
  *                the rescale, recentring and ln Q bookkeeping still run. */
 enum { PAMD_RESAMPLE_NEAREST = 0, PAMD_RESAMPLE_MULTINOMIAL = 1, PAMD_RESAMPLE_NONE = 2 };
+/* Heat bath of the MD steps (pamd_params.thermostat):
+ *   ANDERSEN  velocity Verlet; after each step every atom collides with
+ *             probability 1 - exp(-nu dt) and takes a Maxwell-Boltzmann velocity.
+ *   LANGEVIN  the paper's stochastic bath (friction gamma = nu, a distinct random
+ *             stream per replica) in the B-A-O-A-B velocity-Verlet splitting
+ *             (Leimkuhler & Matthews 2013): v += dt/2 F/m; x += dt/2 v;
+ *             v = c1 v + sqrt(1 - c1^2) sqrt(kB T/m) xi with c1 = exp(-gamma dt) and
+ *             xi from Philox stream 5, counter (slot, step, atom, 5); x += dt/2 v;
+ *             F = F(x); v += dt/2 F/m.  Not combined with pamd_set_mts. */
+enum { PAMD_THERMOSTAT_ANDERSEN = 0, PAMD_THERMOSTAT_LANGEVIN = 1 };
 enum { PAMD_DIELECTRIC_VACUUM = 0, PAMD_DIELECTRIC_4R = 1 };
 
 #define PAMD_MAX_ATOMS 320   /* FP32; FP64 runs take at most 32 atoms */
@@ -119,14 +129,15 @@ typedef struct pamd_params {
     int64_t R_cap;                 /* slots per buffer, >= R_target (fluctuation headroom) */
     double T0;                     /* initial temperature */
     double dt;                     /* MD time step */
-    double nu;                     /* Andersen collision frequency (0: NVE) */
+    double nu;                     /* Andersen collision frequency, or Langevin friction gamma
+                                      (1/time; 0: NVE) */
     uint64_t seed;                 /* Philox key = (seed_lo, seed_hi + run) */
     int32_t precision;             /* PAMD_FP32 (positions, velocities, forces FP32) or PAMD_FP64 */
     int32_t waves_per_block;       /* 0: automatic; else 1..16 (autotuner override) */
     double V_target;               /* adaptive schedule: normalised weight variance per step */
     double T_final;                /* adaptive schedule: lowest temperature T_N */
     int32_t resampling;            /* PAMD_RESAMPLE_*: how pamd_resample draws the copy numbers */
-    int32_t reserved;              /* 0 */
+    int32_t thermostat;            /* PAMD_THERMOSTAT_*: the same for every run of a context */
 } pamd_params;
 
 /* Population observables of one run (PAMD step 4), all FP64. */
@@ -255,6 +266,14 @@ pamd_status pamd_launch_info(const pamd_ctx* ctx, int32_t* waves_per_block, int3
 
 void pamd_destroy(pamd_ctx* ctx);
 const char* pamd_last_error(const pamd_ctx* ctx);
+
+/* Roofline calibration (no context): runs a kernel of independent FP32 FMAs
+ * (v_fma_f32; every kernel of this library is built without packed FP32
+ * instructions) over the whole GPU three times, about 18 ms each, and returns in
+ * *tflops the best rate in TFLOP/s (FMA = 2 flop): the ceiling of an FP32
+ * VALU-bound kernel of this library.  d_sink: device pointer to one float the
+ * kernel may write.  Synchronises `stream`. */
+pamd_status pamd_fp32_fma_rate(float* d_sink, double* tflops, void* stream);
 
 /* ---- learned multiple-time-step (MTS) surrogate --------------------------
  * Not part of the paper's scheme: an optional acceleration of the MD update

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libpamd.so")
-SOURCES = ["md_kernel.hip", "resample.hip", "runtime.hip", "nn_kernel.hip", "nn_runtime.hip"]
+SOURCES = ["md_kernel.hip", "resample.hip", "runtime.hip", "nn_kernel.hip", "nn_runtime.hip", "calib.hip"]
 ARCH = os.environ.get("PAMD_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

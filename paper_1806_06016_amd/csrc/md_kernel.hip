@@ -27,6 +27,7 @@
 #include <type_traits>
 #include <utility>
 
+#include "pamd.h"
 #include "pamd_internal.h"
 #include "philox.h"
 
@@ -547,10 +548,33 @@ __device__ __forceinline__ void andersen(Regs<real, NS>& r, const RunDev<real>& 
     }
 }
 
+// Ornstein-Uhlenbeck velocity step of the Langevin bath (the O of B-A-O-A-B):
+// v = c1 v + c2 sqrt(kT / m) xi, three normals per atom from stream 5 with
+// counter (slot, step, atom, 5)
+template <typename real, int NS>
+__device__ __forceinline__ void langevin_o(Regs<real, NS>& r, const RunDev<real>& d, uint32_t slot, uint32_t gstep,
+                                           real kT, const real* hdtm, real two_over_dt, real c1, real c2, int l16)
+{
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int a = 16 * s + l16;
+        if (a < d.n) {
+            const u32x4 w = philox10(slot, gstep, (uint32_t)a, kStreamLangevin, d.key0, d.key1);
+            real z[3];
+            normals3(w, z);
+            const real sd = c2 * sqrt_(kT * hdtm[s] * two_over_dt);
+            r.vx[s] = c1 * r.vx[s] + sd * z[0];
+            r.vy[s] = c1 * r.vy[s] + sd * z[1];
+            r.vz[s] = c1 * r.vz[s] + sd * z[2];
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
-// the persistent MD kernel
+// the persistent MD kernel (LANG: Langevin bath in the B-A-O-A-B splitting,
+// else velocity Verlet with Andersen collisions)
 // ---------------------------------------------------------------------------
-template <typename real, int NS, int DIEL>
+template <typename real, int NS, int DIEL, int LANG>
 __global__ __launch_bounds__(1024) void k_md(RunDev<real> d, int n_steps)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -630,14 +654,35 @@ __global__ __launch_bounds__(1024) void k_md(RunDev<real> d, int n_steps)
                                        l16);
             }
             if (st < n_steps) {
+                if constexpr (LANG) {
+                    const real hdt = (real)(0.5 * d.dt);
 #pragma unroll
-                for (int s = 0; s < NS; ++s) {
-                    r.vx[s] += hdtm[s] * r.fx[s];
-                    r.vy[s] += hdtm[s] * r.fy[s];
-                    r.vz[s] += hdtm[s] * r.fz[s];
-                    r.x[s] += dt * r.vx[s];
-                    r.y[s] += dt * r.vy[s];
-                    r.z[s] += dt * r.vz[s];
+                    for (int s = 0; s < NS; ++s) {
+                        r.vx[s] += hdtm[s] * r.fx[s];
+                        r.vy[s] += hdtm[s] * r.fy[s];
+                        r.vz[s] += hdtm[s] * r.fz[s];
+                        r.x[s] += hdt * r.vx[s];
+                        r.y[s] += hdt * r.vy[s];
+                        r.z[s] += hdt * r.vz[s];
+                    }
+                    langevin_o<real, NS>(r, d, (uint32_t)ls, step0 + (uint32_t)st, kT, hdtm, two_over_dt,
+                                         (real)d.lc1, (real)d.lc2, l16);
+#pragma unroll
+                    for (int s = 0; s < NS; ++s) {
+                        r.x[s] += hdt * r.vx[s];
+                        r.y[s] += hdt * r.vy[s];
+                        r.z[s] += hdt * r.vz[s];
+                    }
+                } else {
+#pragma unroll
+                    for (int s = 0; s < NS; ++s) {
+                        r.vx[s] += hdtm[s] * r.fx[s];
+                        r.vy[s] += hdtm[s] * r.fy[s];
+                        r.vz[s] += hdtm[s] * r.fz[s];
+                        r.x[s] += dt * r.vx[s];
+                        r.y[s] += dt * r.vy[s];
+                        r.z[s] += dt * r.vz[s];
+                    }
                 }
             }
         }
@@ -1135,7 +1180,7 @@ __device__ __forceinline__ void wide_store(const WideRegs& r, const RunDev<float
 // hands out (run, replica) items, runs in decreasing order of pair work
 // (`order`), replicas of a run in slot order.  n_steps velocity-Verlet steps
 // with Andersen collisions, then E_pot (FP64 sum) and E_kin of the final state.
-template <int DIEL>
+template <int DIEL, int LANG>
 __global__ __launch_bounds__(256, 3) void k_md_wide(const RunDev<float>* runs, const int32_t* order, int n_runs,
                                                   int32_t* counter, int nmax, int n_steps)
 {
@@ -1217,14 +1262,44 @@ __global__ __launch_bounds__(256, 3) void k_md_wide(const RunDev<float>* runs, c
                 }
             }
             if (st < n_steps) {
+                if constexpr (LANG) {
+                    // B-A-O-A-B: half kick, half drift, OU step, half drift
+                    const float hdt = (float)(0.5 * d.dt);
+                    const float c1 = (float)d.lc1, c2 = (float)d.lc2;
+                    const uint32_t gstep = step0 + (uint32_t)st;
 #pragma unroll
-                for (int s = 0; s < kWideSlots; ++s) {
-                    r.vx[s] += hdtm[s] * r.fx[s];
-                    r.vy[s] += hdtm[s] * r.fy[s];
-                    r.vz[s] += hdtm[s] * r.fz[s];
-                    r.x[s] += dt * r.vx[s];
-                    r.y[s] += dt * r.vy[s];
-                    r.z[s] += dt * r.vz[s];
+                    for (int s = 0; s < kWideSlots; ++s) {
+                        r.vx[s] += hdtm[s] * r.fx[s];
+                        r.vy[s] += hdtm[s] * r.fy[s];
+                        r.vz[s] += hdtm[s] * r.fz[s];
+                        r.x[s] += hdt * r.vx[s];
+                        r.y[s] += hdt * r.vy[s];
+                        r.z[s] += hdt * r.vz[s];
+                        const int a = kWide * s + lane;
+                        if (s < nsl && a < d.n) {
+                            const u32x4 w = philox10((uint32_t)rep, gstep, (uint32_t)a, kStreamLangevin, d.key0,
+                                                     d.key1);
+                            float zz[3];
+                            normals3(w, zz);
+                            const float sd = c2 * sqrt_(kT * hdtm[s] * two_over_dt);
+                            r.vx[s] = c1 * r.vx[s] + sd * zz[0];
+                            r.vy[s] = c1 * r.vy[s] + sd * zz[1];
+                            r.vz[s] = c1 * r.vz[s] + sd * zz[2];
+                        }
+                        r.x[s] += hdt * r.vx[s];
+                        r.y[s] += hdt * r.vy[s];
+                        r.z[s] += hdt * r.vz[s];
+                    }
+                } else {
+#pragma unroll
+                    for (int s = 0; s < kWideSlots; ++s) {
+                        r.vx[s] += hdtm[s] * r.fx[s];
+                        r.vy[s] += hdtm[s] * r.fy[s];
+                        r.vz[s] += hdtm[s] * r.fz[s];
+                        r.x[s] += dt * r.vx[s];
+                        r.y[s] += dt * r.vy[s];
+                        r.z[s] += dt * r.vz[s];
+                    }
                 }
             }
         }
@@ -1310,7 +1385,10 @@ template <typename real, int NS, int DIEL>
 static hipError_t launch_md_t(const RunDev<real>& d, int n_steps, int blocks, int waves, hipStream_t s)
 {
     const size_t lds = md_lds_bytes<real>(NS, d.n, waves);
-    hipLaunchKernelGGL((k_md<real, NS, DIEL>), dim3(blocks), dim3(waves * 64), lds, s, d, n_steps);
+    if (d.thermostat == PAMD_THERMOSTAT_LANGEVIN)
+        hipLaunchKernelGGL((k_md<real, NS, DIEL, 1>), dim3(blocks), dim3(waves * 64), lds, s, d, n_steps);
+    else
+        hipLaunchKernelGGL((k_md<real, NS, DIEL, 0>), dim3(blocks), dim3(waves * 64), lds, s, d, n_steps);
     return hipGetLastError();
 }
 
@@ -1360,11 +1438,12 @@ template <typename real, int NS, int DIEL>
 static hipError_t occupancy_t(int waves, int* blocks_per_cu, int n)
 {
     const size_t lds = md_lds_bytes<real>(NS, n, waves);
-    const void* fns[5] = {(const void*)k_md<real, NS, DIEL>, (const void*)k_energy<real, NS, DIEL>,
-                          (const void*)k_forces<real, NS, DIEL>, nullptr, nullptr};
+    const void* fns[6] = {(const void*)k_md<real, NS, DIEL, 0>, (const void*)k_energy<real, NS, DIEL>,
+                          (const void*)k_forces<real, NS, DIEL>, (const void*)k_md<real, NS, DIEL, 1>, nullptr,
+                          nullptr};
     if constexpr (sizeof(real) == 4) {
-        fns[3] = (const void*)k_respa<NS, DIEL>;
-        fns[4] = (const void*)k_export<NS, DIEL>;
+        fns[4] = (const void*)k_respa<NS, DIEL>;
+        fns[5] = (const void*)k_export<NS, DIEL>;
     }
     for (const void* f : fns) {
         if (!f)
@@ -1373,8 +1452,15 @@ static hipError_t occupancy_t(int waves, int* blocks_per_cu, int n)
         if (e != hipSuccess)
             return e;
     }
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, (const void*)k_md<real, NS, DIEL>,
-                                                        waves * 64, lds);
+    // the Langevin variant needs a few more registers: the smaller occupancy of the two
+    int b0 = 0, b1 = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b0, (const void*)k_md<real, NS, DIEL, 0>,
+                                                                waves * 64, lds);
+    if (e != hipSuccess)
+        return e;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b1, (const void*)k_md<real, NS, DIEL, 1>, waves * 64, lds);
+    *blocks_per_cu = b0 < b1 ? b0 : b1;
+    return e;
 }
 
 #define PAMD_DISPATCH(REAL, NSV, DIELV, CALL)                                                    \
@@ -1456,26 +1542,34 @@ size_t wide_lds_bytes(int nmax, int waves) { return (size_t)waves * 6 * nmax * s
 hipError_t wide_setup(int diel, int nmax, int waves, int* blocks_per_cu)
 {
     const size_t lds = wide_lds_bytes(nmax, waves);
-    const void* md = diel ? (const void*)k_md_wide<1> : (const void*)k_md_wide<0>;
+    const void* md = diel ? (const void*)k_md_wide<1, 0> : (const void*)k_md_wide<0, 0>;
+    const void* ml = diel ? (const void*)k_md_wide<1, 1> : (const void*)k_md_wide<0, 1>;
     const void* fo = diel ? (const void*)k_forces_wide<1> : (const void*)k_forces_wide<0>;
-    for (const void* f : {md, fo}) {
+    for (const void* f : {md, ml, fo}) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess)
             return e;
     }
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, md, waves * 64, lds);
+    int b0 = 0, b1 = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b0, md, waves * 64, lds);
+    if (e != hipSuccess)
+        return e;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b1, ml, waves * 64, lds);
+    *blocks_per_cu = b0 < b1 ? b0 : b1;
+    return e;
 }
 
 hipError_t launch_md_wide(const RunDev<float>* runs, const int32_t* order, int n_runs, int32_t* counter, int nmax,
-                          int n_steps, int diel, int blocks, int waves, hipStream_t s)
+                          int n_steps, int diel, int lang, int blocks, int waves, hipStream_t s)
 {
     const size_t lds = wide_lds_bytes(nmax, waves);
-    if (diel)
-        hipLaunchKernelGGL(k_md_wide<1>, dim3(blocks), dim3(waves * 64), lds, s, runs, order, n_runs, counter, nmax,
-                           n_steps);
-    else
-        hipLaunchKernelGGL(k_md_wide<0>, dim3(blocks), dim3(waves * 64), lds, s, runs, order, n_runs, counter, nmax,
-                           n_steps);
+    const dim3 g(blocks), b(waves * 64);
+    switch (diel * 2 + lang) {
+    case 0: hipLaunchKernelGGL((k_md_wide<0, 0>), g, b, lds, s, runs, order, n_runs, counter, nmax, n_steps); break;
+    case 1: hipLaunchKernelGGL((k_md_wide<0, 1>), g, b, lds, s, runs, order, n_runs, counter, nmax, n_steps); break;
+    case 2: hipLaunchKernelGGL((k_md_wide<1, 0>), g, b, lds, s, runs, order, n_runs, counter, nmax, n_steps); break;
+    default: hipLaunchKernelGGL((k_md_wide<1, 1>), g, b, lds, s, runs, order, n_runs, counter, nmax, n_steps); break;
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;

@@ -86,6 +86,8 @@ struct RunDev {
     int32_t dielectric;
     int32_t waves_per_block;
     int32_t resampling;     // PAMD_RESAMPLE_*
+    int32_t thermostat;     // PAMD_THERMOSTAT_*
+    double lc1, lc2;        // Langevin: exp(-gamma dt), sqrt(1 - exp(-2 gamma dt))
     // wide layout only: per-atom (sigma / 2, 2 sqrt(eps), q sqrt(k_e c), 0) with
     // c = 1/2 for eps = 4r and 1 in vacuum, and per (atom, 32-atom chunk) the
     // bit masks (excluded pair incl. self, scaled 1-4 pair)

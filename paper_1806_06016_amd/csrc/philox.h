@@ -13,6 +13,7 @@
 //   stream 3  initial Maxwell-Boltzmann velocity of atom a: block a
 //   stream 4  multinomial resampling: uniform of draw k in the slot word,
 //             step word = temperature index
+//   stream 5  Langevin noise of atom a: block a, three normals per step
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -49,7 +50,8 @@ enum : uint32_t {
     kStreamVelocity = 1,
     kStreamResample = 2,
     kStreamInit = 3,
-    kStreamMultinomial = 4
+    kStreamMultinomial = 4,
+    kStreamLangevin = 5
 };
 
 // 53-bit uniform in [0, 1) from two words

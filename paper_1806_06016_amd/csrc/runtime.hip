@@ -40,7 +40,7 @@ hipError_t launch_export(const RunDev<float>& d, int64_t r0, int64_t count, floa
 size_t wide_lds_bytes(int nmax, int waves);
 hipError_t wide_setup(int diel, int nmax, int waves, int* blocks_per_cu);
 hipError_t launch_md_wide(const RunDev<float>* runs, const int32_t* order, int n_runs, int32_t* counter, int nmax,
-                          int n_steps, int diel, int blocks, int waves, hipStream_t s);
+                          int n_steps, int diel, int lang, int blocks, int waves, hipStream_t s);
 hipError_t launch_forces_wide(const RunDev<float>& d, int64_t r0, int count, int nmax, int waves, hipStream_t s);
 }  // namespace pamd
 
@@ -213,6 +213,8 @@ pamd_status validate(pamd_ctx* c, const pamd_system& s, const pamd_params& p, in
         return fail(c, PAMD_ERR_ARG, "waves_per_block must be 0..16");
     if (p.resampling < PAMD_RESAMPLE_NEAREST || p.resampling > PAMD_RESAMPLE_NONE)
         return fail(c, PAMD_ERR_ARG, "unknown resampling mode");
+    if (p.thermostat != PAMD_THERMOSTAT_ANDERSEN && p.thermostat != PAMD_THERMOSTAT_LANGEVIN)
+        return fail(c, PAMD_ERR_ARG, "unknown thermostat");
     return PAMD_OK;
 }
 
@@ -406,7 +408,11 @@ void carve(Carver& st, Carver& wk, const pamd_system& s, const pamd_params& p, i
     d.T0 = p.T0;
     d.V_target = p.V_target > 0 ? p.V_target : 0.1;
     d.T_final = p.T_final > 0 ? p.T_final : p.T0;
-    d.p24 = (uint32_t)llround((1.0 - exp(-p.nu * p.dt)) * 16777216.0);
+    d.thermostat = p.thermostat;
+    d.p24 = p.thermostat == PAMD_THERMOSTAT_ANDERSEN ? (uint32_t)llround((1.0 - exp(-p.nu * p.dt)) * 16777216.0)
+                                                     : 0u;
+    d.lc1 = exp(-p.nu * p.dt);
+    d.lc2 = sqrt(1.0 - d.lc1 * d.lc1);
     d.key0 = (uint32_t)(p.seed & 0xFFFFFFFFu);
     d.key1 = (uint32_t)(p.seed >> 32) + (uint32_t)run;
     d.dielectric = s.dielectric;
@@ -548,7 +554,7 @@ pamd_status pamd_query_sizes(const pamd_system* sys, int32_t n_runs, const pamd_
         return PAMD_ERR_ARG;
     const int fp32 = p[0].precision == PAMD_FP32;
     for (int r = 0; r < n_runs; ++r) {
-        if (p[r].precision != p[0].precision)
+        if (p[r].precision != p[0].precision || p[r].thermostat != p[0].thermostat)
             return PAMD_ERR_ARG;
         pamd_status st = validate(nullptr, sys[r], p[r], fp32);
         if (st != PAMD_OK)
@@ -729,8 +735,8 @@ pamd_status pamd_md_steps(pamd_ctx* c, int32_t n_steps, void* stream)
     c->have_energy = 1;
     hipStream_t s = as_stream(stream);
     if (c->wide) {
-        HIPCHK(c, launch_md_wide(c->d_runs, c->d_order, c->n_runs, c->d_counter, c->nmax, n_steps, c->diel, c->blocks,
-                                 c->waves, s));
+        HIPCHK(c, launch_md_wide(c->d_runs, c->d_order, c->n_runs, c->d_counter, c->nmax, n_steps, c->diel,
+                                 c->runs[0].f.thermostat == PAMD_THERMOSTAT_LANGEVIN, c->blocks, c->waves, s));
         return PAMD_OK;
     }
     if (c->nn && n_steps > 0) {
@@ -1139,6 +1145,8 @@ pamd_status pamd_set_mts(pamd_ctx* c, pamd_nn* nn, int32_t outer_ratio, void* st
                                          std::to_string(PAMD_TILE_ATOMS) + " atoms");
     if (outer_ratio < 1)
         return fail(c, PAMD_ERR_ARG, "outer_ratio must be >= 1");
+    if (c->runs[0].f.thermostat != PAMD_THERMOSTAT_ANDERSEN)
+        return fail(c, PAMD_ERR_ARG, "r-RESPA with the surrogate runs with the Andersen bath only");
     for (auto& run : c->runs)
         if (run.f.n != nn->topo.n)
             return fail(c, PAMD_ERR_ARG, "surrogate atom count differs from a run's");

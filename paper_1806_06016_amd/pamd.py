@@ -18,6 +18,8 @@ LIB_PATH = os.path.join(_HERE, "libpamd.so")
 PAMD_OK, PAMD_ERR_ARG, PAMD_ERR_HIP, PAMD_ERR_CAPACITY, PAMD_ERR_NONFINITE, PAMD_ERR_STATE = range(6)
 PAMD_FP64, PAMD_FP32 = 0, 1
 PAMD_RESAMPLE_NEAREST, PAMD_RESAMPLE_MULTINOMIAL, PAMD_RESAMPLE_NONE = 0, 1, 2
+PAMD_THERMOSTAT_ANDERSEN, PAMD_THERMOSTAT_LANGEVIN = 0, 1
+THERMOSTATS = {"andersen": PAMD_THERMOSTAT_ANDERSEN, "langevin": PAMD_THERMOSTAT_LANGEVIN}
 RESAMPLING_MODES = {"nearest": PAMD_RESAMPLE_NEAREST, "multinomial": PAMD_RESAMPLE_MULTINOMIAL,
                     "none": PAMD_RESAMPLE_NONE}
 PAMD_FORCE_CHUNK = 256
@@ -49,7 +51,7 @@ class pamd_params(C.Structure):
         ("R_target", C.c_int64), ("R_cap", C.c_int64), ("T0", C.c_double), ("dt", C.c_double),
         ("nu", C.c_double), ("seed", C.c_uint64), ("precision", C.c_int32),
         ("waves_per_block", C.c_int32), ("V_target", C.c_double), ("T_final", C.c_double),
-        ("resampling", C.c_int32), ("reserved", C.c_int32),
+        ("resampling", C.c_int32), ("thermostat", C.c_int32),
     ]
 
 
@@ -74,7 +76,7 @@ EXPORTS = ["pamd_query_sizes", "pamd_init", "pamd_md_steps", "pamd_resample", "p
            "pamd_launch_info", "pamd_destroy", "pamd_last_error",
            "pamd_nn_create", "pamd_nn_set_weights", "pamd_nn_get_weights", "pamd_nn_forces",
            "pamd_nn_loss_grad", "pamd_nn_train_step", "pamd_nn_destroy", "pamd_nn_last_error",
-           "pamd_export_configs", "pamd_set_mts"]
+           "pamd_export_configs", "pamd_set_mts", "pamd_fp32_fma_rate"]
 NN_PARAMS = 49537
 NN_FEATURES, NN_HIDDEN, NN_TYPES = 256, 128, 8
 _NO_STATUS = ("pamd_destroy", "pamd_last_error", "pamd_nn_destroy", "pamd_nn_last_error")
@@ -132,6 +134,20 @@ def load_library(path: str = LIB_PATH):
     return lib
 
 
+def fp32_fma_rate() -> float:
+    """TFLOP/s of independent FP32 FMAs on the current GPU (the ceiling of this
+    library's FP32 VALU-bound kernels, built without packed FP32)."""
+    import torch
+    lib = load_library()
+    sink = torch.zeros(1, dtype=torch.float32, device="cuda")
+    out = C.c_double()
+    st = lib.pamd_fp32_fma_rate(C.c_void_p(sink.data_ptr()), C.byref(out),
+                                C.c_void_p(torch.cuda.current_stream().cuda_stream))
+    if st != PAMD_OK:
+        raise PamdError(st, "FMA-rate calibration failed")
+    return out.value
+
+
 def _ptr(a: Optional[np.ndarray]):
     return None if a is None else a.ctypes.data
 
@@ -169,9 +185,10 @@ class Pamd:
     def __init__(self, systems: Sequence, R_target: int, T0: float, dt: float, nu: float, seed: int,
                  precision: int = PAMD_FP32, R_cap: Optional[int] = None, V_target: float = 0.1,
                  T_final: Optional[float] = None, waves_per_block: int = 0, stream=None,
-                 resampling="nearest"):
+                 resampling="nearest", thermostat: str = "andersen"):
         """resampling: "nearest", "multinomial" or "none" for every run, or one
-        mode per run (a sequence)."""
+        mode per run (a sequence).  thermostat: "andersen" (nu = collision
+        frequency) or "langevin" (nu = friction gamma), one for the context."""
         import torch
         self.torch = torch
         self.lib = load_library()
@@ -199,6 +216,7 @@ class Pamd:
             p.T_final = float(T_final if T_final is not None else T0)
             mode = resampling if isinstance(resampling, str) else resampling[r]
             p.resampling = RESAMPLING_MODES[mode]
+            p.thermostat = THERMOSTATS[thermostat]
             prm.append(p)
         self._prm = P(*prm)
         sb, wb = C.c_size_t(), C.c_size_t()

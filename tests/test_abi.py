@@ -14,7 +14,7 @@ LIB = os.path.join(ROOT, "paper_1806_06016_amd", "libpamd.so")
 
 def _declared_functions():
     txt = open(HEADER).read()
-    return sorted(set(re.findall(r"\b(pamd_[a-z_]+)\s*\(", txt)))
+    return sorted(set(re.findall(r"\b(pamd_[a-z0-9_]+)\s*\(", txt)))
 
 
 def _struct_fields(name):
@@ -81,6 +81,17 @@ def test_query_sizes_is_host_only_and_validates():
         assert lib.pamd_query_sizes(ctypes.byref(s), 1, ctypes.byref(p), ctypes.byref(sb),
                                     ctypes.byref(wb)) == want
     p.resampling = B.PAMD_RESAMPLE_NEAREST
+    p.thermostat = 2                           # no such bath
+    assert lib.pamd_query_sizes(ctypes.byref(s), 1, ctypes.byref(p), ctypes.byref(sb),
+                                ctypes.byref(wb)) == B.PAMD_ERR_ARG
+    p.thermostat = B.PAMD_THERMOSTAT_LANGEVIN
+    assert lib.pamd_query_sizes(ctypes.byref(s), 1, ctypes.byref(p), ctypes.byref(sb),
+                                ctypes.byref(wb)) == 0
+    two_s = (B.pamd_system * 2)(s, s)
+    two_p = (B.pamd_params * 2)(p, p)
+    two_p[1].thermostat = B.PAMD_THERMOSTAT_ANDERSEN   # one bath per context
+    assert lib.pamd_query_sizes(two_s, 2, two_p, ctypes.byref(sb), ctypes.byref(wb)) == B.PAMD_ERR_ARG
+    p.thermostat = B.PAMD_THERMOSTAT_ANDERSEN
     bad = S.c2_system()
     bad.dih_delta = bad.dih_delta + 0.3        # only 0 / pi phases are supported
     sb2 = B.make_system_struct(bad, keep)
