@@ -267,6 +267,52 @@ pamd_status pamd_launch_info(const pamd_ctx* ctx, int32_t* waves_per_block, int3
 void pamd_destroy(pamd_ctx* ctx);
 const char* pamd_last_error(const pamd_ctx* ctx);
 
+/*
+ * Population analysis (host, FP64, no context, no GPU; host pointers only).
+ *
+ * Copies made by resampling are correlated, which the errors of population
+ * averages must respect (the paragraph on correlations after resampling:
+ * binning over the population).  A family is all copies descending from one
+ * initial replica (equal `ancestor`, as pamd_get_state returns it).
+ *   mean        (1/R) sum_j O_j
+ *   naive_se    sqrt( sum_j (O_j - mean)^2 / (R (R - 1)) )        (0 for R = 1)
+ *   family_se   sqrt( sum_f (sum_{j in f} (O_j - mean))^2 / (R (R - 1)) )
+ *   rho_t       R sum_f nu_f^2,  nu_f = n_f / R   (1 without resampling)
+ *   family_entropy  -sum_f nu_f ln nu_f          (exp of it: effective families)
+ * PAMD_ERR_ARG for null pointers or R < 1, PAMD_ERR_NONFINITE for a NaN/Inf value.
+ */
+typedef struct pamd_family_stats {
+    double mean, naive_se, family_se, rho_t, family_entropy;
+    int64_t families;
+} pamd_family_stats;
+pamd_status pamd_family_error(const double* O, const int32_t* ancestor, int64_t R, pamd_family_stats* out);
+
+/* Standard error of the mean from bins of `bin` consecutive slots (copies of
+ * one source occupy consecutive slots after each resampling): the first
+ * floor(R / bin) complete bins, se^2 = sum_k (m_k - m)^2 / ((n_b - 1) n_b).
+ * PAMD_ERR_ARG unless bin >= 1 and R / bin >= 2. */
+pamd_status pamd_binning_error(const double* O, int64_t R, int64_t bin, double* se);
+
+/*
+ * Multiple-histogram (WHAM) self-consistency in per-sample form (the paragraph
+ * on the recorded normalisers: sum ln Q gives ln Z(T_i) - ln Z(T_0) and the
+ * starting values).  Samples: E[n_samples[0]] at beta[0], then E[n_samples[1]]
+ * at beta[1], ... (e.g. the population's E_pot at each temperature).  With
+ *   ln D(E) = logsumexp_l (ln N_l - beta_l E - ln Z_l),
+ * each iteration sets ln Z_k = logsumexp_samples (-beta_k E - ln D(E)), shifted
+ * so that ln Z_0 keeps its input value, until the largest change is < tol or
+ * max_iter iterations.  lnZ[n_temps]: in = starting values (e.g. the running
+ * sum of ln Q), out = refined.  *iterations (optional) = iterations done.
+ * Deterministic for any thread count (fixed chunk order).
+ */
+pamd_status pamd_wham(int32_t n_temps, const double* beta, const int64_t* n_samples, const double* E,
+                      double* lnZ, int32_t max_iter, double tol, int32_t* iterations);
+
+/* <E> and <E^2> at inverse temperature beta_q by reweighting all samples with
+ * exp(-beta_q E) / D(E), D from converged ln Z (same sample layout). */
+pamd_status pamd_wham_average(int32_t n_temps, const double* beta, const int64_t* n_samples, const double* E,
+                              const double* lnZ, double beta_q, double* E_mean, double* E2_mean);
+
 /* Roofline calibration (no context): runs a kernel of independent FP32 FMAs
  * (v_fma_f32; every kernel of this library is built without packed FP32
  * instructions) over the whole GPU three times, about 18 ms each, and returns in

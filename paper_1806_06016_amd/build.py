@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libpamd.so")
-SOURCES = ["md_kernel.hip", "resample.hip", "runtime.hip", "nn_kernel.hip", "nn_runtime.hip", "calib.hip"]
+SOURCES = ["md_kernel.hip", "resample.hip", "runtime.hip", "nn_kernel.hip", "nn_runtime.hip", "calib.hip", "analysis.cpp"]
 ARCH = os.environ.get("PAMD_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [
@@ -40,7 +40,7 @@ def build(verbose: bool = False, extra_flags=()) -> str:
     hipcc = _hipcc()
 
     def compile_one(src):
-        obj = os.path.join(objdir, src.replace(".hip", ".o"))
+        obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
         cmd = [hipcc, *FLAGS, *extra_flags, "-c", os.path.join(CSRC, src), "-o", obj]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:

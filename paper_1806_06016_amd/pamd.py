@@ -76,7 +76,8 @@ EXPORTS = ["pamd_query_sizes", "pamd_init", "pamd_md_steps", "pamd_resample", "p
            "pamd_launch_info", "pamd_destroy", "pamd_last_error",
            "pamd_nn_create", "pamd_nn_set_weights", "pamd_nn_get_weights", "pamd_nn_forces",
            "pamd_nn_loss_grad", "pamd_nn_train_step", "pamd_nn_destroy", "pamd_nn_last_error",
-           "pamd_export_configs", "pamd_set_mts", "pamd_fp32_fma_rate"]
+           "pamd_export_configs", "pamd_set_mts", "pamd_fp32_fma_rate",
+           "pamd_family_error", "pamd_binning_error", "pamd_wham", "pamd_wham_average"]
 NN_PARAMS = 49537
 NN_FEATURES, NN_HIDDEN, NN_TYPES = 256, 128, 8
 _NO_STATUS = ("pamd_destroy", "pamd_last_error", "pamd_nn_destroy", "pamd_nn_last_error")
@@ -127,11 +128,71 @@ def load_library(path: str = LIB_PATH):
     lib.pamd_nn_last_error.restype = C.c_char_p
     lib.pamd_export_configs.argtypes = [vp, i32, i64, i64, vp, vp, vp]
     lib.pamd_set_mts.argtypes = [vp, vp, i32, vp]
+    lib.pamd_fp32_fma_rate.argtypes = [vp, vp, vp]
+    lib.pamd_family_error.argtypes = [vp, vp, i64, vp]
+    lib.pamd_binning_error.argtypes = [vp, i64, i64, vp]
+    lib.pamd_wham.argtypes = [i32, vp, vp, vp, vp, i32, C.c_double, vp]
+    lib.pamd_wham_average.argtypes = [i32, vp, vp, vp, vp, C.c_double, vp, vp]
     for name in EXPORTS:
         if name not in _NO_STATUS:
             getattr(lib, name).restype = i32
     _lib = lib
     return lib
+
+
+class pamd_family_stats(C.Structure):
+    _fields_ = [("mean", C.c_double), ("naive_se", C.c_double), ("family_se", C.c_double),
+                ("rho_t", C.c_double), ("family_entropy", C.c_double), ("families", C.c_int64)]
+
+
+def _host_check(st: int, what: str):
+    if st != PAMD_OK:
+        raise PamdError(st, what)
+
+
+def family_error(O, ancestor) -> Dict:
+    """Population mean of O with its naive and family (common-ancestor) errors,
+    rho_t and the family entropy (host, FP64)."""
+    O = np.ascontiguousarray(O, np.float64)
+    a = np.ascontiguousarray(ancestor, np.int32)
+    assert O.shape == a.shape and O.ndim == 1
+    out = pamd_family_stats()
+    _host_check(load_library().pamd_family_error(_ptr(O), _ptr(a), len(O), C.byref(out)), "family_error")
+    return {k: getattr(out, k) for k, _ in pamd_family_stats._fields_}
+
+
+def binning_error(O, bin_size: int) -> float:
+    O = np.ascontiguousarray(O, np.float64)
+    se = C.c_double()
+    _host_check(load_library().pamd_binning_error(_ptr(O), len(O), int(bin_size), C.byref(se)), "binning_error")
+    return se.value
+
+
+def _wham_args(beta, samples):
+    b = np.ascontiguousarray(beta, np.float64)
+    n = np.ascontiguousarray([len(s) for s in samples], np.int64)
+    E = np.ascontiguousarray(np.concatenate([np.asarray(s, np.float64) for s in samples]))
+    assert len(b) == len(n)
+    return b, n, E
+
+
+def wham(beta, samples, lnZ0, max_iter: int = 1000, tol: float = 1e-10):
+    """Refined ln Z [L] and the iteration count (see pamd_wham)."""
+    b, n, E = _wham_args(beta, samples)
+    lnZ = np.ascontiguousarray(lnZ0, np.float64).copy()
+    it = C.c_int32()
+    _host_check(load_library().pamd_wham(len(b), _ptr(b), _ptr(n), _ptr(E), _ptr(lnZ), int(max_iter), float(tol),
+                                         C.byref(it)), "wham")
+    return lnZ, it.value
+
+
+def wham_average(beta_q: float, beta, samples, lnZ):
+    b, n, E = _wham_args(beta, samples)
+    z = np.ascontiguousarray(lnZ, np.float64)
+    e1, e2 = C.c_double(), C.c_double()
+    _host_check(load_library().pamd_wham_average(len(b), _ptr(b), _ptr(n), _ptr(E), _ptr(z), float(beta_q),
+                                                 C.byref(e1), C.byref(e2)), "wham_average")
+    return e1.value, e2.value
 
 
 def fp32_fma_rate() -> float:

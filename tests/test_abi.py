@@ -46,7 +46,8 @@ def test_library_exports_every_declared_entry_point():
 def test_binding_structs_match_header():
     from paper_1806_06016_amd import pamd as B
     for cname, py in [("pamd_system", B.pamd_system), ("pamd_params", B.pamd_params),
-                      ("pamd_obs", B.pamd_obs), ("pamd_run_scalars", B.pamd_run_scalars)]:
+                      ("pamd_obs", B.pamd_obs), ("pamd_run_scalars", B.pamd_run_scalars),
+                      ("pamd_family_stats", B.pamd_family_stats)]:
         assert [f for f, _ in py._fields_] == _struct_fields(cname), cname
 
 
