@@ -322,63 +322,125 @@ __device__ __forceinline__ void bonded_terms(const RunDev<real>& d, const real* 
             }
         }
     }
-    // dihedrals: U = k (1 + cos(n phi - delta)) = k + kc cos(n phi), kc = k cos(delta), delta in {0, pi}
-    for (int t0 = 0; t0 < d.nd; t0 += W) {
+    // dihedrals: U = k (1 + cos(n phi - delta)) = |kc| + kc cos(n phi), kc = k cos(delta), delta in {0, pi}.
+    // One lane per group of torsions around one central bond j-k (up to three
+    // outer atoms i on the j side, three l on the k side, every (i, l) one
+    // torsion): the bond vector b2 is shared, each i contributes its plane
+    // normal n1 = b1 x b2 and each l its n2 = b2 x b3 once, and the torsion
+    // forces collapse to per-atom sums:  with g_i = -|b2| n1 / |n1|^2,
+    // g_l = |b2| n2 / |n2|^2, p_i = b1.b2 / |b2|^2, q_l = b3.b2 / |b2|^2 and
+    // D_i = sum_l dU/dphi_il, E_l = sum_i dU/dphi_il:
+    //   F_i = -D_i g_i,  F_l = -E_l g_l,
+    //   F_j = sum_i (1 + p_i) D_i g_i - sum_l q_l E_l g_l,
+    //   F_k = -sum_i p_i D_i g_i + sum_l (1 + q_l) E_l g_l.
+    for (int t0 = 0; t0 < d.ng; t0 += W) {
         const int t = t0 + l16;
-        const int4 ix = d.didx[t];
-        if (ix.x >= 0) {
-            const real kc = d.dpar[2 * t];
-            const int nmul = (int)d.dpar[2 * t + 1];
-            real pi[3], pj[3], pk[3], pl[3];
-            ld3(pos, ix.x, pi);
-            ld3(pos, ix.y, pj);
-            ld3(pos, ix.z, pk);
-            ld3(pos, ix.w, pl);
-            const real b1x = pj[0] - pi[0], b1y = pj[1] - pi[1], b1z = pj[2] - pi[2];
+        const int4 ga = d.dgrp[2 * t], gb = d.dgrp[2 * t + 1];
+        if (ga.x >= 0) {
+            const int ia[3] = {ga.z, ga.w, gb.x};
+            const int la[3] = {gb.y, gb.z, gb.w};
+            const real* par = d.dgpar + 18 * t;
+            real pj[3], pk[3];
+            ld3(pos, ga.x, pj);
+            ld3(pos, ga.y, pk);
             const real b2x = pk[0] - pj[0], b2y = pk[1] - pj[1], b2z = pk[2] - pj[2];
-            const real b3x = pl[0] - pk[0], b3y = pl[1] - pk[1], b3z = pl[2] - pk[2];
-            const real n1x = b1y * b2z - b1z * b2y, n1y = b1z * b2x - b1x * b2z, n1z = b1x * b2y - b1y * b2x;
-            const real n2x = b2y * b3z - b2z * b3y, n2y = b2z * b3x - b2x * b3z, n2z = b2x * b3y - b2y * b3x;
-            real n1sq = n1x * n1x + n1y * n1y + n1z * n1z;
-            real n2sq = n2x * n2x + n2y * n2y + n2z * n2z;
-            n1sq = n1sq < (real)1e-30 ? (real)1e-30 : n1sq;
-            n2sq = n2sq < (real)1e-30 ? (real)1e-30 : n2sq;
             const real b2sq = b2x * b2x + b2y * b2y + b2z * b2z;
             const real lb2 = sqrt_(b2sq);
-            const real inn = rsq_(n1sq * n2sq);
-            const real c = (n1x * n2x + n1y * n2y + n1z * n2z) * inn;             // cos phi
-            const real s = lb2 * (b1x * n2x + b1y * n2y + b1z * n2z) * inn;       // sin phi
-            // Chebyshev: T_n(c) = cos(n phi), U_{n-1}(c) = sin(n phi) / sin(phi)
-            real tp = (real)1, tc = c, up = (real)0, uc = (real)1;
-            for (int q = 1; q < nmul; ++q) {
-                const real tn = (real)2 * c * tc - tp;
-                const real un = (real)2 * c * uc - up;
-                tp = tc;
-                tc = tn;
-                up = uc;
-                uc = un;
+            const real ib2 = rcp_(b2sq);
+            // j side: b1 = x_j - x_i, n1 = b1 x b2
+            real b1[3][3], n1[3][3], n1sq[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                real pi[3];
+                ld3(pos, ia[a] >= 0 ? ia[a] : ga.x, pi);
+                b1[a][0] = pj[0] - pi[0];
+                b1[a][1] = pj[1] - pi[1];
+                b1[a][2] = pj[2] - pi[2];
+                n1[a][0] = b1[a][1] * b2z - b1[a][2] * b2y;
+                n1[a][1] = b1[a][2] * b2x - b1[a][0] * b2z;
+                n1[a][2] = b1[a][0] * b2y - b1[a][1] * b2x;
+                // absent outer atoms (their torsions carry kc = 0) keep every product finite
+                const real q2 = n1[a][0] * n1[a][0] + n1[a][1] * n1[a][1] + n1[a][2] * n1[a][2];
+                n1sq[a] = ia[a] < 0 ? (real)1 : q2 < (real)1e-30 ? (real)1e-30 : q2;
             }
-            if constexpr (ENERGY) {
-                // k (1 + cos(n phi - delta)) = |kc| + kc cos(n phi)
-                eacc += (double)(fabs(kc) + kc * tc);
-            } else {
-                // dU/dphi = -kc n sin(n phi) = -kc n sin(phi) U_{n-1}(cos phi)
-                const real dU = -kc * (real)nmul * s * uc;
-                const real ai = -lb2 * rcp_(n1sq);
-                const real al = lb2 * rcp_(n2sq);
-                const real gix = ai * n1x, giy = ai * n1y, giz = ai * n1z;   // d phi / d x_i
-                const real glx = al * n2x, gly = al * n2y, glz = al * n2z;   // d phi / d x_l
-                const real ib2 = rcp_(b2sq);
-                const real p = (b1x * b2x + b1y * b2y + b1z * b2z) * ib2;
-                const real q = (b3x * b2x + b3y * b2y + b3z * b2z) * ib2;
-                const real gjx = (-(real)1 - p) * gix + q * glx, gjy = (-(real)1 - p) * giy + q * gly,
-                           gjz = (-(real)1 - p) * giz + q * glz;
-                const real gkx = p * gix + (-(real)1 - q) * glx, gky = p * giy + (-(real)1 - q) * gly,
-                           gkz = p * giz + (-(real)1 - q) * glz;
-                add3<real, ENERGY>(frc, ix.x, -dU * gix, -dU * giy, -dU * giz);
-                add3<real, ENERGY>(frc, ix.y, -dU * gjx, -dU * gjy, -dU * gjz);
-                add3<real, ENERGY>(frc, ix.z, -dU * gkx, -dU * gky, -dU * gkz);
-                add3<real, ENERGY>(frc, ix.w, -dU * glx, -dU * gly, -dU * glz);
+            // k side: b3 = x_l - x_k, n2 = b2 x b3, q_l = b3.b2 / |b2|^2
+            real n2[3][3], n2sq[3], ql[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                real pl[3];
+                ld3(pos, la[c] >= 0 ? la[c] : ga.y, pl);
+                const real b3x = pl[0] - pk[0], b3y = pl[1] - pk[1], b3z = pl[2] - pk[2];
+                n2[c][0] = b2y * b3z - b2z * b3y;
+                n2[c][1] = b2z * b3x - b2x * b3z;
+                n2[c][2] = b2x * b3y - b2y * b3x;
+                ql[c] = (b3x * b2x + b3y * b2y + b3z * b2z) * ib2;
+                const real q2 = n2[c][0] * n2[c][0] + n2[c][1] * n2[c][1] + n2[c][2] * n2[c][2];
+                n2sq[c] = la[c] < 0 ? (real)1 : q2 < (real)1e-30 ? (real)1e-30 : q2;
+            }
+            real Di[3] = {(real)0, (real)0, (real)0}, El[3] = {(real)0, (real)0, (real)0};
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const real kc = par[2 * (3 * a + c)];
+                    const int nmul = (int)par[2 * (3 * a + c) + 1];
+                    const real inn = rsq_(n1sq[a] * n2sq[c]);
+                    const real cphi = (n1[a][0] * n2[c][0] + n1[a][1] * n2[c][1] + n1[a][2] * n2[c][2]) * inn;
+                    // Chebyshev: T_n(c) = cos(n phi), U_{n-1}(c) = sin(n phi) / sin(phi)
+                    real tp = (real)1, tc = cphi, up = (real)0, uc = (real)1;
+                    for (int q = 1; q < nmul; ++q) {
+                        const real tn = (real)2 * cphi * tc - tp;
+                        const real un = (real)2 * cphi * uc - up;
+                        tp = tc;
+                        tc = tn;
+                        up = uc;
+                        uc = un;
+                    }
+                    if constexpr (ENERGY) {
+                        eacc += (double)(fabs(kc) + kc * tc);
+                    } else {
+                        const real sphi = lb2 * (b1[a][0] * n2[c][0] + b1[a][1] * n2[c][1] + b1[a][2] * n2[c][2]) * inn;
+                        // dU/dphi = -kc n sin(n phi) = -kc n sin(phi) U_{n-1}(cos phi)
+                        const real dU = -kc * (real)nmul * sphi * uc;
+                        Di[a] += dU;
+                        El[c] += dU;
+                    }
+                }
+            }
+            if constexpr (!ENERGY) {
+                real fj[3] = {(real)0, (real)0, (real)0}, fk[3] = {(real)0, (real)0, (real)0};
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    // D_i g_i with g_i = -|b2| n1 / |n1|^2
+                    const real s = -lb2 * rcp_(n1sq[a]) * Di[a];
+                    const real gx = s * n1[a][0], gy = s * n1[a][1], gz = s * n1[a][2];
+                    const real pa = (b1[a][0] * b2x + b1[a][1] * b2y + b1[a][2] * b2z) * ib2;
+                    fj[0] += ((real)1 + pa) * gx;
+                    fj[1] += ((real)1 + pa) * gy;
+                    fj[2] += ((real)1 + pa) * gz;
+                    fk[0] -= pa * gx;
+                    fk[1] -= pa * gy;
+                    fk[2] -= pa * gz;
+                    if (ia[a] >= 0)
+                        add3<real, ENERGY>(frc, ia[a], -gx, -gy, -gz);
+                }
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    // E_l g_l with g_l = |b2| n2 / |n2|^2
+                    const real s = lb2 * rcp_(n2sq[c]) * El[c];
+                    const real gx = s * n2[c][0], gy = s * n2[c][1], gz = s * n2[c][2];
+                    const real qc = ql[c];
+                    fj[0] -= qc * gx;
+                    fj[1] -= qc * gy;
+                    fj[2] -= qc * gz;
+                    fk[0] += ((real)1 + qc) * gx;
+                    fk[1] += ((real)1 + qc) * gy;
+                    fk[2] += ((real)1 + qc) * gz;
+                    if (la[c] >= 0)
+                        add3<real, ENERGY>(frc, la[c], -gx, -gy, -gz);
+                }
+                add3<real, ENERGY>(frc, ga.x, fj[0], fj[1], fj[2]);
+                add3<real, ENERGY>(frc, ga.y, fk[0], fk[1], fk[2]);
             }
         }
     }

@@ -70,15 +70,15 @@ struct RunDev {
     const real* bpar;       // [nb][2] (k, r0)
     const int4* aidx;       // [na]   (i, centre, k, -)
     const real* apar;       // [na][2] (k, theta0)
-    const int4* didx;       // [nd]   (i, j, k, l)
-    const real* dpar;       // [nd][2] (k cos(delta), n)
+    const int4* dgrp;       // [ng][2] dihedral groups: (j, k, i0, i1), (i2, l0, l1, l2), -1 = none
+    const real* dgpar;      // [ng][9][2] (k cos(delta), n) of (i_a, l_c) at 3 a + c
     const double* mass;     // [npad] (0 for padding)
     const double* x_init;   // [n][3]
     const double* sched;    // device temperature schedule [kMaxSched]
     int32_t n_sched;        // its length (set by pamd_set_schedule; 0 = none)
     double* dbg;            // force-debug scratch [PAMD_FORCE_CHUNK][npad][4]
     void* obs;              // device pamd_obs
-    int32_t n, npad, nslot, nb, na, nd;
+    int32_t n, npad, nslot, nb, na, ng;
     int64_t R_target, R_cap;
     double kB, dt, T0, V_target, T_final;
     uint32_t p24;           // Andersen threshold: collide iff (w >> 8) < p24

@@ -71,8 +71,8 @@ struct HostTables {
     std::vector<double> atomp;           // wide layout: [n][4] per-atom pair parameters
     std::vector<uint32_t> pmask;         // wide layout: [n][nchunk][2] exclusion / 1-4 bits
     std::vector<double> ab, c;           // [steps][16][2], [steps][16]
-    std::vector<int32_t> bidx, aidx, didx;  // int4 records
-    std::vector<double> bpar, apar, dpar;
+    std::vector<int32_t> bidx, aidx, didx;  // int4 records (dihedrals: two per group slot)
+    std::vector<double> bpar, apar, dpar;   // dihedrals: 18 per group slot
     std::vector<double> mass, x_init;
     double mtot = 0;
 };
@@ -223,47 +223,319 @@ pamd_status validate(pamd_ctx* c, const pamd_system& s, const pamd_params& p, in
 // stored reversed (a bond, angle or dihedral read backwards is the same
 // term).  Empty lanes get index -1.  Returns the packed records
 // (4 indices + 2 parameters per slot).
-void pack_terms(int count, int k, const int32_t* idx, const double* p0, const double* p1,
-                std::vector<int32_t>& rec, std::vector<double>& par, int W)
+// First fit of bonded terms into passes of W lanes in which no two lanes name
+// the same atom in the same role (a term may be reversed).  Returns the passes
+// as lists of (term, reversed).
+struct Packing {
+    std::vector<std::vector<std::pair<int, int>>> passes;
+};
+
+static Packing first_fit(int k, const int32_t* idx, const std::vector<int>& order, int W)
 {
-    std::vector<std::vector<std::vector<int>>> passes;   // pass -> terms -> atoms (oriented)
-    std::vector<std::vector<int>> pass_term;
-    for (int t = 0; t < count; ++t) {
-        std::vector<int> fwd(idx + (size_t)t * k, idx + (size_t)t * k + k);
-        std::vector<int> rev(fwd.rbegin(), fwd.rend());
+    constexpr int kWords = (PAMD_MAX_ATOMS + 63) / 64;
+    struct Used {
+        uint64_t bits[4][kWords];
+    };
+    Packing pk;
+    std::vector<Used> used;
+    for (int t : order) {
+        const int32_t* a = idx + (size_t)t * k;
         bool placed = false;
         for (int o = 0; o < 2 && !placed; ++o) {
-            const std::vector<int>& cand = o == 0 ? fwd : rev;
-            for (size_t b = 0; b < passes.size() && !placed; ++b) {
-                if (passes[b].size() >= (size_t)W)
+            for (size_t b = 0; b < pk.passes.size() && !placed; ++b) {
+                if (pk.passes[b].size() >= (size_t)W)
                     continue;
                 bool ok = true;
-                for (const auto& other : passes[b])
-                    for (int r = 0; r < k && ok; ++r)
-                        ok = other[r] != cand[r];
+                for (int r = 0; r < k && ok; ++r) {
+                    const int at = o ? a[k - 1 - r] : a[r];
+                    ok = !((used[b].bits[r][at >> 6] >> (at & 63)) & 1u);
+                }
                 if (ok) {
-                    passes[b].push_back(cand);
-                    pass_term[b].push_back(t);
+                    for (int r = 0; r < k; ++r) {
+                        const int at = o ? a[k - 1 - r] : a[r];
+                        used[b].bits[r][at >> 6] |= (uint64_t)1 << (at & 63);
+                    }
+                    pk.passes[b].push_back({t, o});
                     placed = true;
                 }
             }
         }
         if (!placed) {
-            passes.push_back({fwd});
-            pass_term.push_back({t});
+            Used u;
+            memset(&u, 0, sizeof(u));
+            for (int r = 0; r < k; ++r)
+                u.bits[r][a[r] >> 6] |= (uint64_t)1 << (a[r] & 63);
+            used.push_back(u);
+            pk.passes.push_back({{t, 0}});
         }
     }
-    const size_t slots = std::max<size_t>(1, passes.size()) * W;
+    return pk;
+}
+
+// Bonded-term records in passes of W lanes (one term per lane, -1 = empty).
+// The number of passes depends on the order in which first fit sees the terms,
+// so a fixed set of orders is tried and the one with the fewest passes kept:
+// the given order, most-constrained first (terms whose atoms carry the most
+// terms), and 62 shuffles from a fixed-seed xorshift generator.  Deterministic.
+void pack_terms(int count, int k, const int32_t* idx, const double* p0, const double* p1,
+                std::vector<int32_t>& rec, std::vector<double>& par, int W)
+{
+    Packing best;
+    if (count > 0) {
+        std::vector<int> order(count);
+        for (int t = 0; t < count; ++t)
+            order[t] = t;
+        best = first_fit(k, idx, order, W);
+        std::vector<int> deg(PAMD_MAX_ATOMS, 0);
+        for (int t = 0; t < count * k; ++t)
+            ++deg[idx[t]];
+        std::vector<int> mcf = order;
+        std::stable_sort(mcf.begin(), mcf.end(), [&](int a, int b) {
+            int da = 0, db = 0;
+            for (int r = 0; r < k; ++r) {
+                da += deg[idx[(size_t)a * k + r]];
+                db += deg[idx[(size_t)b * k + r]];
+            }
+            return da > db;
+        });
+        Packing p = first_fit(k, idx, mcf, W);
+        if (p.passes.size() < best.passes.size())
+            best = p;
+        uint64_t st = 0x9E3779B97F4A7C15ull ^ ((uint64_t)count << 8 ^ (uint64_t)k);
+        for (int trial = 0; trial < 62; ++trial) {
+            for (int i = count - 1; i > 0; --i) {
+                st ^= st << 13;
+                st ^= st >> 7;
+                st ^= st << 17;
+                const int j = (int)(st % (uint64_t)(i + 1));
+                std::swap(order[i], order[j]);
+            }
+            p = first_fit(k, idx, order, W);
+            if (p.passes.size() < best.passes.size())
+                best = p;
+        }
+    }
+    const size_t slots = std::max<size_t>(1, best.passes.size()) * W;
     rec.assign(slots * 4, -1);
     par.assign(slots * 2, 0.0);
-    for (size_t b = 0; b < passes.size(); ++b)
-        for (size_t q = 0; q < passes[b].size(); ++q) {
+    for (size_t b = 0; b < best.passes.size(); ++b)
+        for (size_t q = 0; q < best.passes[b].size(); ++q) {
             const size_t sl = b * W + q;
+            const int t = best.passes[b][q].first, o = best.passes[b][q].second;
             for (int r = 0; r < 4; ++r)
-                rec[sl * 4 + r] = r < k ? passes[b][q][r] : 0;
-            par[sl * 2] = p0[pass_term[b][q]];
-            par[sl * 2 + 1] = p1[pass_term[b][q]];
+                rec[sl * 4 + r] = r < k ? idx[(size_t)t * k + (o ? k - 1 - r : r)] : 0;
+            par[sl * 2] = p0[t];
+            par[sl * 2 + 1] = p1[t];
         }
+}
+
+// Dihedrals grouped by their central bond (j, k): up to three outer atoms i on
+// the j side and three l on the k side, every (i, l) combination one term
+// (k cos(delta), n), so that one lane computes the shared bond vector, the
+// plane normals of each i and each l once and the up to nine torsions from
+// them.  Slot record: 8 atoms in roles j, k, i0, i1, i2, l0, l1, l2 (-1: none;
+// j = -1: empty slot) and 9 (k cos(delta), n) pairs for (i_a, l_c) at 3 a + c
+// (k cos(delta) = 0, n = 1 where no term).  Passes of W slots in which no two
+// lanes name the same atom in the same role: a group may be reversed
+// (j <-> k, i <-> l) and its outer atoms permuted among their three roles.
+// Orders tried: the input order and 63 fixed-seed shuffles; fewest passes
+// kept.  Returns the slot count (a multiple of W, 0 without dihedrals).
+struct DihGroup {
+    int j, k;
+    int I[3], L[3];
+    int term[3][3];   // dihedral index of (I[a], L[c]) or -1
+    int ni, nl;
+};
+
+static std::vector<DihGroup> dihedral_groups(const pamd_system& s)
+{
+    std::vector<DihGroup> g;
+    for (int q = 0; q < s.n_dihedrals; ++q) {
+        int i = s.dih_idx[4 * q], j = s.dih_idx[4 * q + 1], k = s.dih_idx[4 * q + 2], l = s.dih_idx[4 * q + 3];
+        if (j > k) {
+            std::swap(i, l);
+            std::swap(j, k);
+        }
+        bool placed = false;
+        for (DihGroup& G : g) {
+            if (G.j != j || G.k != k)
+                continue;
+            int a = -1, c = -1;
+            for (int u = 0; u < G.ni; ++u)
+                if (G.I[u] == i)
+                    a = u;
+            for (int u = 0; u < G.nl; ++u)
+                if (G.L[u] == l)
+                    c = u;
+            if ((a < 0 && G.ni == 3) || (c < 0 && G.nl == 3) || (a >= 0 && c >= 0 && G.term[a][c] >= 0))
+                continue;
+            if (a < 0) {
+                a = G.ni++;
+                G.I[a] = i;
+            }
+            if (c < 0) {
+                c = G.nl++;
+                G.L[c] = l;
+            }
+            G.term[a][c] = q;
+            placed = true;
+            break;
+        }
+        if (!placed) {
+            DihGroup G;
+            G.j = j;
+            G.k = k;
+            G.ni = G.nl = 1;
+            G.I[0] = i;
+            G.L[0] = l;
+            for (int a = 0; a < 3; ++a)
+                for (int c = 0; c < 3; ++c)
+                    G.term[a][c] = -1;
+            G.I[1] = G.I[2] = G.L[1] = G.L[2] = -1;
+            G.term[0][0] = q;
+            g.push_back(G);
+        }
+    }
+    return g;
+}
+
+namespace {
+// one placed group: orientation and the role index of each outer atom
+struct Placed {
+    int grp, flip;
+    int ri[3], rl[3];
+};
+}  // namespace
+
+static std::vector<std::vector<Placed>> pack_groups(const std::vector<DihGroup>& g, const std::vector<int>& order,
+                                                    int W)
+{
+    constexpr int kWords = (PAMD_MAX_ATOMS + 63) / 64;
+    struct Used {
+        uint64_t bits[8][kWords];
+        bool has(int r, int a) const { return (bits[r][a >> 6] >> (a & 63)) & 1u; }
+        void set(int r, int a) { bits[r][a >> 6] |= (uint64_t)1 << (a & 63); }
+    };
+    std::vector<std::vector<Placed>> passes;
+    std::vector<Used> used;
+    // roles 2.. / 5.. for n outer atoms: first permutation whose roles are free
+    auto assign = [](const Used& u, const int* at, int n, int base, int* role) {
+        static const int perm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+        for (const auto& pm : perm) {
+            bool ok = true;
+            for (int a = 0; a < n && ok; ++a)
+                ok = !u.has(base + pm[a], at[a]);
+            if (ok) {
+                for (int a = 0; a < n; ++a)
+                    role[a] = pm[a];
+                return true;
+            }
+        }
+        return false;
+    };
+    for (int gi : order) {
+        const DihGroup& G = g[gi];
+        bool placed = false;
+        for (int flip = 0; flip < 2 && !placed; ++flip) {
+            const int j = flip ? G.k : G.j, k = flip ? G.j : G.k;
+            const int* I = flip ? G.L : G.I;
+            const int* L = flip ? G.I : G.L;
+            const int ni = flip ? G.nl : G.ni, nl = flip ? G.ni : G.nl;
+            for (size_t b = 0; b < passes.size() && !placed; ++b) {
+                if (passes[b].size() >= (size_t)W || used[b].has(0, j) || used[b].has(1, k))
+                    continue;
+                Placed P{gi, flip, {0, 1, 2}, {0, 1, 2}};
+                if (!assign(used[b], I, ni, 2, P.ri) || !assign(used[b], L, nl, 5, P.rl))
+                    continue;
+                used[b].set(0, j);
+                used[b].set(1, k);
+                for (int a = 0; a < ni; ++a)
+                    used[b].set(2 + P.ri[a], I[a]);
+                for (int c = 0; c < nl; ++c)
+                    used[b].set(5 + P.rl[c], L[c]);
+                passes[b].push_back(P);
+                placed = true;
+            }
+        }
+        if (!placed) {
+            Used u;
+            memset(&u, 0, sizeof(u));
+            u.set(0, G.j);
+            u.set(1, G.k);
+            for (int a = 0; a < G.ni; ++a)
+                u.set(2 + a, G.I[a]);
+            for (int c = 0; c < G.nl; ++c)
+                u.set(5 + c, G.L[c]);
+            used.push_back(u);
+            passes.push_back({Placed{gi, 0, {0, 1, 2}, {0, 1, 2}}});
+        }
+    }
+    return passes;
+}
+
+int pack_dihedral_groups(const pamd_system& s, int W, std::vector<int32_t>* rec, std::vector<double>* par)
+{
+    if (s.n_dihedrals <= 0) {
+        if (rec)
+            rec->clear();
+        if (par)
+            par->clear();
+        return 0;
+    }
+    const std::vector<DihGroup> g = dihedral_groups(s);
+    const int ng = (int)g.size();
+    std::vector<int> order(ng);
+    for (int q = 0; q < ng; ++q)
+        order[q] = q;
+    std::vector<std::vector<Placed>> best = pack_groups(g, order, W);
+    uint64_t st = 0xD1B54A32D192ED03ull ^ (uint64_t)ng;
+    for (int trial = 0; trial < 63; ++trial) {
+        for (int i = ng - 1; i > 0; --i) {
+            st ^= st << 13;
+            st ^= st >> 7;
+            st ^= st << 17;
+            std::swap(order[i], order[(int)(st % (uint64_t)(i + 1))]);
+        }
+        std::vector<std::vector<Placed>> p = pack_groups(g, order, W);
+        if (p.size() < best.size())
+            best = std::move(p);
+    }
+    const int slots = (int)best.size() * W;
+    if (rec && par) {
+        rec->assign((size_t)slots * 8, -1);
+        par->assign((size_t)slots * 18, 0.0);
+        for (int q = 0; q < slots; ++q)
+            (*par)[(size_t)q * 18 + 1] = 1.0;
+        for (size_t b = 0; b < best.size(); ++b)
+            for (size_t q = 0; q < best[b].size(); ++q) {
+                const Placed& P = best[b][q];
+                const DihGroup& G = g[P.grp];
+                const size_t sl = b * W + q;
+                int32_t* r = rec->data() + sl * 8;
+                double* pp = par->data() + sl * 18;
+                for (int u = 0; u < 9; ++u) {
+                    pp[2 * u] = 0.0;
+                    pp[2 * u + 1] = 1.0;
+                }
+                r[0] = P.flip ? G.k : G.j;
+                r[1] = P.flip ? G.j : G.k;
+                const int ni = P.flip ? G.nl : G.ni, nl = P.flip ? G.ni : G.nl;
+                for (int a = 0; a < ni; ++a)
+                    r[2 + P.ri[a]] = P.flip ? G.L[a] : G.I[a];
+                for (int c = 0; c < nl; ++c)
+                    r[5 + P.rl[c]] = P.flip ? G.I[c] : G.L[c];
+                for (int a = 0; a < ni; ++a)
+                    for (int c = 0; c < nl; ++c) {
+                        const int t = P.flip ? G.term[c][a] : G.term[a][c];
+                        if (t < 0)
+                            continue;
+                        const int u = 3 * P.ri[a] + P.rl[c];
+                        pp[2 * u] = s.dih_k[t] * (cos(s.dih_delta[t]) > 0 ? 1.0 : -1.0);   // k cos(delta)
+                        pp[2 * u + 1] = (double)s.dih_n[t];
+                    }
+            }
+    }
+    return slots;
 }
 
 // Pair coefficients in the order the MD kernel walks its tiles: for block J,
@@ -333,12 +605,7 @@ void build_tables(const pamd_system& s, HostTables& t, int wide)
     }
     pack_terms(s.n_bonds, 2, s.bond_idx, s.bond_k, s.bond_r0, t.bidx, t.bpar, W);
     pack_terms(s.n_angles, 3, s.angle_idx, s.angle_k, s.angle_theta0, t.aidx, t.apar, W);
-    std::vector<double> kc(s.n_dihedrals), nm(s.n_dihedrals);
-    for (int q = 0; q < s.n_dihedrals; ++q) {
-        kc[q] = s.dih_k[q] * (cos(s.dih_delta[q]) > 0 ? 1.0 : -1.0);   // k cos(delta), delta in {0, pi}
-        nm[q] = (double)s.dih_n[q];
-    }
-    pack_terms(s.n_dihedrals, 4, s.dih_idx, kc.data(), nm.data(), t.didx, t.dpar, W);
+    pack_dihedral_groups(s, W, &t.didx, &t.dpar);
     t.mass.assign(t.npad, 0.0);
     t.mtot = 0;
     for (int a = 0; a < n; ++a) {
@@ -380,14 +647,13 @@ void carve(Carver& st, Carver& wk, const pamd_system& s, const pamd_params& p, i
     const int nb_slots = (int)(rec.size() / 4);
     pack_terms(s.n_angles, 3, s.angle_idx, zeros.data(), zeros.data(), rec, par, W);
     const int na_slots = (int)(rec.size() / 4);
-    pack_terms(s.n_dihedrals, 4, s.dih_idx, zeros.data(), zeros.data(), rec, par, W);
-    const int nd_slots = (int)(rec.size() / 4);
+    const int nd_slots = std::max(pack_dihedral_groups(s, W, nullptr, nullptr), 1);
     d.bidx = wk.take<int4>(nb_slots);
     d.bpar = wk.take<real>((size_t)nb_slots * 2);
     d.aidx = wk.take<int4>(na_slots);
     d.apar = wk.take<real>((size_t)na_slots * 2);
-    d.didx = wk.take<int4>(nd_slots);
-    d.dpar = wk.take<real>((size_t)nd_slots * 2);
+    d.dgrp = wk.take<int4>((size_t)nd_slots * 2);
+    d.dgpar = wk.take<real>((size_t)nd_slots * 18);
     d.mass = wk.take<double>(npad);
     d.x_init = wk.take<double>((size_t)3 * n);
     d.sched = wk.take<double>(kMaxSched);
@@ -400,7 +666,7 @@ void carve(Carver& st, Carver& wk, const pamd_system& s, const pamd_params& p, i
     d.nslot = nslot;
     d.nb = s.n_bonds > 0 ? nb_slots : 0;
     d.na = s.n_angles > 0 ? na_slots : 0;
-    d.nd = s.n_dihedrals > 0 ? nd_slots : 0;
+    d.ng = s.n_dihedrals > 0 ? nd_slots : 0;
     d.R_target = p.R_target;
     d.R_cap = Rc;
     d.kB = s.kB;
@@ -464,8 +730,8 @@ hipError_t upload(const RunDev<real>& d, const HostTables& t, hipStream_t s)
     if ((e = up(d.bpar, t.bpar)) != hipSuccess) return e;
     if ((e = upi(d.aidx, t.aidx)) != hipSuccess) return e;
     if ((e = up(d.apar, t.apar)) != hipSuccess) return e;
-    if ((e = upi(d.didx, t.didx)) != hipSuccess) return e;
-    if ((e = up(d.dpar, t.dpar)) != hipSuccess) return e;
+    if (!t.didx.empty() && (e = upi(d.dgrp, t.didx)) != hipSuccess) return e;
+    if (!t.dpar.empty() && (e = up(d.dgpar, t.dpar)) != hipSuccess) return e;
     if ((e = upd(d.mass, t.mass)) != hipSuccess) return e;
     if ((e = upd(d.x_init, t.x_init)) != hipSuccess) return e;
     return hipSuccess;
