@@ -282,43 +282,70 @@ __device__ __forceinline__ void bonded_terms(const RunDev<real>& d, const real* 
             }
         }
     }
-    // angles: U = 1/2 k (theta - theta0)^2, theta = atan2(|u x w|, u.w)
-    for (int t0 = 0; t0 < d.na; t0 += W) {
+    // angles: U = 1/2 k (theta - theta0)^2, theta = atan2(|e_a x e_c|, e_a . e_c).
+    // One lane per centre atom j with up to four outer atoms: each bond vector
+    // u_a = x_a - x_j is normalised once (e_a), and the force on outer atom a
+    // of angle (a, j, c) is -k dth (cos theta e_a - e_c) / (|u_a| sin theta);
+    // the centre takes minus the sum.
+    for (int t0 = 0; t0 < d.nag; t0 += W) {
         const int t = t0 + l16;
-        const int4 ix = d.aidx[t];
-        if (ix.x >= 0) {
-            const real k = d.apar[2 * t], th0 = d.apar[2 * t + 1];
-            real pi[3], pj[3], pk[3];
-            ld3(pos, ix.x, pi);
-            ld3(pos, ix.y, pj);
-            ld3(pos, ix.z, pk);
-            const real ux = pi[0] - pj[0], uy = pi[1] - pj[1], uz = pi[2] - pj[2];
-            const real wx = pk[0] - pj[0], wy = pk[1] - pj[1], wz = pk[2] - pj[2];
-            const real cx = uy * wz - uz * wy, cy = uz * wx - ux * wz, cz = ux * wy - uy * wx;
-            const real sn = sqrt_(cx * cx + cy * cy + cz * cz);
-            const real cs = ux * wx + uy * wy + uz * wz;
-            const real th = atan2_(sn, cs);
-            const real dth = th - th0;
-            if constexpr (ENERGY) {
-                eacc += (double)((real)0.5 * k * dth * dth);
-            } else {
-                const real iu = rsq_(ux * ux + uy * uy + uz * uz);
-                const real iw = rsq_(wx * wx + wy * wy + wz * wz);
-                const real cost = cs * iu * iw;
-                real sint = sn * iu * iw;
-                sint = sint < (real)1e-8 ? (real)1e-8 : sint;
-                const real g = k * dth * rcp_(sint);
-                // F_i = -k dth (cos u^ - w^) / (|u| sin) ; F_k likewise ; F_j = -(F_i + F_k)
-                const real gi = g * iu, gk = g * iw;
-                const real fix = -gi * (cost * ux * iu - wx * iw);
-                const real fiy = -gi * (cost * uy * iu - wy * iw);
-                const real fiz = -gi * (cost * uz * iu - wz * iw);
-                const real fkx = -gk * (cost * wx * iw - ux * iu);
-                const real fky = -gk * (cost * wy * iw - uy * iu);
-                const real fkz = -gk * (cost * wz * iw - uz * iu);
-                add3<real, ENERGY>(frc, ix.x, fix, fiy, fiz);
-                add3<real, ENERGY>(frc, ix.z, fkx, fky, fkz);
-                add3<real, ENERGY>(frc, ix.y, -(fix + fkx), -(fiy + fky), -(fiz + fkz));
+        const int4 ga = d.agrp[2 * t];
+        if (ga.x >= 0) {
+            const int oa[4] = {ga.y, ga.z, ga.w, d.agrp[2 * t + 1].x};
+            const real* par = d.agpar + 12 * t;
+            real pj[3];
+            ld3(pos, ga.x, pj);
+            real e[4][3], iu[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                real pa[3];
+                ld3(pos, oa[a] >= 0 ? oa[a] : ga.x, pa);
+                const real ux = pa[0] - pj[0], uy = pa[1] - pj[1], uz = pa[2] - pj[2];
+                // absent outer atoms (their angles carry k = 0): a unit vector along x
+                iu[a] = oa[a] >= 0 ? rsq_(ux * ux + uy * uy + uz * uz) : (real)1;
+                e[a][0] = oa[a] >= 0 ? ux * iu[a] : (real)1;
+                e[a][1] = uy * iu[a];
+                e[a][2] = uz * iu[a];
+            }
+            real S[4][3];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+                S[a][0] = S[a][1] = S[a][2] = (real)0;
+#pragma unroll
+            for (int q = 0; q < 6; ++q) {
+                constexpr int A[6] = {0, 0, 0, 1, 1, 2}, C[6] = {1, 2, 3, 2, 3, 3};
+                const int a = A[q], c = C[q];
+                const real k = par[2 * q], th0 = par[2 * q + 1];
+                const real cs = e[a][0] * e[c][0] + e[a][1] * e[c][1] + e[a][2] * e[c][2];
+                const real cx = e[a][1] * e[c][2] - e[a][2] * e[c][1];
+                const real cy = e[a][2] * e[c][0] - e[a][0] * e[c][2];
+                const real cz = e[a][0] * e[c][1] - e[a][1] * e[c][0];
+                const real sn = sqrt_(cx * cx + cy * cy + cz * cz);
+                const real dth = atan2_(sn, cs) - th0;
+                if constexpr (ENERGY) {
+                    eacc += (double)((real)0.5 * k * dth * dth);
+                } else {
+                    const real g = k * dth * rcp_(sn < (real)1e-8 ? (real)1e-8 : sn);
+                    S[a][0] += g * (cs * e[a][0] - e[c][0]);
+                    S[a][1] += g * (cs * e[a][1] - e[c][1]);
+                    S[a][2] += g * (cs * e[a][2] - e[c][2]);
+                    S[c][0] += g * (cs * e[c][0] - e[a][0]);
+                    S[c][1] += g * (cs * e[c][1] - e[a][1]);
+                    S[c][2] += g * (cs * e[c][2] - e[a][2]);
+                }
+            }
+            if constexpr (!ENERGY) {
+                real fj[3] = {(real)0, (real)0, (real)0};
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    const real fx = -S[a][0] * iu[a], fy = -S[a][1] * iu[a], fz = -S[a][2] * iu[a];
+                    fj[0] -= fx;
+                    fj[1] -= fy;
+                    fj[2] -= fz;
+                    if (oa[a] >= 0)
+                        add3<real, ENERGY>(frc, oa[a], fx, fy, fz);
+                }
+                add3<real, ENERGY>(frc, ga.x, fj[0], fj[1], fj[2]);
             }
         }
     }

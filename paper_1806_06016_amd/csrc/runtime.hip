@@ -9,6 +9,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <array>
 #include <string>
 #include <vector>
 
@@ -538,6 +539,171 @@ int pack_dihedral_groups(const pamd_system& s, int W, std::vector<int32_t>* rec,
     return slots;
 }
 
+// Angles grouped by their centre atom j: up to four outer atoms, every pair
+// (a, c) of them one angle term (k, theta0), so that one lane normalises each
+// bond vector once and evaluates the up to six angles from the unit vectors.
+// Slot record: 8 ints (j, o0, o1, o2, o3, -1, -1, -1) (-1: no atom; j = -1:
+// empty slot) and 6 (k, theta0) pairs for the outer pairs (0,1) (0,2) (0,3)
+// (1,2) (1,3) (2,3) (k = 0 where no term).  Passes of W slots with no atom
+// twice in one role; outer atoms may be permuted among their four roles.
+// Orders tried: the input order and 63 fixed-seed shuffles; fewest passes kept.
+struct AngGroup {
+    int j, no;
+    int o[4];
+    int term[4][4];   // angle index of outer pair (a, c), a < c, or -1
+};
+
+static int pair_slot(int a, int c)
+{
+    if (a > c)
+        std::swap(a, c);
+    static const int tab[4][4] = {{-1, 0, 1, 2}, {0, -1, 3, 4}, {1, 3, -1, 5}, {2, 4, 5, -1}};
+    return tab[a][c];
+}
+
+static std::vector<AngGroup> angle_groups(const pamd_system& s)
+{
+    std::vector<AngGroup> g;
+    for (int q = 0; q < s.n_angles; ++q) {
+        const int i = s.angle_idx[3 * q], j = s.angle_idx[3 * q + 1], k = s.angle_idx[3 * q + 2];
+        bool placed = false;
+        for (AngGroup& G : g) {
+            if (G.j != j)
+                continue;
+            int a = -1, c = -1;
+            for (int u = 0; u < G.no; ++u) {
+                if (G.o[u] == i)
+                    a = u;
+                if (G.o[u] == k)
+                    c = u;
+            }
+            const int need = (a < 0) + (c < 0);
+            if (G.no + need > 4 || (a >= 0 && c >= 0 && G.term[a][c] >= 0))
+                continue;
+            if (a < 0)
+                G.o[a = G.no++] = i;
+            if (c < 0)
+                G.o[c = G.no++] = k;
+            G.term[a][c] = G.term[c][a] = q;
+            placed = true;
+            break;
+        }
+        if (!placed) {
+            AngGroup G;
+            G.j = j;
+            G.no = 2;
+            G.o[0] = i;
+            G.o[1] = k;
+            G.o[2] = G.o[3] = -1;
+            for (int a = 0; a < 4; ++a)
+                for (int c = 0; c < 4; ++c)
+                    G.term[a][c] = -1;
+            G.term[0][1] = G.term[1][0] = q;
+            g.push_back(G);
+        }
+    }
+    return g;
+}
+
+static std::vector<std::vector<std::pair<int, std::array<int, 4>>>> pack_angle_passes(
+    const std::vector<AngGroup>& g, const std::vector<int>& order, int W)
+{
+    constexpr int kWords = (PAMD_MAX_ATOMS + 63) / 64;
+    struct Used {
+        uint64_t bits[5][kWords];
+        bool has(int r, int a) const { return (bits[r][a >> 6] >> (a & 63)) & 1u; }
+        void set(int r, int a) { bits[r][a >> 6] |= (uint64_t)1 << (a & 63); }
+    };
+    std::vector<std::vector<std::pair<int, std::array<int, 4>>>> passes;
+    std::vector<Used> used;
+    for (int gi : order) {
+        const AngGroup& G = g[gi];
+        bool placed = false;
+        for (size_t b = 0; b < passes.size() && !placed; ++b) {
+            if (passes[b].size() >= (size_t)W || used[b].has(0, G.j))
+                continue;
+            std::array<int, 4> perm = {0, 1, 2, 3};
+            do {
+                bool ok = true;
+                for (int a = 0; a < G.no && ok; ++a)
+                    ok = !used[b].has(1 + perm[a], G.o[a]);
+                if (ok) {
+                    used[b].set(0, G.j);
+                    for (int a = 0; a < G.no; ++a)
+                        used[b].set(1 + perm[a], G.o[a]);
+                    passes[b].push_back({gi, perm});
+                    placed = true;
+                }
+            } while (!placed && std::next_permutation(perm.begin(), perm.end()));
+        }
+        if (!placed) {
+            Used u;
+            memset(&u, 0, sizeof(u));
+            u.set(0, G.j);
+            for (int a = 0; a < G.no; ++a)
+                u.set(1 + a, G.o[a]);
+            used.push_back(u);
+            passes.push_back({{gi, std::array<int, 4>{0, 1, 2, 3}}});
+        }
+    }
+    return passes;
+}
+
+int pack_angle_groups(const pamd_system& s, int W, std::vector<int32_t>* rec, std::vector<double>* par)
+{
+    if (s.n_angles <= 0) {
+        if (rec)
+            rec->clear();
+        if (par)
+            par->clear();
+        return 0;
+    }
+    const std::vector<AngGroup> g = angle_groups(s);
+    const int ng = (int)g.size();
+    std::vector<int> order(ng);
+    for (int q = 0; q < ng; ++q)
+        order[q] = q;
+    auto best = pack_angle_passes(g, order, W);
+    uint64_t st = 0xA0761D6478BD642Full ^ (uint64_t)ng;
+    for (int trial = 0; trial < 63; ++trial) {
+        for (int i = ng - 1; i > 0; --i) {
+            st ^= st << 13;
+            st ^= st >> 7;
+            st ^= st << 17;
+            std::swap(order[i], order[(int)(st % (uint64_t)(i + 1))]);
+        }
+        auto p = pack_angle_passes(g, order, W);
+        if (p.size() < best.size())
+            best = std::move(p);
+    }
+    const int slots = (int)best.size() * W;
+    if (rec && par) {
+        rec->assign((size_t)slots * 8, -1);
+        par->assign((size_t)slots * 12, 0.0);
+        for (size_t b = 0; b < best.size(); ++b)
+            for (size_t q = 0; q < best[b].size(); ++q) {
+                const AngGroup& G = g[best[b][q].first];
+                const std::array<int, 4>& perm = best[b][q].second;
+                const size_t sl = b * W + q;
+                int32_t* r = rec->data() + sl * 8;
+                double* pp = par->data() + sl * 12;
+                r[0] = G.j;
+                for (int a = 0; a < G.no; ++a)
+                    r[1 + perm[a]] = G.o[a];
+                for (int a = 0; a < G.no; ++a)
+                    for (int c = a + 1; c < G.no; ++c) {
+                        const int t = G.term[a][c];
+                        if (t < 0)
+                            continue;
+                        const int u = pair_slot(perm[a], perm[c]);
+                        pp[2 * u] = s.angle_k[t];
+                        pp[2 * u + 1] = s.angle_theta0[t];
+                    }
+            }
+    }
+    return slots;
+}
+
 // Pair coefficients in the order the MD kernel walks its tiles: for block J,
 // the diagonal block (rotations k = 1..8; k = 8 only on lanes 0..7), then for
 // k = 0..15 the blocks I < J.  Lane l of step (I, J, k) pairs atom 16 I + l
@@ -604,7 +770,7 @@ void build_tables(const pamd_system& s, HostTables& t, int wide)
         }
     }
     pack_terms(s.n_bonds, 2, s.bond_idx, s.bond_k, s.bond_r0, t.bidx, t.bpar, W);
-    pack_terms(s.n_angles, 3, s.angle_idx, s.angle_k, s.angle_theta0, t.aidx, t.apar, W);
+    pack_angle_groups(s, W, &t.aidx, &t.apar);
     pack_dihedral_groups(s, W, &t.didx, &t.dpar);
     t.mass.assign(t.npad, 0.0);
     t.mtot = 0;
@@ -645,13 +811,12 @@ void carve(Carver& st, Carver& wk, const pamd_system& s, const pamd_params& p, i
     std::vector<double> zeros(std::max({s.n_bonds, s.n_angles, s.n_dihedrals, 1}), 0.0);
     pack_terms(s.n_bonds, 2, s.bond_idx, zeros.data(), zeros.data(), rec, par, W);
     const int nb_slots = (int)(rec.size() / 4);
-    pack_terms(s.n_angles, 3, s.angle_idx, zeros.data(), zeros.data(), rec, par, W);
-    const int na_slots = (int)(rec.size() / 4);
+    const int na_slots = std::max(pack_angle_groups(s, W, nullptr, nullptr), 1);
     const int nd_slots = std::max(pack_dihedral_groups(s, W, nullptr, nullptr), 1);
     d.bidx = wk.take<int4>(nb_slots);
     d.bpar = wk.take<real>((size_t)nb_slots * 2);
-    d.aidx = wk.take<int4>(na_slots);
-    d.apar = wk.take<real>((size_t)na_slots * 2);
+    d.agrp = wk.take<int4>((size_t)na_slots * 2);
+    d.agpar = wk.take<real>((size_t)na_slots * 12);
     d.dgrp = wk.take<int4>((size_t)nd_slots * 2);
     d.dgpar = wk.take<real>((size_t)nd_slots * 18);
     d.mass = wk.take<double>(npad);
@@ -665,7 +830,7 @@ void carve(Carver& st, Carver& wk, const pamd_system& s, const pamd_params& p, i
     d.npad = npad;
     d.nslot = nslot;
     d.nb = s.n_bonds > 0 ? nb_slots : 0;
-    d.na = s.n_angles > 0 ? na_slots : 0;
+    d.nag = s.n_angles > 0 ? na_slots : 0;
     d.ng = s.n_dihedrals > 0 ? nd_slots : 0;
     d.R_target = p.R_target;
     d.R_cap = Rc;
@@ -728,8 +893,8 @@ hipError_t upload(const RunDev<real>& d, const HostTables& t, hipStream_t s)
     }
     if ((e = upi(d.bidx, t.bidx)) != hipSuccess) return e;
     if ((e = up(d.bpar, t.bpar)) != hipSuccess) return e;
-    if ((e = upi(d.aidx, t.aidx)) != hipSuccess) return e;
-    if ((e = up(d.apar, t.apar)) != hipSuccess) return e;
+    if (!t.aidx.empty() && (e = upi(d.agrp, t.aidx)) != hipSuccess) return e;
+    if (!t.apar.empty() && (e = up(d.agpar, t.apar)) != hipSuccess) return e;
     if (!t.didx.empty() && (e = upi(d.dgrp, t.didx)) != hipSuccess) return e;
     if (!t.dpar.empty() && (e = up(d.dgpar, t.dpar)) != hipSuccess) return e;
     if ((e = upd(d.mass, t.mass)) != hipSuccess) return e;
