@@ -390,29 +390,28 @@ __device__ __forceinline__ void bonded_terms(const RunDev<real>& d, const real* 
                 const real q2 = n1[a][0] * n1[a][0] + n1[a][1] * n1[a][1] + n1[a][2] * n1[a][2];
                 n1sq[a] = ia[a] < 0 ? (real)1 : q2 < (real)1e-30 ? (real)1e-30 : q2;
             }
-            // k side: b3 = x_l - x_k, n2 = b2 x b3, q_l = b3.b2 / |b2|^2
-            real n2[3][3], n2sq[3], ql[3];
+            // k side, one outer atom l at a time (b3 = x_l - x_k, n2 = b2 x b3,
+            // q_l = b3.b2 / |b2|^2): its torsions with every i, then its force
+            real Di[3] = {(real)0, (real)0, (real)0};
+            real fj[3] = {(real)0, (real)0, (real)0}, fk[3] = {(real)0, (real)0, (real)0};
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 real pl[3];
                 ld3(pos, la[c] >= 0 ? la[c] : ga.y, pl);
                 const real b3x = pl[0] - pk[0], b3y = pl[1] - pk[1], b3z = pl[2] - pk[2];
-                n2[c][0] = b2y * b3z - b2z * b3y;
-                n2[c][1] = b2z * b3x - b2x * b3z;
-                n2[c][2] = b2x * b3y - b2y * b3x;
-                ql[c] = (b3x * b2x + b3y * b2y + b3z * b2z) * ib2;
-                const real q2 = n2[c][0] * n2[c][0] + n2[c][1] * n2[c][1] + n2[c][2] * n2[c][2];
-                n2sq[c] = la[c] < 0 ? (real)1 : q2 < (real)1e-30 ? (real)1e-30 : q2;
-            }
-            real Di[3] = {(real)0, (real)0, (real)0}, El[3] = {(real)0, (real)0, (real)0};
+                const real n2x = b2y * b3z - b2z * b3y;
+                const real n2y = b2z * b3x - b2x * b3z;
+                const real n2z = b2x * b3y - b2y * b3x;
+                const real q2 = n2x * n2x + n2y * n2y + n2z * n2z;
+                // absent outer atoms (their torsions carry kc = 0) keep every product finite
+                const real n2sq = la[c] < 0 ? (real)1 : q2 < (real)1e-30 ? (real)1e-30 : q2;
+                real El = (real)0;
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
+                for (int a = 0; a < 3; ++a) {
                     const real kc = par[2 * (3 * a + c)];
                     const int nmul = (int)par[2 * (3 * a + c) + 1];
-                    const real inn = rsq_(n1sq[a] * n2sq[c]);
-                    const real cphi = (n1[a][0] * n2[c][0] + n1[a][1] * n2[c][1] + n1[a][2] * n2[c][2]) * inn;
+                    const real inn = rsq_(n1sq[a] * n2sq);
+                    const real cphi = (n1[a][0] * n2x + n1[a][1] * n2y + n1[a][2] * n2z) * inn;
                     // Chebyshev: T_n(c) = cos(n phi), U_{n-1}(c) = sin(n phi) / sin(phi)
                     real tp = (real)1, tc = cphi, up = (real)0, uc = (real)1;
                     for (int q = 1; q < nmul; ++q) {
@@ -426,21 +425,34 @@ __device__ __forceinline__ void bonded_terms(const RunDev<real>& d, const real* 
                     if constexpr (ENERGY) {
                         eacc += (double)(fabs(kc) + kc * tc);
                     } else {
-                        const real sphi = lb2 * (b1[a][0] * n2[c][0] + b1[a][1] * n2[c][1] + b1[a][2] * n2[c][2]) * inn;
+                        const real sphi = lb2 * (b1[a][0] * n2x + b1[a][1] * n2y + b1[a][2] * n2z) * inn;
                         // dU/dphi = -kc n sin(n phi) = -kc n sin(phi) U_{n-1}(cos phi)
                         const real dU = -kc * (real)nmul * sphi * uc;
                         Di[a] += dU;
-                        El[c] += dU;
+                        El += dU;
                     }
+                }
+                if constexpr (!ENERGY) {
+                    // E_l g_l with g_l = |b2| n2 / |n2|^2
+                    const real sc = lb2 * rcp_(n2sq) * El;
+                    const real gx = sc * n2x, gy = sc * n2y, gz = sc * n2z;
+                    const real qc = (b3x * b2x + b3y * b2y + b3z * b2z) * ib2;
+                    fj[0] -= qc * gx;
+                    fj[1] -= qc * gy;
+                    fj[2] -= qc * gz;
+                    fk[0] += ((real)1 + qc) * gx;
+                    fk[1] += ((real)1 + qc) * gy;
+                    fk[2] += ((real)1 + qc) * gz;
+                    if (la[c] >= 0)
+                        add3<real, ENERGY>(frc, la[c], -gx, -gy, -gz);
                 }
             }
             if constexpr (!ENERGY) {
-                real fj[3] = {(real)0, (real)0, (real)0}, fk[3] = {(real)0, (real)0, (real)0};
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
                     // D_i g_i with g_i = -|b2| n1 / |n1|^2
-                    const real s = -lb2 * rcp_(n1sq[a]) * Di[a];
-                    const real gx = s * n1[a][0], gy = s * n1[a][1], gz = s * n1[a][2];
+                    const real sa = -lb2 * rcp_(n1sq[a]) * Di[a];
+                    const real gx = sa * n1[a][0], gy = sa * n1[a][1], gz = sa * n1[a][2];
                     const real pa = (b1[a][0] * b2x + b1[a][1] * b2y + b1[a][2] * b2z) * ib2;
                     fj[0] += ((real)1 + pa) * gx;
                     fj[1] += ((real)1 + pa) * gy;
@@ -450,21 +462,6 @@ __device__ __forceinline__ void bonded_terms(const RunDev<real>& d, const real* 
                     fk[2] -= pa * gz;
                     if (ia[a] >= 0)
                         add3<real, ENERGY>(frc, ia[a], -gx, -gy, -gz);
-                }
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    // E_l g_l with g_l = |b2| n2 / |n2|^2
-                    const real s = lb2 * rcp_(n2sq[c]) * El[c];
-                    const real gx = s * n2[c][0], gy = s * n2[c][1], gz = s * n2[c][2];
-                    const real qc = ql[c];
-                    fj[0] -= qc * gx;
-                    fj[1] -= qc * gy;
-                    fj[2] -= qc * gz;
-                    fk[0] += ((real)1 + qc) * gx;
-                    fk[1] += ((real)1 + qc) * gy;
-                    fk[2] += ((real)1 + qc) * gz;
-                    if (la[c] >= 0)
-                        add3<real, ENERGY>(frc, la[c], -gx, -gy, -gz);
                 }
                 add3<real, ENERGY>(frc, ga.x, fj[0], fj[1], fj[2]);
                 add3<real, ENERGY>(frc, ga.y, fk[0], fk[1], fk[2]);
