@@ -374,18 +374,17 @@ __device__ __forceinline__ void bonded_terms(const RunDev<real>& d, const real* 
             const real b2sq = b2x * b2x + b2y * b2y + b2z * b2z;
             const real lb2 = sqrt_(b2sq);
             const real ib2 = rcp_(b2sq);
-            // j side: b1 = x_j - x_i, n1 = b1 x b2
-            real b1[3][3], n1[3][3], n1sq[3];
+            // j side: b1 = x_j - x_i, n1 = b1 x b2, p_i = b1.b2 / |b2|^2
+            real n1[3][3], n1sq[3], pi_[3];
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 real pi[3];
                 ld3(pos, ia[a] >= 0 ? ia[a] : ga.x, pi);
-                b1[a][0] = pj[0] - pi[0];
-                b1[a][1] = pj[1] - pi[1];
-                b1[a][2] = pj[2] - pi[2];
-                n1[a][0] = b1[a][1] * b2z - b1[a][2] * b2y;
-                n1[a][1] = b1[a][2] * b2x - b1[a][0] * b2z;
-                n1[a][2] = b1[a][0] * b2y - b1[a][1] * b2x;
+                const real b1x = pj[0] - pi[0], b1y = pj[1] - pi[1], b1z = pj[2] - pi[2];
+                n1[a][0] = b1y * b2z - b1z * b2y;
+                n1[a][1] = b1z * b2x - b1x * b2z;
+                n1[a][2] = b1x * b2y - b1y * b2x;
+                pi_[a] = (b1x * b2x + b1y * b2y + b1z * b2z) * ib2;
                 // absent outer atoms (their torsions carry kc = 0) keep every product finite
                 const real q2 = n1[a][0] * n1[a][0] + n1[a][1] * n1[a][1] + n1[a][2] * n1[a][2];
                 n1sq[a] = ia[a] < 0 ? (real)1 : q2 < (real)1e-30 ? (real)1e-30 : q2;
@@ -425,7 +424,8 @@ __device__ __forceinline__ void bonded_terms(const RunDev<real>& d, const real* 
                     if constexpr (ENERGY) {
                         eacc += (double)(fabs(kc) + kc * tc);
                     } else {
-                        const real sphi = lb2 * (b1[a][0] * n2x + b1[a][1] * n2y + b1[a][2] * n2z) * inn;
+                        // sin phi = |b2| b1.(b2 x b3) / (|n1| |n2|), and b1.(b2 x b3) = n1.b3
+                        const real sphi = lb2 * (n1[a][0] * b3x + n1[a][1] * b3y + n1[a][2] * b3z) * inn;
                         // dU/dphi = -kc n sin(n phi) = -kc n sin(phi) U_{n-1}(cos phi)
                         const real dU = -kc * (real)nmul * sphi * uc;
                         Di[a] += dU;
@@ -453,7 +453,7 @@ __device__ __forceinline__ void bonded_terms(const RunDev<real>& d, const real* 
                     // D_i g_i with g_i = -|b2| n1 / |n1|^2
                     const real sa = -lb2 * rcp_(n1sq[a]) * Di[a];
                     const real gx = sa * n1[a][0], gy = sa * n1[a][1], gz = sa * n1[a][2];
-                    const real pa = (b1[a][0] * b2x + b1[a][1] * b2y + b1[a][2] * b2z) * ib2;
+                    const real pa = pi_[a];
                     fj[0] += ((real)1 + pa) * gx;
                     fj[1] += ((real)1 + pa) * gy;
                     fj[2] += ((real)1 + pa) * gz;
