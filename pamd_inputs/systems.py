@@ -155,6 +155,46 @@ def bead_chain(n: int = 10, seed: int = 1, jitter: float = 0.05) -> System:
         kB=1.0, x_init=_f64(x), units="reduced")
 
 
+def branched_pair(seed: int = 3, jitter: float = 0.04) -> System:
+    """Two six-coordinated hubs joined by one bond, in reduced units: hub 0 and
+    hub 1 each carry five leaves (12 atoms, 11 bonds), so each hub is the centre
+    of 15 angles and the hub-hub bond is the central bond of 25 torsions; the
+    torsions with i = leaf 2 carry a second term (n = 1, delta = pi) besides
+    the n = 3 one, as force fields often stack terms on one quadruple.  Masses
+    1..3, charges +-0.2, LJ sigma 0.6, epsilon 0.5; 1-4 pairs scaled by 0.5
+    (LJ) and 0.8 (Coulomb).  Start: leaves on two cones about the hub axis,
+    with seeded N(0, jitter^2) noise."""
+    rng = np.random.default_rng(seed)
+    n = 12
+    bonds = [(0, 1)] + [(0, a) for a in range(2, 7)] + [(1, a) for a in range(7, 12)]
+    bonds = _i32(bonds).reshape(-1, 2)
+    ang, dih = angles_and_dihedrals_from_bonds(n, bonds)
+    dih = np.asarray(dih, np.int32).reshape(-1, 4)
+    extra = [d for d in dih if 2 in (d[0], d[3])]
+    dih_all = np.concatenate([dih, np.asarray(extra, np.int32).reshape(-1, 4)])
+    dk = np.concatenate([np.full(len(dih), 1.5), np.full(len(extra), 0.7)])
+    dn = np.concatenate([np.full(len(dih), 3), np.full(len(extra), 1)]).astype(np.int32)
+    dd = np.concatenate([np.zeros(len(dih)), np.full(len(extra), math.pi)])
+    x = np.zeros((n, 3))
+    x[1] = (1.0, 0.0, 0.0)
+    for q in range(5):
+        phi = 2 * math.pi * q / 5
+        x[2 + q] = (-0.45, 0.9 * math.cos(phi), 0.9 * math.sin(phi))
+        x[7 + q] = (1.45, 0.9 * math.cos(phi + 0.3), 0.9 * math.sin(phi + 0.3))
+    x += rng.normal(0.0, jitter, size=(n, 3))
+    q = np.where(np.arange(n) % 2 == 0, 0.2, -0.2)
+    return System(
+        name="branched_pair", n_atoms=n,
+        mass=1.0 + (np.arange(n) % 3).astype(np.float64), charge=_f64(q), sigma=np.full(n, 0.6),
+        epsilon=np.full(n, 0.5), atype=(np.arange(n) % 8).astype(np.int32),
+        bonds=bonds, bond_k=np.full(len(bonds), 100.0), bond_r0=np.ones(len(bonds)),
+        angles=np.asarray(ang, np.int32).reshape(-1, 3), angle_k=np.full(len(ang), 20.0),
+        angle_theta0=np.full(len(ang), math.radians(100.0)),
+        dihedrals=dih_all, dih_k=dk, dih_n=dn, dih_delta=dd,
+        scale14_lj=0.5, scale14_coul=0.8, coulomb_k=1.0, dielectric=DIELECTRIC_VACUUM,
+        kB=1.0, x_init=_f64(x), units="reduced")
+
+
 def gaussian_chain(n: int = 10, k: float = 100.0, r0: float = 0.0) -> System:
     """Bonds-only chain in reduced units: no angles, dihedrals or nonbonded
     interactions (epsilon = charge = 0).  With r0 = 0 every bond vector is an

@@ -262,6 +262,7 @@ class Pamd:
             R_cap = max(int(np.ceil(1.02 * R_target)), R_target + 64)
         self.R_cap = int(R_cap)
         self.R_target = int(R_target)
+        self.fp32 = int(precision) == PAMD_FP32
         self._keep: list = []
         S = pamd_system * self.n_runs
         P = pamd_params * self.n_runs

@@ -18,6 +18,7 @@ pytestmark = pytest.mark.gpu
 
 from oracle import oracle as O  # noqa: E402
 from pamd_inputs import systems as S  # noqa: E402
+from pamd_inputs.precision import as_stored  # noqa: E402
 
 
 @pytest.fixture(scope="module")
@@ -50,8 +51,9 @@ def test_langevin_trajectory_matches_oracle(B, which, prec, tol):
     x = _perturbed(sysd, R, scale, 4)
     v = O.init_velocities(osys, R, T, seed=6)
     p.set_state(0, x, v, T=T, step=300)
+    xo, vo = as_stored(x, prec), as_stored(v, prec)
     st = p.get_state(0)
-    xo, vo = st["x"].copy(), st["v"].copy()
+    assert np.array_equal(st["x"], xo) and np.array_equal(st["v"], vo)
     p.md_steps(n_steps)
     g = p.get_state(0)
     Ep, Ek = O.md_steps(osys, xo, vo, n_steps, T, dt, gamma, 91, step0=300, thermostat="langevin")

@@ -21,6 +21,7 @@ pytestmark = pytest.mark.gpu
 from oracle import nn as NN  # noqa: E402
 from oracle import oracle as O  # noqa: E402
 from pamd_inputs import systems as S  # noqa: E402
+from pamd_inputs.precision import as_stored  # noqa: E402
 
 
 @pytest.fixture(scope="module")
@@ -143,8 +144,9 @@ def test_export_configs_nonbonded_forces(B):
     p.set_state(0, x, np.zeros_like(x), T=700.0)
     xg, fg = p.export_configs(0, 0, R)
     xg, fg = xg.cpu().numpy().astype(np.float64), fg.cpu().numpy().astype(np.float64)
-    assert np.abs(xg - x).max() < 1e-6
-    Fo = O.energy_forces(osys, xg, O.T_LJ | O.T_COUL)[1]
+    xs = as_stored(x, True)
+    assert np.array_equal(xg, xs)
+    Fo = O.energy_forces(osys, xs, O.T_LJ | O.T_COUL)[1]
     frms = np.sqrt((Fo ** 2).sum(-1).mean(-1))[:, None]
     bound = 1e-4 * (np.linalg.norm(Fo, axis=-1) + frms)
     assert (np.linalg.norm(fg - Fo, axis=-1) <= bound).all()
@@ -152,19 +154,24 @@ def test_export_configs_nonbonded_forces(B):
 
 
 def _respa_case(B, w, n_outer, M, seed=41):
-    """Both sides start from the same relaxed state: 300 plain MD steps on
-    the GPU from the built conformation (a perturbed start has clashes whose
+    """Both sides start from the same relaxed state: 300 plain MD steps of the
+    oracle from the built conformation (a perturbed start has clashes whose
     repulsion a 4 fs outer impulse cannot integrate stably, and unstable
-    trajectories diverge at rounding level).  With an untrained or zero
-    surrogate the outer impulse carries the whole stiff nonbonded force, so
-    the parity cases use an outer step of 2 inner steps."""
+    trajectories diverge at rounding level), stored in FP32.  With an untrained
+    or zero surrogate the outer impulse carries the whole stiff nonbonded
+    force, so the parity cases use an outer step of 2 inner steps."""
     sysd = S.c2_system()
     R, T, dt, nu = 45, 700.0, 0.001, 1.0
     osys = O.OracleSystem(sysd)
+    x0 = np.ascontiguousarray(np.broadcast_to(sysd.x_init, (R, sysd.n_atoms, 3)).astype(np.float64))
+    v0 = O.init_velocities(osys, R, T, seed)
+    O.md_steps(osys, x0, v0, 300, T, dt, nu, seed, 0)
+    step0 = 300
+    xo, vo = as_stored(x0, True), as_stored(v0, True)
     p = B.Pamd([sysd], R_target=R, T0=T, dt=dt, nu=nu, seed=seed, precision=B.PAMD_FP32)
-    p.md_steps(300)
+    p.set_state(0, x0, v0, T=T, step=step0)
     st = p.get_state(0)
-    xo, vo, step0 = st["x"].copy(), st["v"].copy(), st["step"]
+    assert np.array_equal(st["x"], xo) and np.array_equal(st["v"], vo)
     print("start: max |F_nb|", np.abs(O.energy_forces(osys, xo, O.T_LJ | O.T_COUL)[1]).max(), flush=True)
     nn = B.PamdNN(sysd, sysd.atype)
     if w is not None:

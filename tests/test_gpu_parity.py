@@ -20,6 +20,7 @@ pytestmark = pytest.mark.gpu
 
 from oracle import oracle as O  # noqa: E402
 from pamd_inputs import systems as S  # noqa: E402
+from pamd_inputs.precision import as_stored  # noqa: E402
 
 
 @pytest.fixture(scope="module")
@@ -60,7 +61,8 @@ def test_forces_and_energies(gpu, which, prec):
     x = _perturbed(sysd, R, 0.1 if which == "chain" else 0.01, 5)
     v = np.zeros_like(x)
     p.set_state(0, x, v, T=700.0 if which == "peptide" else 2.0)
-    xs = p.get_state(0)["x"]               # the positions as the GPU holds them
+    xs = as_stored(x, prec)                # the positions as the context stores them
+    assert np.array_equal(p.get_state(0)["x"], xs)
     F, E = p.get_forces(0)
     osys = O.OracleSystem(sysd)
     Eo, Fo, terms = O.energy_forces(osys, xs, want_terms=True)
@@ -100,8 +102,9 @@ def test_trajectory_matches_oracle(gpu, which, prec, nsteps, tol):
     x = _perturbed(sysd, R, 0.005 if which == "peptide" else 0.05, 8)
     v = O.init_velocities(osys, R, T, seed=3)
     p.set_state(0, x, v, T=T, step=500)
+    xo, vo = as_stored(x, prec).copy(), as_stored(v, prec).copy()
     st = p.get_state(0)
-    xo, vo = st["x"].copy(), st["v"].copy()
+    assert np.array_equal(st["x"], xo) and np.array_equal(st["v"], vo)
     p.md_steps(nsteps)
     g = p.get_state(0)
     Ep, Ek, col = O.md_steps(osys, xo, vo, nsteps, T, 0.001 if which == "peptide" else 0.002, nu, 77,
@@ -117,11 +120,19 @@ def test_trajectory_matches_oracle(gpu, which, prec, nsteps, tol):
 
 
 def _synthetic_population(p, sysd, R, E, T, seed=0):
+    """Sets a seeded population with energies E; returns it as the context
+    stores it (rounded on the host), after checking the device holds exactly that."""
     rng = np.random.default_rng(seed)
     x = _perturbed(sysd, R, 0.01, seed)
     v = rng.normal(size=x.shape)
     p.set_state(0, x, v, T=T, E_pot=E, ancestor=np.arange(R) + 1000 * 0)
-    return p.get_state(0)
+    fp32 = p.fp32
+    st = dict(x=as_stored(x, fp32), v=as_stored(v, fp32), E_pot=np.asarray(E, np.float64).copy(),
+              ancestor=np.arange(R))
+    g = p.get_state(0)
+    assert np.array_equal(g["x"], st["x"]) and np.array_equal(g["v"], st["v"])
+    assert np.array_equal(g["E_pot"], st["E_pot"])
+    return st
 
 
 @pytest.mark.parametrize("R", [1, 7, 1000, 4099])
@@ -198,16 +209,29 @@ def test_adaptive_temperature_matches_oracle(gpu):
 
 
 def test_observables_match_oracle(gpu):
+    """Population averages (PAMD step 4): exact FP64 reductions of host-given
+    energies and ancestors; then, after an energy evaluation, the kinetic
+    averages against the host's 1/2 m v^2 of the stored velocities."""
     sysd = S.c2_system()
     R = 333
+    rng = np.random.default_rng(12)
     p = _ctx(gpu, sysd, R, 1)
-    p.md_steps(10)
+    E = rng.normal(-300.0, 20.0, R)
+    anc = rng.integers(0, 40, R).astype(np.int32)
+    x = _perturbed(sysd, R, 0.01, 13)
+    v = rng.normal(0, 0.5, x.shape)
+    p.set_state(0, x, v, T=700.0, E_pot=E, ancestor=anc, step=10)
     obs = p.observables()[0]
-    st = p.get_state(0)
-    o = O.observables(st["E_pot"], st["E_kin"], st["ancestor"], sysd.n_atoms, sysd.kB, 700.0)
-    for k in ("E_mean", "E2_mean", "K_mean", "T_measured", "Cv"):
+    vs = as_stored(v, True)
+    K = 0.5 * (sysd.mass[None, :, None] * vs * vs).sum((1, 2))
+    o = O.observables(E, K, anc, sysd.n_atoms, sysd.kB, 700.0)
+    for k in ("E_mean", "E2_mean", "Cv"):
         assert abs(obs[k] - o[k]) <= 1e-12 * abs(o[k]) + 1e-12, k
-    assert obs["R"] == R and obs["families"] == R and obs["step"] == 10
+    assert obs["R"] == R and obs["families"] == o["families"] and obs["step"] == 10
+    p.md_steps(0)                              # E_pot and E_kin of the stored state
+    obs = p.observables()[0]
+    for k in ("K_mean", "T_measured"):
+        assert abs(obs[k] - o[k]) <= 1e-6 * abs(o[k]), k
     p.close()
 
 

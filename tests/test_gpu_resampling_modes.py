@@ -21,6 +21,7 @@ pytestmark = pytest.mark.gpu
 
 from oracle import oracle as O  # noqa: E402
 from pamd_inputs import systems as S  # noqa: E402
+from pamd_inputs.precision import as_stored  # noqa: E402
 
 EPS = 2.0 ** -52
 
@@ -35,11 +36,18 @@ def B():
 
 
 def _population(p, run, sysd, R, E, T, seed):
+    """Sets a seeded population; returns it as the context stores it (rounded
+    on the host), after checking that the device holds exactly that."""
     rng = np.random.default_rng(seed)
     x = np.ascontiguousarray(sysd.x_init[None] + rng.normal(0, 0.01, (R,) + sysd.x_init.shape))
     v = rng.normal(size=x.shape)
     p.set_state(run, x, v, T=T, E_pot=E, ancestor=np.arange(R))
-    return p.get_state(run)
+    st = dict(x=as_stored(x, p.fp32), v=as_stored(v, p.fp32), E_pot=np.asarray(E, np.float64).copy(),
+              ancestor=np.arange(R))
+    g = p.get_state(run)
+    assert np.array_equal(g["x"], st["x"]) and np.array_equal(g["v"], st["v"])
+    assert np.array_equal(g["E_pot"], st["E_pot"])
+    return st
 
 
 def _assert_draws_match(c, E, dbeta, u):
@@ -119,17 +127,21 @@ def test_multinomial_philox_draws_match_oracle_per_run(B):
 
 def test_multinomial_at_the_full_population(B):
     """R = 1e5 FP32 peptide copies (the population of the headline workload),
-    energies with the spread of a thermal 75-atom peptide, adaptive step: every
-    draw against the oracle, population size exactly R."""
+    energies with the spread of a thermal 75-atom peptide, the oracle's
+    adaptive step: every draw against the oracle, population size exactly R."""
     sysd = S.c2_system()
     R = 100_000
     p = B.Pamd([sysd], R_target=R, T0=700.0, dt=0.001, nu=1.0, seed=77, precision=B.PAMD_FP32,
                T_final=250.0, resampling="multinomial")
     E = np.random.default_rng(5).gamma(219 / 2, sysd.kB * 700.0, R) - 800.0
     st = _population(p, 0, sysd, R, E, 700.0, 6)
-    p.resample(None)
+    # the oracle's adaptive step, requested explicitly so both sides use one T
+    kB = sysd.kB
+    db = O.adaptive_dbeta(st["E_pot"], 1 / (kB * 250.0) - 1 / (kB * 700.0), 0.1)
+    T1 = 1 / (kB * (db + 1 / (kB * 700.0)))
+    db = 1 / (kB * T1) - 1 / (kB * 700.0)
+    p.resample([T1])
     g = p.get_state(0, want_xv=False)
-    db = 1 / (sysd.kB * g["T"]) - 1 / (sysd.kB * 700.0)
     u = O.multinomial_uniforms(R, 1, seed=77)
     c = p.get_counts(0)
     _, amb = _assert_draws_match(c, st["E_pot"], db, u)

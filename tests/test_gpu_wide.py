@@ -19,6 +19,7 @@ pytestmark = pytest.mark.gpu
 
 from oracle import oracle as O  # noqa: E402
 from pamd_inputs import systems as S  # noqa: E402
+from pamd_inputs.precision import as_stored  # noqa: E402
 
 SIZES = (40, 120, 300)
 
@@ -70,8 +71,9 @@ def test_wide_forces_and_energies(B):
         p.set_state(r, x, np.zeros_like(x), T=700.0)
         F, E = p.get_forces(r)
         osys = O.OracleSystem(sysd)
-        st = p.get_state(r)
-        Eo, Fo, terms = O.energy_forces(osys, st["x"], want_terms=True)
+        xs = as_stored(x, True)
+        assert np.array_equal(p.get_state(r)["x"], xs)
+        Eo, Fo, terms = O.energy_forces(osys, xs, want_terms=True)
         frms = np.sqrt((Fo ** 2).sum(-1).mean(-1))[:, None]
         ratio = (np.linalg.norm(F - Fo, axis=-1) / (1e-4 * (np.linalg.norm(Fo, axis=-1) + frms))).max()
         print(f"n={sysd.n_atoms}: force error / bound {ratio:.3f}")
@@ -93,8 +95,9 @@ def test_wide_trajectories_match_oracle(B):
         x = _perturbed(sysd, R, 0.003, 8 + r)
         v = O.init_velocities(osys, R, T, seed=3 + r)
         p.set_state(r, x, v, T=T, step=500)
+        starts.append((as_stored(x, True), as_stored(v, True)))
         st = p.get_state(r)
-        starts.append((st["x"].copy(), st["v"].copy()))
+        assert np.array_equal(st["x"], starts[-1][0]) and np.array_equal(st["v"], starts[-1][1])
     p.md_steps(n_steps)
     for r, sysd in enumerate(syss):
         osys = O.OracleSystem(sysd)

@@ -26,13 +26,15 @@ def _fd_forces(osys, x, mask, h):
     return G
 
 
-@pytest.mark.parametrize("which", ["chain", "peptide"])
+@pytest.mark.parametrize("which", ["chain", "peptide", "branched"])
 @pytest.mark.parametrize("mask", [O.T_BOND, O.T_ANGLE, O.T_DIHEDRAL, O.T_LJ, O.T_COUL, O.T_ALL])
 def test_forces_are_minus_energy_gradient(which, mask):
-    sysd = S.c1_system() if which == "chain" else S.c2_system()
+    """Every term type on the bead chain, the peptide and the branched pair
+    (six-coordinated hubs, stacked torsion terms on one quadruple)."""
+    sysd = {"chain": S.c1_system, "peptide": S.c2_system, "branched": S.branched_pair}[which]()
     osys = O.OracleSystem(sysd)
     rng = np.random.default_rng(11)
-    noise = 0.1 if which == "chain" else 0.01
+    noise = 0.01 if which == "peptide" else 0.1
     x = sysd.x_init + rng.normal(0, noise, size=sysd.x_init.shape)
     E, F = O.energy_forces(osys, x, mask)
     G = _fd_forces(osys, x, mask, 1e-6)
