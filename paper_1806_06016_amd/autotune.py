@@ -23,21 +23,25 @@ def _cache_path() -> str:
     return os.path.join(base, "pamd_autotune.json")
 
 
-def _key(sysd, precision: int) -> str:
+def _key(sysd, precision: int, R_probe: int) -> str:
     import torch
     arch = torch.cuda.get_device_properties(0).gcnArchName
     with open(LIB_PATH, "rb") as f:
         lib = hashlib.sha256(f.read()).hexdigest()[:16]
-    return f"N{sysd.n_atoms}-diel{int(sysd.dielectric)}-p{precision}-{arch}-{lib}"
+    return f"N{sysd.n_atoms}-diel{int(sysd.dielectric)}-p{precision}-{arch}-{lib}-R{R_probe}"
 
 
-def autotune(sysd, precision: int = PAMD_FP32, R_probe: int = 16384, theta_probe: int = 50,
+def autotune(sysd, precision: int = PAMD_FP32, R_probe: int = 65536, theta_probe: int = 100,
              candidates: Sequence[int] = CANDIDATES, T0: float = 700.0, dt: float = 0.001,
              use_cache: bool = True, cache_path: Optional[str] = None) -> Dict:
-    """Returns {"waves_per_block": w, "timings": {w: replica-steps/s}, "cached": bool}."""
+    """Returns {"waves_per_block": w, "timings": {w: replica-steps/s}, "cached": bool}.
+
+    The probe population should be the one the run will use (or large): the
+    persistent kernel hands out 4-replica work items to every resident wave,
+    and a probe with about one item per wave times the tail, not the rate."""
     import torch
     path = cache_path or _cache_path()
-    key = _key(sysd, precision)
+    key = _key(sysd, precision, R_probe)
     cache = {}
     if use_cache and os.path.exists(path):
         try:
@@ -53,7 +57,7 @@ def autotune(sysd, precision: int = PAMD_FP32, R_probe: int = 16384, theta_probe
         p.md_steps(theta_probe)
         torch.cuda.synchronize()
         best = None
-        for _ in range(2):
+        for _ in range(3):
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record(p.stream)
