@@ -74,6 +74,8 @@ __device__ __forceinline__ float rsq_(float x) { return __builtin_amdgcn_rsqf(x)
 __device__ __forceinline__ double rsq_(double x) { return 1.0 / sqrt(x); }
 __device__ __forceinline__ float sqrt_(float x) { return __builtin_sqrtf(x); }
 __device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
+__device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float atan2_(float y, float x) { return atan2f(y, x); }
 __device__ __forceinline__ double atan2_(double y, double x) { return atan2(y, x); }
 
@@ -162,7 +164,11 @@ __device__ __forceinline__ Coef<real> load_coef(const real* ab_lane, const real*
     return c;
 }
 
-template <typename real, int DIEL, int KBACK, bool ENERGY>
+// ACC: (fxj, fyj, fzj) is an unrotated accumulator of the partner's reaction
+// forces, rotated back once by the caller after all the pair steps that share
+// the partner block and rotation; otherwise the reaction goes straight to the
+// partner's force by the opposite rotation
+template <typename real, int DIEL, int KBACK, bool ENERGY, bool ACC = false>
 __device__ __forceinline__ void pair_step(real xi, real yi, real zi, real xjr, real yjr, real zjr,
                                           real& fxi, real& fyi, real& fzi, real& fxj, real& fyj,
                                           real& fzj, const Coef<real>& cf, double& eacc)
@@ -199,15 +205,24 @@ __device__ __forceinline__ void pair_step(real xi, real yi, real zi, real xjr, r
             const real t1 = A * ir6 + nB;
             fs = t1 * ir4 * ir4 + C * ir2 * ir;
         }
-        // force on i = fs (x_i - x_j) = -fs d ; on j = +fs d, returned to the
-        // lane that owns j by the opposite rotation
-        const real tx = fs * dx, ty = fs * dy, tz = fs * dz;
-        fxi -= tx;
-        fyi -= ty;
-        fzi -= tz;
-        fxj += rowrot<KBACK>(tx);
-        fyj += rowrot<KBACK>(ty);
-        fzj += rowrot<KBACK>(tz);
+        // force on i = fs (x_i - x_j) = -fs d ; on j = +fs d
+        if constexpr (ACC) {
+            fxi = fma_(-fs, dx, fxi);
+            fyi = fma_(-fs, dy, fyi);
+            fzi = fma_(-fs, dz, fzi);
+            fxj = fma_(fs, dx, fxj);
+            fyj = fma_(fs, dy, fyj);
+            fzj = fma_(fs, dz, fzj);
+        } else {
+            // returned to the lane that owns j by the opposite rotation
+            const real tx = fs * dx, ty = fs * dy, tz = fs * dz;
+            fxi -= tx;
+            fyi -= ty;
+            fzi -= tz;
+            fxj += rowrot<KBACK>(tx);
+            fyj += rowrot<KBACK>(ty);
+            fzj += rowrot<KBACK>(tz);
+        }
     }
 }
 
@@ -239,20 +254,30 @@ __device__ __forceinline__ void nonbonded(Regs<real, NS>& r, const real* tab_ab,
             // math of many steps into spilled registers
             __builtin_amdgcn_sched_barrier(0);
         });
-        // blocks I < J against block J rotated by K
-        static_for<0, 16>([&](auto Kc) {
-            constexpr int K = decltype(Kc)::value;
-            const real xr = rowrot<K>(r.x[J]), yr = rowrot<K>(r.y[J]), zr = rowrot<K>(r.z[J]);
-            static_for<0, J>([&](auto Ic) {
-                constexpr int I = decltype(Ic)::value;
-                constexpr int st = base + 8 + K * J + I;
-                const Coef<real> nxt = load_coef<(st + 1 < NST ? st + 1 : st)>(ab_lane, c_lane);
-                pair_step<real, DIEL, (16 - K) & 15, ENERGY>(r.x[I], r.y[I], r.z[I], xr, yr, zr, r.fx[I], r.fy[I],
-                                                             r.fz[I], r.fx[J], r.fy[J], r.fz[J], cur, eacc);
-                cur = nxt;
-                __builtin_amdgcn_sched_barrier(0);
+        // blocks I < J against block J rotated by K: the reactions of the J
+        // pair steps that share this rotated copy accumulate unrotated and go
+        // back to block J by one opposite rotation
+        if constexpr (J > 0) {
+            static_for<0, 16>([&](auto Kc) {
+                constexpr int K = decltype(Kc)::value;
+                const real xr = rowrot<K>(r.x[J]), yr = rowrot<K>(r.y[J]), zr = rowrot<K>(r.z[J]);
+                real gx = (real)0, gy = (real)0, gz = (real)0;
+                static_for<0, J>([&](auto Ic) {
+                    constexpr int I = decltype(Ic)::value;
+                    constexpr int st = base + 8 + K * J + I;
+                    const Coef<real> nxt = load_coef<(st + 1 < NST ? st + 1 : st)>(ab_lane, c_lane);
+                    pair_step<real, DIEL, (16 - K) & 15, ENERGY, true>(r.x[I], r.y[I], r.z[I], xr, yr, zr, r.fx[I],
+                                                                       r.fy[I], r.fz[I], gx, gy, gz, cur, eacc);
+                    cur = nxt;
+                    __builtin_amdgcn_sched_barrier(0);
+                });
+                if constexpr (!ENERGY) {
+                    r.fx[J] += rowrot<(16 - K) & 15>(gx);
+                    r.fy[J] += rowrot<(16 - K) & 15>(gy);
+                    r.fz[J] += rowrot<(16 - K) & 15>(gz);
+                }
             });
-        });
+        }
     });
 }
 
