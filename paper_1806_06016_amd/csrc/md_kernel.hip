@@ -1181,11 +1181,41 @@ __device__ __forceinline__ void wide_evaluate(WideRegs& r, const RunDev<float>& 
                     s4[s] = ((uint64_t)m1.y << 32) | m0.y;
                 }
             }
+            // steps k at which some lane of own slot s meets an excluded or 1-4
+            // partner of slot t (bit k of stepmask[t][s], wave-uniform); every
+            // other step takes the pair code without masks and scale factors
+            uint64_t smask[kWideSlots];
+#pragma unroll
+            for (int s = 0; s <= t; ++s)
+                smask[s] = d.stepmask[t * kWideSlots + s];
             const int kend = (t == 0) ? 33 : kWide;
             for (int k = 0; k < kend; ++k) {
 #pragma unroll
                 for (int s = 0; s <= t; ++s) {
-                    if (s < t || (k >= 1 && k <= 32)) {
+                    if ((s < t || (k >= 1 && k <= 32)) && !((smask[s] >> k) & 1ull)) {
+                        const float dx = r.x[s] - px, dy = r.y[s] - py, dz = r.z[s] - pz;
+                        const float r2 = dx * dx + dy * dy + dz * dz;
+                        const float ir2 = rcp_(r2);
+                        const float sig = r.sg[s] + psg;
+                        const float tt = sig * sig * ir2;
+                        const float t3 = tt * tt * tt;
+                        const float e4 = r.se[s] * pse;
+                        const float C = r.qs[s] * pqs;
+                        if constexpr (ENERGY) {
+                            const float uc = (DIEL == 1) ? 0.5f * C * ir2 : C * rsq_(r2);
+                            eacc += (double)(e4 * t3 * (t3 - 1.f) + uc);
+                        } else {
+                            const float flj = e4 * t3 * (12.f * t3 - 6.f) * ir2;
+                            const float fc = (DIEL == 1) ? C * ir2 * ir2 : C * ir2 * rsq_(r2);
+                            const float g = flj + fc;
+                            r.fx[s] = fma_(g, dx, r.fx[s]);
+                            r.fy[s] = fma_(g, dy, r.fy[s]);
+                            r.fz[s] = fma_(g, dz, r.fz[s]);
+                            pfx = fma_(-g, dx, pfx);
+                            pfy = fma_(-g, dy, pfy);
+                            pfz = fma_(-g, dz, pfz);
+                        }
+                    } else if (s < t || (k >= 1 && k <= 32)) {
                         bool skip = ((ex[s] >> pid) & 1ull) != 0ull;
                         if (s == t && k == 32 && pid < lane)
                             skip = true;

@@ -93,6 +93,8 @@ struct RunDev {
     // bit masks (excluded pair incl. self, scaled 1-4 pair)
     const float4* apar4;    // [n]
     const uint2* pmask;     // [n][nchunk]
+    const uint64_t* stepmask;   // [t][s] (5 x 5): bit k set when some lane of own slot s meets an
+                                // excluded or 1-4 partner of slot t at rotation step k
     int32_t nchunk;
     int32_t wide;
     float s14lj, s14c;

@@ -71,6 +71,7 @@ struct HostTables {
     int wide = 0, nchunk = 0;
     std::vector<double> atomp;           // wide layout: [n][4] per-atom pair parameters
     std::vector<uint32_t> pmask;         // wide layout: [n][nchunk][2] exclusion / 1-4 bits
+    std::vector<uint64_t> stepmask;      // wide layout: [t][s] rotation steps that need the masks
     std::vector<double> ab, c;           // [steps][16][2], [steps][16]
     std::vector<int32_t> bidx, aidx, didx;  // int4 records (dihedrals: two per group slot)
     std::vector<double> bpar, apar, dpar;   // dihedrals: 18 per group slot
@@ -768,6 +769,23 @@ void build_tables(const pamd_system& s, HostTables& t, int wide)
                     t.pmask[w + 1] |= 1u << (j & 31);
             }
         }
+        // rotation steps of the nonbonded ring that meet an excluded or 1-4
+        // pair on some lane: at step k own atom 64 s + l meets partner
+        // 64 t + (l + k) mod 64; the same-slot ring also keeps its k = 32 step
+        // (the pair seen from both lanes) on the masked path
+        t.stepmask.assign((size_t)kWideSlots * kWideSlots, 0ull);
+        const int nsl = (n + kWide - 1) / kWide;
+        for (int tt = 0; tt < nsl; ++tt)
+            for (int ss = 0; ss <= tt; ++ss) {
+                uint64_t m = ss == tt ? (1ull | (1ull << 32)) : 0ull;
+                for (int k = 0; k < kWide; ++k)
+                    for (int l = 0; l < kWide && !((m >> k) & 1ull); ++l) {
+                        const int a = kWide * ss + l, j = kWide * tt + (l + k) % kWide;
+                        if (a < n && j < n && (a == j || dist[(size_t)a * n + j] <= 3))
+                            m |= 1ull << k;
+                    }
+                t.stepmask[(size_t)tt * kWideSlots + ss] = m;
+            }
     }
     pack_terms(s.n_bonds, 2, s.bond_idx, s.bond_k, s.bond_r0, t.bidx, t.bpar, W);
     pack_angle_groups(s, W, &t.aidx, &t.apar);
@@ -852,6 +870,7 @@ void carve(Carver& st, Carver& wk, const pamd_system& s, const pamd_params& p, i
     d.nchunk = wide ? nchunk : 0;
     d.apar4 = wide ? wk.take<float4>(n) : nullptr;
     d.pmask = wide ? wk.take<uint2>((size_t)n * nchunk) : nullptr;
+    d.stepmask = wide ? wk.take<uint64_t>((size_t)kWideSlots * kWideSlots) : nullptr;
     d.s14lj = (float)s.scale14_lj;
     d.s14c = (float)s.scale14_coul;
 }
@@ -887,6 +906,9 @@ hipError_t upload(const RunDev<real>& d, const HostTables& t, hipStream_t s)
             hipSuccess)
             return e;
         if ((e = hipMemcpyAsync((void*)d.pmask, t.pmask.data(), t.pmask.size() * sizeof(uint32_t),
+                                hipMemcpyHostToDevice, s)) != hipSuccess)
+            return e;
+        if ((e = hipMemcpyAsync((void*)d.stepmask, t.stepmask.data(), t.stepmask.size() * sizeof(uint64_t),
                                 hipMemcpyHostToDevice, s)) != hipSuccess)
             return e;
         if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
