@@ -5,8 +5,8 @@
 //             Q = (1/R) sum_j exp(-(1/kB T_i - 1/kB T_{i-1}) E_j)        (PAMD scheme, step 2)
 //             evaluated as m = min E, S = sum exp(-dbeta (E - m)), ln Q = -dbeta m + ln S - ln R;
 //             ln Q_i estimates ln Z(T_i) - ln Z(T_{i-1}) and is summed on the device
-//   adaptive  T_i: largest step whose normalised weight variance R sum p^2 - 1
-//             stays within the target, by bisection on dbeta
+//   adaptive  T_i: the step whose normalised weight variance R sum p^2 - 1
+//             equals the target, by safeguarded Newton iterations on dbeta
 //   counts    nearest: c_j = floor(tau_j) + [u_j < frac(tau_j)], tau_j = R_target w_j / S;
 //             multinomial: R_target independent draws from p_j = w_j / S (the rule
 //             stated after the scheme), each an inverse-CDF binary search over
@@ -78,6 +78,27 @@ __device__ __forceinline__ int64_t block_exscan(int64_t v, int64_t* sh, int64_t*
     *total = sh[kBlk - 1];
     __syncthreads();
     return inc - v;
+}
+
+// S = sum w, S1 = sum w e, S2 = sum w^2, S21 = sum w^2 e with e = E - m and
+// w = exp(-db e), fixed order
+__device__ __forceinline__ void weight_moments(const double* E, int64_t R, double db, double m, double* sh,
+                                               double* S, double* S1, double* S2, double* S21)
+{
+    double s = 0.0, s1 = 0.0, s2 = 0.0, s21 = 0.0;
+    for (int64_t j = threadIdx.x; j < R; j += kBlk) {
+        const double e = E[j] - m;
+        const double w = exp(-db * e);
+        const double ww = w * w;
+        s += w;
+        s1 += w * e;
+        s2 += ww;
+        s21 += ww * e;
+    }
+    *S = block_sum(s, sh);
+    *S1 = block_sum(s1, sh);
+    *S2 = block_sum(s2, sh);
+    *S21 = block_sum(s21, sh);
 }
 
 // sums S = sum w, S2 = sum w^2 with w = exp(-db (E - m)), fixed order
@@ -197,18 +218,42 @@ __global__ __launch_bounds__(kBlk) void k_weights(RunDev<real> d, double T_req)
             if ((double)R * S2 / (S * S) - 1.0 <= d.V_target) {
                 Tn = d.T_final;
             } else {
+                // root of V(b) = V_target in (0, dmax) (V grows with b): Newton
+                // steps on V, each one O(R) pass for S, S1 = sum w e, S2 and
+                // S21 = sum w^2 e (e = E - m), dV/db = 2 R (S2 S1 / S^3 - S21 / S^2);
+                // a step leaving the bracket [lo, hi] bisects instead.  Start:
+                // the Gaussian-energy solution sqrt(ln(1 + V_target)) / std(E).
                 double lo = 0.0, hi = dmax;
+                double e1 = 0.0, e2 = 0.0;
+                for (int64_t j = threadIdx.x; j < R; j += kBlk) {
+                    const double e = E[j] - mn;
+                    e1 += e;
+                    e2 += e * e;
+                }
+                e1 = block_sum(e1, sh) / (double)R;
+                e2 = block_sum(e2, sh) / (double)R;
+                const double var = e2 - e1 * e1;
+                double b = var > 0.0 ? sqrt(log1p(d.V_target) / var) : 0.5 * dmax;
+                if (!(b > lo && b < hi))
+                    b = 0.5 * (lo + hi);
                 for (int it = 0; it < 64; ++it) {
-                    const double mid = 0.5 * (lo + hi);
-                    weight_sums(E, R, mid, mn, sh, &S, &S2);
-                    if ((double)R * S2 / (S * S) - 1.0 <= d.V_target)
-                        lo = mid;
+                    double S1, S21;
+                    weight_moments(E, R, b, mn, sh, &S, &S1, &S2, &S21);
+                    const double V = (double)R * S2 / (S * S) - 1.0;
+                    if (V <= d.V_target)
+                        lo = b;
                     else
-                        hi = mid;
-                    if (hi - lo <= 1e-12 * hi)
+                        hi = b;
+                    const double dV = 2.0 * (double)R * (S2 * S1 / (S * S * S) - S21 / (S * S));
+                    double bn = b - (V - d.V_target) / dV;
+                    if (!(bn > lo && bn < hi))
+                        bn = 0.5 * (lo + hi);
+                    const bool done = fabs(bn - b) <= 1e-13 * b || hi - lo <= 1e-12 * hi;
+                    b = bn;
+                    if (done)
                         break;
                 }
-                Tn = 1.0 / (kB * (lo + 1.0 / (kB * T)));
+                Tn = 1.0 / (kB * (b + 1.0 / (kB * T)));
             }
         }
     }
