@@ -140,7 +140,7 @@ def loss_grad_torch(x, F_target, atype, pairs, w):
     L = ((F - torch.tensor(F_target)) ** 2).mean()
     L.backward()
     # b3 shifts every energy by a constant: no force depends on it (grad None)
-    return float(L), {k: (v.grad.numpy().copy() if v.grad is not None else np.zeros(v.shape))
+    return float(L.detach()), {k: (v.grad.numpy().copy() if v.grad is not None else np.zeros(v.shape))
                       for k, v in t.items()}
 
 
