@@ -18,7 +18,9 @@ own slot.  Work that is O(R) on the host is compared for every replica.
 * PAMD step 2: the adaptive temperature within 1e-9 relative of the oracle's
   bisection; with the oracle's temperature requested explicitly, every copy
   number bit-exact, ancestors and energies of the gathered population exact,
-  sampled positions recentred within 2e-6 nm, ln Q within 1e-12 relative.
+  sampled positions recentred within 2e-6 nm, ln Q within 1e-12 relative;
+* the batched workload (eight peptides, R = 4096 each, wide layout): 100 NVT
+  steps of sampled slots of every run, same tolerances as above.
 """
 import math
 
@@ -163,4 +165,42 @@ def test_copy_numbers_and_gather_at_full_population(B, sysd):
     assert np.abs(g["x"][rows] - xr).max() < 2e-6
     assert np.abs(g["v"][rows] - vo[src[rows]] * math.sqrt(T1 / T0)).max() < 1e-6 * np.abs(vo).max()
     print("families", p.observables()[0]["families"], "R", g["R"])
+    p.close()
+
+
+def test_batched_workload_sampled(B):
+    """The batched workload as timed (eight peptides of 40-300 atoms, R = 4096
+    each, 0.5 fs, one persistent wide launch with the default launch shape):
+    100 NVT steps, sampled slots of every run against the oracle (Philox key
+    of that run), every slot's state checked by properties."""
+    syss = S.c4_systems()
+    Rb, dt = 4096, 0.0005
+    p = B.Pamd(syss, R_target=Rb, T0=T0, dt=dt, nu=NU, seed=SEED, precision=B.PAMD_FP32)
+    print("launch", p.launch_info(), flush=True)
+    starts = []
+    for r, sysd in enumerate(syss):
+        rng = np.random.default_rng(40 + r)
+        x = np.ascontiguousarray(sysd.x_init[None] + rng.normal(0, 0.003, (Rb,) + sysd.x_init.shape))
+        v = np.ascontiguousarray(rng.normal(size=x.shape) * np.sqrt(sysd.kB * T0 / sysd.mass)[None, :, None])
+        p.set_state(r, x, v, T=T0, step=500)
+        starts.append((as_stored(x, True), as_stored(v, True)))
+    n_steps = 100
+    p.md_steps(n_steps)
+    rng = np.random.default_rng(41)
+    for r, sysd in enumerate(syss):
+        g = p.get_state(r)
+        assert g["step"] == 500 + n_steps and g["R"] == Rb
+        assert np.isfinite(g["x"]).all() and np.isfinite(g["E_pot"]).all()
+        ek = 0.5 * (sysd.mass[None, :] * (g["v"].astype(np.float64) ** 2).sum(-1)).sum(-1)
+        assert np.abs(g["E_kin"] - ek).max() <= 1e-12 * np.abs(ek).max()
+        slots = np.unique(np.r_[0, 1, 63, 64, Rb - 1, rng.choice(Rb, 5, replace=False)]).astype(np.int64)
+        xo, vo = starts[r]
+        xs, vs = np.ascontiguousarray(xo[slots]), np.ascontiguousarray(vo[slots])
+        Ep, Ek = O.md_steps(O.OracleSystem(sysd), xs, vs, n_steps, T0, dt, NU, SEED, step0=500, run=r,
+                            slots=slots)
+        err = np.abs(g["x"][slots] - xs).max()
+        print(f"run {r} n={sysd.n_atoms}: max |dx| {err:.2e}")
+        assert err < 1e-4
+        assert np.abs(g["E_pot"][slots] - Ep).max() <= 1e-3 * np.abs(Ep).mean()
+        assert np.allclose(g["E_kin"][slots], Ek, rtol=1e-3)
     p.close()
