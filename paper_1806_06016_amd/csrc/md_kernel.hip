@@ -1205,9 +1205,10 @@ __device__ __forceinline__ void wide_evaluate(WideRegs& r, const RunDev<float>& 
                             const float uc = (DIEL == 1) ? 0.5f * C * ir2 : C * rsq_(r2);
                             eacc += (double)(e4 * t3 * (t3 - 1.f) + uc);
                         } else {
-                            const float flj = e4 * t3 * (12.f * t3 - 6.f) * ir2;
-                            const float fc = (DIEL == 1) ? C * ir2 * ir2 : C * ir2 * rsq_(r2);
-                            const float g = flj + fc;
+                            // g = (e4 t3 (12 t3 - 6) + C c) / r^2, c = 1 / r^2 (dielectric 4r)
+                            // or 1 / r (vacuum): the LJ and Coulomb parts share one 1 / r^2
+                            const float w = e4 * t3 * fma_(12.f, t3, -6.f);
+                            const float g = fma_(C, (DIEL == 1) ? ir2 : rsq_(r2), w) * ir2;
                             r.fx[s] = fma_(g, dx, r.fx[s]);
                             r.fy[s] = fma_(g, dy, r.fy[s]);
                             r.fz[s] = fma_(g, dz, r.fz[s]);
@@ -1237,9 +1238,8 @@ __device__ __forceinline__ void wide_evaluate(WideRegs& r, const RunDev<float>& 
                             eacc += skip ? 0.0 : (double)u;
                         } else {
                             // force on the own atom = g (x_own - x_partner), on the partner -g (...)
-                            const float flj = e4 * t3 * (12.f * t3 - 6.f) * ir2;
-                            const float fc = (DIEL == 1) ? C * ir2 * ir2 : C * ir2 * rsq_(r2);
-                            float g = slj * flj + sc * fc;
+                            const float w = e4 * t3 * fma_(12.f, t3, -6.f);
+                            float g = fma_(sc * C, (DIEL == 1) ? ir2 : rsq_(r2), slj * w) * ir2;
                             g = skip ? 0.f : g;
                             r.fx[s] += g * dx;
                             r.fy[s] += g * dy;
