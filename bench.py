@@ -240,7 +240,7 @@ def main():
     waves = args.waves
     if waves == 0 and not args.no_autotune:
         from paper_1806_06016_amd.autotune import autotune
-        tuned = autotune(sysd, PAMD_FP32, R_probe=min(R, 131072))
+        tuned = autotune(sysd, PAMD_FP32, R_probe=min(R, 131072), thermostat=args.thermostat)
         waves = tuned["waves_per_block"]
     p = Pamd([sysd], R_target=R, T0=T0, dt=dt, nu=nu, seed=seed, precision=PAMD_FP32,
              V_target=0.1, T_final=T_final, waves_per_block=waves, resampling=args.resampling,

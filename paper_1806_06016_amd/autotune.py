@@ -2,9 +2,11 @@
 
 Times ``pamd_md_steps`` of a probe population on the GPU for each candidate
 number of waves per workgroup (which sets replicas per workgroup, LDS per
-workgroup and therefore waves per CU) and keeps the fastest.  Results are
-cached per (system size, dielectric, precision, GPU architecture, library
-build) in a JSON file, so a run pays for the sweep once.
+workgroup and therefore waves per CU) and keeps the fastest.  The probe runs
+the kernel of the run's thermostat (the Langevin variant holds more registers).
+Results are cached per (system size, dielectric, precision, thermostat, GPU
+architecture, library build, probe size) in a JSON file, so a run pays for the
+sweep once.
 """
 from __future__ import annotations
 
@@ -23,17 +25,17 @@ def _cache_path() -> str:
     return os.path.join(base, "pamd_autotune.json")
 
 
-def _key(sysd, precision: int, R_probe: int) -> str:
+def _key(sysd, precision: int, R_probe: int, thermostat: str) -> str:
     import torch
     arch = torch.cuda.get_device_properties(0).gcnArchName
     with open(LIB_PATH, "rb") as f:
         lib = hashlib.sha256(f.read()).hexdigest()[:16]
-    return f"N{sysd.n_atoms}-diel{int(sysd.dielectric)}-p{precision}-{arch}-{lib}-R{R_probe}"
+    return f"N{sysd.n_atoms}-diel{int(sysd.dielectric)}-p{precision}-{thermostat}-{arch}-{lib}-R{R_probe}"
 
 
 def autotune(sysd, precision: int = PAMD_FP32, R_probe: int = 65536, theta_probe: int = 100,
              candidates: Sequence[int] = CANDIDATES, T0: float = 700.0, dt: float = 0.001,
-             use_cache: bool = True, cache_path: Optional[str] = None) -> Dict:
+             use_cache: bool = True, cache_path: Optional[str] = None, thermostat: str = "andersen") -> Dict:
     """Returns {"waves_per_block": w, "timings": {w: replica-steps/s}, "cached": bool}.
 
     The probe population should be the one the run will use (or large): the
@@ -41,7 +43,7 @@ def autotune(sysd, precision: int = PAMD_FP32, R_probe: int = 65536, theta_probe
     and a probe with about one item per wave times the tail, not the rate."""
     import torch
     path = cache_path or _cache_path()
-    key = _key(sysd, precision, R_probe)
+    key = _key(sysd, precision, R_probe, thermostat)
     cache = {}
     if use_cache and os.path.exists(path):
         try:
@@ -53,7 +55,7 @@ def autotune(sysd, precision: int = PAMD_FP32, R_probe: int = 65536, theta_probe
     timings = {}
     for w in candidates:
         p = Pamd([sysd], R_target=R_probe, T0=T0, dt=dt, nu=1.0, seed=1, precision=precision,
-                 waves_per_block=w)
+                 waves_per_block=w, thermostat=thermostat)
         p.md_steps(theta_probe)
         torch.cuda.synchronize()
         best = None

@@ -81,3 +81,10 @@ def test_autotuner_returns_a_candidate(B, tmp_path):
     assert r["waves_per_block"] in (16, 8) and not r["cached"]
     r2 = autotune(sysd, R_probe=4096, theta_probe=10, candidates=(16, 8), cache_path=str(tmp_path / "c.json"))
     assert r2["cached"] and r2["waves_per_block"] == r["waves_per_block"]
+    # the Langevin kernel is another instantiation: probed and cached on its own
+    r3 = autotune(sysd, R_probe=4096, theta_probe=10, candidates=(16, 8), cache_path=str(tmp_path / "c.json"),
+                  thermostat="langevin")
+    assert r3["waves_per_block"] in (16, 8) and not r3["cached"]
+    r4 = autotune(sysd, R_probe=4096, theta_probe=10, candidates=(16, 8), cache_path=str(tmp_path / "c.json"),
+                  thermostat="langevin")
+    assert r4["cached"] and r4["waves_per_block"] == r3["waves_per_block"]
