@@ -114,3 +114,45 @@ def test_trajectory(B, kind, n, prec):
     assert np.allclose(g["E_kin"], Ek, rtol=1e-9 if prec == 0 else 1e-3)
     p.close()
 
+
+
+def test_register_tile_runs_of_different_sizes(B):
+    """One context, three runs of 33, 64 and 75 atoms (all within the register
+    tiles, so each run launches its own block count): 100 NVT steps of every
+    run against the oracle with that run's Philox key, then one resampling
+    step per run with its own temperature from host-given energies (copy
+    numbers bit-exact)."""
+    syss = [_system("peptide", n) for n in (33, 64)] + [S.c2_system()]
+    R, n_steps, seed = 9, 100, 43
+    T, dt, nu, scale = 700.0, 0.0005, 2.0, 0.003
+    p = B.Pamd(syss, R_target=R, T0=T, dt=dt, nu=nu, seed=seed, precision=B.PAMD_FP32)
+    starts = []
+    for r, sysd in enumerate(syss):
+        osys = O.OracleSystem(sysd)
+        x = _perturbed(sysd, R, scale, 50 + r)
+        v = O.init_velocities(osys, R, T, seed=60 + r)
+        p.set_state(r, x, v, T=T, step=200)
+        starts.append((as_stored(x, True).copy(), as_stored(v, True).copy()))
+    p.md_steps(n_steps)
+    for r, sysd in enumerate(syss):
+        xo, vo = starts[r]
+        Ep, Ek = O.md_steps(O.OracleSystem(sysd), xo, vo, n_steps, T, dt, nu, seed, step0=200, run=r)
+        g = p.get_state(r)
+        err = np.abs(g["x"] - xo).max()
+        print(f"run {r} n={sysd.n_atoms}: max |dx| {err:.2e}")
+        assert err < 1e-4 and g["step"] == 200 + n_steps
+        assert np.abs(g["E_pot"] - Ep).max() <= 1e-3 * np.abs(Ep).mean()
+    # resampling from host-given energies (the oracle never takes device output)
+    temps = [690.0, 680.0, 670.0]
+    E = []
+    for r, sysd in enumerate(syss):
+        E.append(np.random.default_rng(70 + r).normal(-300.0, 15.0, R))
+        xo, vo = starts[r]
+        p.set_state(r, xo, vo, T=T, E_pot=E[r], ancestor=np.arange(R))
+    p.resample(temps)
+    for r, sysd in enumerate(syss):
+        db = 1 / (sysd.kB * temps[r]) - 1 / (sysd.kB * T)
+        u = O.resample_uniforms(R, 1, seed=seed, run=r)
+        co, _ = O.copy_counts(E[r], db, R, u)
+        assert (p.get_counts(r) == co).all()
+    p.close()
