@@ -68,7 +68,8 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        _lib = C.CDLL(build())
+        # PAMD_ORACLE_LIB: another build of oracle.c (the sanitizer test uses it)
+        _lib = C.CDLL(os.environ.get("PAMD_ORACLE_LIB") or build())
         vp, i32, i64, d = C.c_void_p, C.c_int32, C.c_int64, C.c_double
         _lib.ora_philox4x32_10.argtypes = [vp, vp, vp]
         _lib.ora_energy_forces.argtypes = [vp, vp, vp, vp, i32]
