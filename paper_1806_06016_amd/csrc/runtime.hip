@@ -13,9 +13,23 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "nn_internal.h"
 #include "pamd.h"
 #include "pamd_internal.h"
+
+namespace {
+// Named range of one C-ABI call in the ROCm marker trace (rocprofv3
+// --marker-trace): host-side enqueue of the call's kernels; without a tracing
+// tool attached the push and pop do nothing.
+struct TraceRange {
+    explicit TraceRange(const char* name) { roctxRangePushA(name); }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange&) = delete;
+    TraceRange& operator=(const TraceRange&) = delete;
+};
+}  // namespace
 
 namespace pamd {
 hipError_t launch_md(const RunDev<float>& d, int n_steps, int blocks, int waves, hipStream_t s);
@@ -1047,6 +1061,7 @@ static pamd_status init_runs(pamd_ctx* c, const pamd_system* sys, hipStream_t s)
 pamd_status pamd_init(const pamd_system* sys, int32_t n_runs, const pamd_params* p, void* d_state,
                       size_t state_bytes, void* d_work, size_t work_bytes, void* stream, pamd_ctx** out)
 {
+    TraceRange trace_range("pamd_init");
     if (!out)
         return PAMD_ERR_ARG;
     *out = nullptr;
@@ -1180,6 +1195,7 @@ static pamd_status respa_steps(pamd_ctx* c, Run& run, int n_steps, hipStream_t s
 
 pamd_status pamd_md_steps(pamd_ctx* c, int32_t n_steps, void* stream)
 {
+    TraceRange trace_range("pamd_md_steps");
     pamd_status st = check_ctx(c);
     if (st != PAMD_OK)
         return st;
@@ -1218,6 +1234,7 @@ pamd_status pamd_md_steps(pamd_ctx* c, int32_t n_steps, void* stream)
 
 pamd_status pamd_resample(pamd_ctx* c, const double* T_next, const double* d_uniforms, void* stream)
 {
+    TraceRange trace_range("pamd_resample");
     pamd_status st = check_ctx(c);
     if (st != PAMD_OK)
         return st;
@@ -1245,6 +1262,7 @@ pamd_status pamd_resample(pamd_ctx* c, const double* T_next, const double* d_uni
 
 pamd_status pamd_observables(pamd_ctx* c, pamd_obs* out, void* stream)
 {
+    TraceRange trace_range("pamd_observables");
     pamd_status st = check_ctx(c);
     if (st != PAMD_OK)
         return st;
@@ -1306,6 +1324,7 @@ static pamd_status get_forces_t(pamd_ctx* c, Run& run, int64_t r0, int32_t count
 pamd_status pamd_get_forces(pamd_ctx* c, int32_t run, int64_t r0, int32_t count, double* host_F, double* host_E,
                             void* stream)
 {
+    TraceRange trace_range("pamd_get_forces");
     pamd_status st = check_ctx(c);
     if (st != PAMD_OK)
         return st;
@@ -1367,6 +1386,7 @@ static pamd_status get_state_t(pamd_ctx* c, Run& run, double* x, double* v, doub
 pamd_status pamd_get_state(pamd_ctx* c, int32_t run, double* x, double* v, double* E_pot, double* E_kin,
                            int32_t* ancestor, pamd_run_scalars* scalars, void* stream)
 {
+    TraceRange trace_range("pamd_get_state");
     if (!c)
         return PAMD_ERR_ARG;
     if (run < 0 || run >= c->n_runs)
@@ -1433,6 +1453,7 @@ static pamd_status set_state_t(pamd_ctx* c, Run& run, const double* x, const dou
 pamd_status pamd_set_state(pamd_ctx* c, int32_t run, const double* x, const double* v, const double* E_pot,
                            const int32_t* ancestor, const pamd_run_scalars* scalars, void* stream)
 {
+    TraceRange trace_range("pamd_set_state");
     pamd_status st = check_ctx(c);
     if (st != PAMD_OK)
         return st;
@@ -1486,6 +1507,7 @@ pamd_status pamd_launch_info(const pamd_ctx* c, int32_t* waves_per_block, int32_
 
 pamd_status pamd_set_schedule(pamd_ctx* c, int32_t run, const double* T, int32_t n, void* stream)
 {
+    TraceRange trace_range("pamd_set_schedule");
     pamd_status st = check_ctx(c);
     if (st != PAMD_OK)
         return st;
@@ -1517,6 +1539,7 @@ static void drop_graph(pamd_ctx* c, int slot)
 pamd_status pamd_graph_capture(pamd_ctx* c, int32_t slot, int32_t parts, int32_t n_steps, int32_t mode,
                                void* stream)
 {
+    TraceRange trace_range("pamd_graph_capture");
     pamd_status st = check_ctx(c);
     if (st != PAMD_OK)
         return st;
@@ -1549,6 +1572,7 @@ pamd_status pamd_graph_capture(pamd_ctx* c, int32_t slot, int32_t parts, int32_t
 
 pamd_status pamd_graph_launch(pamd_ctx* c, int32_t slot, void* stream)
 {
+    TraceRange trace_range("pamd_graph_launch");
     pamd_status st = check_ctx(c);
     if (st != PAMD_OK)
         return st;
@@ -1561,6 +1585,7 @@ pamd_status pamd_graph_launch(pamd_ctx* c, int32_t slot, void* stream)
 pamd_status pamd_export_configs(pamd_ctx* c, int32_t run, int64_t r0, int64_t count, float* d_x, float* d_F_nb,
                                 void* stream)
 {
+    TraceRange trace_range("pamd_export_configs");
     pamd_status st = check_ctx(c);
     if (st != PAMD_OK)
         return st;
