@@ -246,7 +246,12 @@ typedef struct pamd_run_scalars {
 
 /* Copy the current population of `run` to the host.  Arrays have room for
  * R_cap replicas; x, v: [R][n_atoms][3]; E_pot, E_kin: [R]; ancestor: [R].
- * Any pointer may be NULL. */
+ * Any pointer may be NULL.  After a device-side error the outputs are still
+ * filled and that error is returned: on PAMD_ERR_CAPACITY the population and
+ * scalars the failed resampling step started from, on PAMD_ERR_NONFINITE the
+ * population holding the non-finite energy; the context then accepts no
+ * further step (PAMD_ERR_STATE), so a caller recovers by moving the state to a
+ * new context. */
 pamd_status pamd_get_state(pamd_ctx* ctx, int32_t run, double* x, double* v, double* E_pot,
                            double* E_kin, int32_t* ancestor, pamd_run_scalars* scalars,
                            void* stream);

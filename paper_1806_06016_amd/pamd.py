@@ -377,7 +377,10 @@ class Pamd:
             E[c0:c0 + c] = Ec
         return F, E
 
-    def get_state(self, run: int = 0, want_xv: bool = True) -> Dict:
+    def get_state(self, run: int = 0, want_xv: bool = True, after_error: bool = False) -> Dict:
+        """Population and scalars of `run`.  With after_error, a context stopped
+        by PAMD_ERR_CAPACITY or PAMD_ERR_NONFINITE still returns its state (key
+        "error" holds the code) instead of raising."""
         n = self.n_atoms[run]
         sc = pamd_run_scalars()
         x = np.zeros((self.R_cap, n, 3)) if want_xv else None
@@ -385,12 +388,14 @@ class Pamd:
         Ep = np.zeros(self.R_cap)
         Ek = np.zeros(self.R_cap)
         anc = np.zeros(self.R_cap, np.int32)
-        self._check(self.lib.pamd_get_state(self.ctx, run, _ptr(x), _ptr(v), _ptr(Ep), _ptr(Ek), _ptr(anc),
-                                            C.byref(sc), self._s()), self.ctx)
+        st = self.lib.pamd_get_state(self.ctx, run, _ptr(x), _ptr(v), _ptr(Ep), _ptr(Ek), _ptr(anc), C.byref(sc),
+                                     self._s())
+        if not (after_error and st in (PAMD_ERR_CAPACITY, PAMD_ERR_NONFINITE)):
+            self._check(st, self.ctx)
         R = int(sc.R)
         d = dict(R=R, T=sc.T, T_prev=sc.T_prev, sum_lnQ=sc.sum_lnQ, lnQ_last=sc.lnQ_last, step=int(sc.step),
                  temp_index=int(sc.temp_index), E_pot=Ep[:R].copy(), E_kin=Ek[:R].copy(),
-                 ancestor=anc[:R].copy())
+                 ancestor=anc[:R].copy(), error=int(st))
         if want_xv:
             d["x"] = x[:R].copy()
             d["v"] = v[:R].copy()

@@ -243,14 +243,33 @@ def test_capacity_overflow_is_reported_and_state_kept(gpu):
     E[:100] = 0.0
     E[100:] = 50.0
     p = _ctx(gpu, sysd, R, 0, R_cap=220)
-    _synthetic_population(p, sysd, R, E, 2.0)
+    st = _synthetic_population(p, sysd, R, E, 2.0)
     # half of the copies get ~2 copies each only if weights are flat; make them not:
     u = torch.zeros(p.R_cap, dtype=torch.float64, device="cuda")      # every fractional part rounds up
     p.resample([1.0], uniforms=u)
     with pytest.raises(PamdError) as ei:
         p.observables()
     assert ei.value.code in (PAMD_ERR_CAPACITY,)
+    # the stopped context still hands out the population the failed step
+    # started from, so a caller can recover (e.g. retry with a smaller step)
+    g = p.get_state(0, after_error=True)
+    assert g["error"] == PAMD_ERR_CAPACITY and g["R"] == R and g["T"] == 2.0
+    assert np.array_equal(g["x"], st["x"]) and np.array_equal(g["v"], st["v"])
+    assert np.array_equal(g["E_pot"], st["E_pot"]) and (g["ancestor"] == np.arange(R)).all()
+    with pytest.raises(PamdError) as ei:
+        p.md_steps(1)
+    assert ei.value.code == gpu.PAMD_ERR_STATE
     p.close()
+    # recovery: the rescued population in a new context, a smaller step
+    q = _ctx(gpu, sysd, R, 0, R_cap=220)
+    q.set_state(0, g["x"], g["v"], T=g["T"], E_pot=g["E_pot"], ancestor=g["ancestor"], step=g["step"])
+    q.resample([1.9])                         # the context's own Philox uniforms
+    o = q.observables()[0]
+    dbeta = 1 / 1.9 - 1 / 2.0
+    co, _ = O.copy_counts(st["E_pot"], dbeta, R, O.resample_uniforms(R, 1, seed=1806))
+    assert (q.get_counts(0) == co).all()
+    assert o["R"] == co.sum() <= 220 and o["T"] == 1.9
+    q.close()
 
 
 def test_nonfinite_energy_is_reported(gpu):
@@ -265,6 +284,12 @@ def test_nonfinite_energy_is_reported(gpu):
     with pytest.raises(PamdError) as ei:
         p.observables()
     assert ei.value.code == PAMD_ERR_NONFINITE
+    # the population is still readable: the bad replica is the one with the NaN
+    g = p.get_state(0, after_error=True)
+    assert g["error"] == PAMD_ERR_NONFINITE
+    bad = ~np.isfinite(g["E_pot"])
+    assert bad.tolist() == [r == 3 for r in range(R)]
+    assert np.isnan(g["x"][3, 5, 0]) and np.isfinite(np.delete(g["x"], 3, axis=0)).all()
     p.close()
 
 
