@@ -184,6 +184,7 @@ def batched(args):
                    "replicas_per_run": R, "theta": args.theta, "T": obs[0]["T"]},
         "pair_interactions_per_s": pairs_total / el,
         "md_kernel_ms_avg": md_s / args.steps * 1e3,
+        "md_kernel_ms_median": float(np.median([a.elapsed_time(b) for a, b in ev])),
         "launch": info,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_VALU_TFLOPS,
@@ -332,6 +333,7 @@ def main():
                    "T_range": [obs_log[0]["T"], obs_log[-1]["T"]]},
         "pair_interactions_per_s": value * pairs,
         "md_kernel_ms_avg": float(np.mean(md_ms)),
+        "md_kernel_ms_median": float(np.median(md_ms)),
         "md_replica_steps_per_s": R_steps / md_s,
         "resampling": {"mode": args.resampling, "ms_avg": float(np.mean(rs_ms)),
                        "gather_bytes": gather_bytes,
