@@ -733,6 +733,10 @@ __global__ __launch_bounds__(1024) void k_md(RunDev<real> d, int n_steps)
     real* frc = pos + 3 * d.n;
 
     const RunCtl* ctl = d.ctl;
+    // a run with a sticky error keeps its state (uniform over the launch:
+    // only k_md_begin writes `frozen`)
+    if (ctl->frozen)
+        return;
     const int64_t R = ctl->R_cur;
     const int cur = ctl->cur;
     const uint32_t step0 = ctl->step;
@@ -839,7 +843,7 @@ __global__ __launch_bounds__(1024) void k_md(RunDev<real> d, int n_steps)
         if (valid) {
             store_replica<real, NS>(r, slab, l16);
             if (l16 == 0)
-                d.ekin[slot] = ek;
+                d.ekin[cur][slot] = ek;
         }
     }
 }
@@ -862,6 +866,8 @@ __global__ __launch_bounds__(1024) void k_energy(RunDev<real> d)
     const int lane = threadIdx.x & 63, row = lane >> 4, l16 = lane & 15, wave = threadIdx.x >> 6;
     real* pos = stage + (size_t)(wave * kRowsPerWave + row) * 6 * d.n;
     real* frc = pos + 3 * d.n;
+    if (d.ctl->frozen)
+        return;
     const int64_t R = d.ctl->R_cur;
     const int cur = d.ctl->cur;
     const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
@@ -960,6 +966,8 @@ __global__ __launch_bounds__(1024) void k_respa(RunDev<float> d, const float* fn
     for (int i = l16; i < 3 * d.n; i += kRow)
         frc[i] = 0.f;
     const RunCtl* ctl = d.ctl;
+    if (ctl->frozen)
+        return;
     const int64_t R = ctl->R_cur;
     const int cur = ctl->cur;
     const uint32_t gstep = ctl->step + step_off;
@@ -1054,7 +1062,7 @@ __global__ __launch_bounds__(1024) void k_respa(RunDev<float> d, const float* fn
         if (valid) {
             store_replica<float, NS>(r, slab, l16);
             if (!(ops & kRespaDrift) && l16 == 0)
-                d.ekin[slot] = ek;
+                d.ekin[cur][slot] = ek;
         }
     }
 }
@@ -1366,7 +1374,8 @@ __global__ __launch_bounds__(256, 3) void k_md_wide(const RunDev<float>* runs, c
         int64_t rep = g;
         for (int q = 0; q < n_runs; ++q) {
             const int run = order[q];
-            const int64_t R = runs[run].ctl->R_cur;
+            // frozen runs (sticky error at the start of the call) hand out no items
+            const int64_t R = runs[run].ctl->frozen ? 0 : runs[run].ctl->R_cur;
             if (rep < R) {
                 k = run;
                 break;
@@ -1485,11 +1494,19 @@ __global__ __launch_bounds__(256, 3) void k_md_wide(const RunDev<float>* runs, c
         wide_store(r, d, slab, lane, nsl);
         if (lane == 0) {
             d.epot[cur][rep] = ep;
-            d.ekin[rep] = ek;
+            d.ekin[cur][rep] = ek;
             if (!isfinite(ep))
                 atomicCAS(&d.ctl->error, 0, 4);
         }
     }
+}
+
+// start of a batched MD call: every run whose sticky error is set stays
+// frozen for the whole call
+__global__ void k_wide_begin(RunDev<float>* runs, int n_runs)
+{
+    for (int q = threadIdx.x; q < n_runs; q += blockDim.x)
+        runs[q].ctl->frozen = runs[q].ctl->error != 0;
 }
 
 // reset of the batch work counter and every run's step counter after k_md_wide
@@ -1499,7 +1516,8 @@ __global__ void k_wide_finalize(RunDev<float>* runs, int n_runs, int32_t* counte
         return;
     *counter = 0;
     for (int q = 0; q < n_runs; ++q) {
-        runs[q].ctl->step += (uint32_t)n_steps;
+        if (!runs[q].ctl->frozen)
+            runs[q].ctl->step += (uint32_t)n_steps;
         runs[q].ctl->work = 0;
     }
 }
@@ -1731,6 +1749,7 @@ hipError_t launch_md_wide(const RunDev<float>* runs, const int32_t* order, int n
 {
     const size_t lds = wide_lds_bytes(nmax, waves);
     const dim3 g(blocks), b(waves * 64);
+    hipLaunchKernelGGL(k_wide_begin, dim3(1), dim3(64), 0, s, const_cast<RunDev<float>*>(runs), n_runs);
     switch (diel * 2 + lang) {
     case 0: hipLaunchKernelGGL((k_md_wide<0, 0>), g, b, lds, s, runs, order, n_runs, counter, nmax, n_steps); break;
     case 1: hipLaunchKernelGGL((k_md_wide<0, 1>), g, b, lds, s, runs, order, n_runs, counter, nmax, n_steps); break;

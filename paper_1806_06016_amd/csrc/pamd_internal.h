@@ -44,7 +44,8 @@ struct alignas(64) RunCtl {
     int32_t cur;         // ping-pong buffer holding the current population
     int32_t error;       // sticky PAMD_ERR_* code
     int32_t work;        // persistent-kernel work counter
-    int32_t pad[3];
+    int32_t frozen;      // error != 0 when the current MD call began: its kernels leave the run unchanged
+    int32_t pad[2];
 };
 
 // operations of one r-RESPA kernel pass (k_respa), applied in this order
@@ -56,7 +57,7 @@ struct RunDev {
     RunCtl* ctl;
     real* slab[2];          // [R_cap][6][npad]  x | y | z | vx | vy | vz
     double* epot[2];        // [R_cap]
-    double* ekin;           // [R_cap]
+    double* ekin[2];        // [R_cap] (ping-pong with the slabs)
     int32_t* anc[2];        // [R_cap]
     int32_t* counts;        // [R_cap]
     int32_t* src_of;        // [R_cap]

@@ -140,6 +140,7 @@ __global__ void k_init(RunDev<real> d)
         c->cur = 0;
         c->error = 0;
         c->work = 0;
+        c->frozen = 0;
     }
     if (gid >= total)
         return;
@@ -169,7 +170,7 @@ __global__ void k_init(RunDev<real> d)
     if (a == 0) {
         d.anc[0][r] = (int32_t)r;
         d.epot[0][r] = 0.0;
-        d.ekin[r] = 0.0;
+        d.ekin[0][r] = 0.0;
     }
 }
 
@@ -438,6 +439,7 @@ __global__ __launch_bounds__(256) void k_gather(RunDev<real> d, double mtot)
     const real* src_all = d.slab[cur];
     real* dst_all = d.slab[cur ^ 1];
     const real vs = (real)sqrt(c->T_next / c->T_cur);
+    const double ks = c->T_next / c->T_cur;   // kinetic energy of the rescaled copy
     const int lane = threadIdx.x & 63;
     const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
     const int npad = d.npad, n = d.n;
@@ -475,6 +477,7 @@ __global__ __launch_bounds__(256) void k_gather(RunDev<real> d, double mtot)
         }
         if (lane == 0) {
             d.epot[cur ^ 1][dd] = d.epot[cur][j];
+            d.ekin[cur ^ 1][dd] = d.ekin[cur][j] * ks;
             d.anc[cur ^ 1][dd] = d.anc[cur][j];
         }
     }
@@ -496,12 +499,23 @@ __global__ void k_resample_finalize(RunDev<real> d)
     c->sum_lnQ += c->lnQ_last;
 }
 
+// Start of an MD call of one run: with a sticky error set (for instance a
+// resampling over capacity) the MD, energy and finalize kernels of this call
+// leave positions, velocities, energies and the step counter unchanged.
+template <typename real>
+__global__ void k_md_begin(RunDev<real> d)
+{
+    if (threadIdx.x == 0)
+        d.ctl->frozen = d.ctl->error != 0;
+}
+
 template <typename real>
 __global__ void k_md_finalize(RunDev<real> d, int n_steps)
 {
     if (threadIdx.x != 0)
         return;
-    d.ctl->step += (uint32_t)n_steps;
+    if (!d.ctl->frozen)
+        d.ctl->step += (uint32_t)n_steps;
     d.ctl->work = 0;
 }
 
@@ -527,7 +541,7 @@ __global__ __launch_bounds__(kBlk) void k_observables(RunDev<real> d)
         const double e = E[j];
         se += e;
         se2 += e * e;
-        sk += d.ekin[j];
+        sk += d.ekin[cur][j];
     }
     se = block_sum(se, sh);
     se2 = block_sum(se2, sh);
@@ -595,6 +609,13 @@ hipError_t launch_resample_t(const RunDev<real>& d, double T_req, double mtot, i
 }
 
 template <typename real>
+hipError_t launch_md_begin_t(const RunDev<real>& d, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_md_begin<real>, dim3(1), dim3(64), 0, s, d);
+    return hipGetLastError();
+}
+
+template <typename real>
 hipError_t launch_md_finalize_t(const RunDev<real>& d, int n_steps, hipStream_t s)
 {
     hipLaunchKernelGGL(k_md_finalize<real>, dim3(1), dim3(64), 0, s, d, n_steps);
@@ -618,6 +639,8 @@ hipError_t launch_resample(const RunDev<double>& d, double T_req, double mtot, i
 {
     return launch_resample_t(d, T_req, mtot, gb, s);
 }
+hipError_t launch_md_begin(const RunDev<float>& d, hipStream_t s) { return launch_md_begin_t(d, s); }
+hipError_t launch_md_begin(const RunDev<double>& d, hipStream_t s) { return launch_md_begin_t(d, s); }
 hipError_t launch_md_finalize(const RunDev<float>& d, int n, hipStream_t s) { return launch_md_finalize_t(d, n, s); }
 hipError_t launch_md_finalize(const RunDev<double>& d, int n, hipStream_t s) { return launch_md_finalize_t(d, n, s); }
 hipError_t launch_observables(const RunDev<float>& d, hipStream_t s) { return launch_observables_t(d, s); }

@@ -44,6 +44,8 @@ hipError_t launch_init(const RunDev<float>& d, hipStream_t s);
 hipError_t launch_init(const RunDev<double>& d, hipStream_t s);
 hipError_t launch_resample(const RunDev<float>& d, double T_req, double mtot, int gb, hipStream_t s);
 hipError_t launch_resample(const RunDev<double>& d, double T_req, double mtot, int gb, hipStream_t s);
+hipError_t launch_md_begin(const RunDev<float>& d, hipStream_t s);
+hipError_t launch_md_begin(const RunDev<double>& d, hipStream_t s);
 hipError_t launch_md_finalize(const RunDev<float>& d, int n, hipStream_t s);
 hipError_t launch_md_finalize(const RunDev<double>& d, int n, hipStream_t s);
 hipError_t launch_observables(const RunDev<float>& d, hipStream_t s);
@@ -827,7 +829,8 @@ void carve(Carver& st, Carver& wk, const pamd_system& s, const pamd_params& p, i
         d.slab[b] = st.take<real>((size_t)Rc * 6 * npad);
     for (int b = 0; b < 2; ++b)
         d.epot[b] = st.take<double>(Rc);
-    d.ekin = st.take<double>(Rc);
+    for (int b = 0; b < 2; ++b)
+        d.ekin[b] = st.take<double>(Rc);
     for (int b = 0; b < 2; ++b)
         d.anc[b] = st.take<int32_t>(Rc);
     d.ctl = wk.take<RunCtl>(1);
@@ -1171,6 +1174,7 @@ static pamd_status respa_steps(pamd_ctx* c, Run& run, int n_steps, hipStream_t s
     const uint32_t p24 = (uint32_t)llround((1.0 - exp(-run.nu * Dt)) * 16777216.0);
     const float* fnn = run.mts.fnn.as<float>();
     pamd_status st = PAMD_OK;
+    HIPCHK(c, launch_md_begin(d, s));
     if (n_outer > 0) {
         if ((st = nn_force(c, run, s)) != PAMD_OK)
             return st;
@@ -1220,10 +1224,12 @@ pamd_status pamd_md_steps(pamd_ctx* c, int32_t n_steps, void* stream)
     }
     for (auto& run : c->runs) {
         if (c->fp32) {
+            HIPCHK(c, launch_md_begin(run.f, s));
             HIPCHK(c, launch_md(run.f, n_steps, c->blocks, c->waves, s));
             HIPCHK(c, launch_energy(run.f, c->blocks, c->waves, s));
             HIPCHK(c, launch_md_finalize(run.f, n_steps, s));
         } else {
+            HIPCHK(c, launch_md_begin(run.d, s));
             HIPCHK(c, launch_md(run.d, n_steps, c->blocks, c->waves, s));
             HIPCHK(c, launch_energy(run.d, c->blocks, c->waves, s));
             HIPCHK(c, launch_md_finalize(run.d, n_steps, s));
@@ -1365,7 +1371,7 @@ static pamd_status get_state_t(pamd_ctx* c, Run& run, double* x, double* v, doub
     if (Ep && R > 0)
         HIPCHK(c, hipMemcpyAsync(Ep, d.epot[cur], R * sizeof(double), hipMemcpyDeviceToHost, s));
     if (Ek && R > 0)
-        HIPCHK(c, hipMemcpyAsync(Ek, d.ekin, R * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipMemcpyAsync(Ek, d.ekin[cur], R * sizeof(double), hipMemcpyDeviceToHost, s));
     if (anc && R > 0)
         HIPCHK(c, hipMemcpyAsync(anc, d.anc[cur], R * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
@@ -1435,6 +1441,8 @@ static pamd_status set_state_t(pamd_ctx* c, Run& run, const double* x, const dou
     HIPCHK(c, hipMemcpyAsync(d.slab[cur], buf.data(), buf.size() * sizeof(real), hipMemcpyHostToDevice, s));
     HIPCHK(c, hipMemcpyAsync(d.epot[cur], e.data(), R * sizeof(double), hipMemcpyHostToDevice, s));
     HIPCHK(c, hipMemcpyAsync(d.anc[cur], an.data(), R * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    // kinetic energies are evaluated by the next MD call
+    HIPCHK(c, hipMemsetAsync(d.ekin[cur], 0, R * sizeof(double), s));
     c->have_energy = Ep ? 1 : 0;   // without energies the next resampling needs an MD call first
     ctl.R_cur = R;
     ctl.R_new = R;

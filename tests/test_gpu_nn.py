@@ -4,10 +4,12 @@ oracle in oracle/nn.py (every call through libpamd's C ABI).
 Tolerances.  The GPU rounds the features, the weight copies and the hidden
 activations / adjoints to BF16 (unit roundoff u = 2^-9 ~ 2e-3) and accumulates
 in FP32; each of the 5-6 roundings on the path from positions to forces adds
-a relative error of order u, so forces and energies are compared at 2e-2
-relative (about 10 u), the loss gradient (two more BF16 roundings: the feature
-derivative and the adjoints) at 5e-2 relative in the L2 norm of each
-parameter block.  Integrator tests use surrogate-independent bounds: with
+a relative error of order u.  Every element is checked: the force on each
+atom within 2e-2 (about 10 u) of (|F_a| + F_rms), F_rms the RMS atomic force
+of that configuration (so nearly cancelled atomic forces are not failed on
+their own magnitude); each energy within 2e-2 of (|E| + RMS energy); every loss-gradient
+component g within 5e-2 of (|g_o| + rms of its parameter block) (two more BF16
+roundings: the feature derivative and the adjoints).  Integrator tests use surrogate-independent bounds: with
 F_NN = 0 the r-RESPA trajectory matches to the FP32 MD bound (1e-4 nm); with
 a non-zero surrogate the position difference is bounded by the force
 difference, |dx| <~ (n dt)^2 |dF| / m.
@@ -42,6 +44,20 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+def _force_ratio(F, Fo, tol):
+    """max over configurations and atoms of |F_a - F_o,a| / (tol (|F_o,a| + F_rms))"""
+    F = F.reshape(-1, Fo.shape[-2], 3)
+    Fo = Fo.reshape(-1, Fo.shape[-2], 3)
+    frms = np.sqrt((Fo ** 2).sum(-1).mean(-1))[:, None]
+    return float((np.linalg.norm(F - Fo, axis=-1) / (tol * (np.linalg.norm(Fo, axis=-1) + frms))).max())
+
+
+def _grad_ratio(g, go, tol):
+    """max over the components of a parameter block of |g - g_o| / (tol (|g_o| + rms(g_o)))"""
+    rms = np.sqrt(np.mean(go ** 2))
+    return float((np.abs(g - go) / (tol * (np.abs(go) + rms))).max())
+
+
 def test_surrogate_energies_and_forces(B):
     sysd = S.c2_system()
     n = sysd.n_atoms
@@ -55,10 +71,11 @@ def test_surrogate_energies_and_forces(B):
     nn.set_weights(w)
     E, F = nn.forces(torch.tensor(x, dtype=torch.float32, device="cuda"))
     E, F = E.cpu().numpy().astype(np.float64), F.cpu().numpy().astype(np.float64)
-    errs = [_rel(F[c], Fo[c]) for c in range(nb)]
-    print("max relative force error", max(errs), "energy", np.abs(E - Eo).max() / np.abs(Eo).max())
-    assert max(errs) < 2e-2
-    assert np.abs(E - Eo).max() < 2e-2 * np.abs(Eo).max()
+    ratio = _force_ratio(F, Fo, 2e-2)
+    print("per-atom force error / bound", ratio, "L2", max(_rel(F[c], Fo[c]) for c in range(nb)),
+          "energy", np.abs(E - Eo).max() / np.abs(Eo).max())
+    assert ratio <= 1.0
+    assert np.all(np.abs(E - Eo) <= 2e-2 * (np.abs(Eo) + np.sqrt(np.mean(Eo ** 2))))
     nn.close()
 
 
@@ -83,8 +100,9 @@ def test_surrogate_small_molecule_and_single_configuration(B):
     nn.set_weights(w)
     E, F = nn.forces(torch.tensor(x, dtype=torch.float32, device="cuda"))
     F = F.cpu().numpy().astype(np.float64)
-    print("chain relative force error", _rel(F[0], Fo[0]))
-    assert _rel(F[0], Fo[0]) < 2e-2
+    ratio = _force_ratio(F, Fo, 2e-2)
+    print("chain per-atom force error / bound", ratio)
+    assert ratio <= 1.0
     assert abs(float(E[0]) - Eo[0]) < 2e-2 * abs(Eo[0]) + 1e-3
     nn.close()
 
@@ -108,9 +126,9 @@ def test_loss_gradient_matches_oracle(B):
     print("loss", lg, L)
     assert abs(lg - L) < 2e-2 * L
     for k in ("W1", "b1", "W2", "b2", "w3"):
-        e = _rel(gd[k], g[k])
-        print("gradient block", k, "relative error", e)
-        assert e < 5e-2, k
+        r = _grad_ratio(gd[k], g[k], 5e-2)
+        print("gradient block", k, "max element error / bound", r, "L2 relative", _rel(gd[k], g[k]))
+        assert r <= 1.0, k
     assert float(gd["b3"][0]) == 0.0
     nn.close()
 

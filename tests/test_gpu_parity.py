@@ -272,6 +272,55 @@ def test_capacity_overflow_is_reported_and_state_kept(gpu):
     q.close()
 
 
+@pytest.mark.parametrize("which", ["chain_fp64", "peptide_fp32", "wide_two_runs"])
+def test_capacity_overflow_then_md_steps_keeps_state(gpu, which):
+    """The calls are asynchronous, so MD steps can be enqueued after a
+    resampling that overflows the capacity on the device and before the error
+    surfaces.  Those steps must leave the failed run exactly as the resampling
+    found it (positions, velocities, E_pot and the step counter), in the
+    register-tile kernels and in the batched wide launch; in the batched
+    launch the other run still advances."""
+    from paper_1806_06016_amd import PamdError, PAMD_ERR_CAPACITY
+    R = 200
+    E = np.zeros(R)
+    E[100:] = 50.0
+    if which == "chain_fp64":
+        systems, prec, T0, T1 = [S.c1_system()], 0, 2.0, 1.0
+    elif which == "peptide_fp32":
+        systems, prec, T0, T1 = [S.c2_system()], 1, 700.0, 350.0
+    else:
+        systems, prec, T0, T1 = [S.c2_system(), S.make_peptide(1811, 120)], 1, 700.0, 350.0
+    print("capacity overflow then MD:", which, flush=True)
+    p = gpu.Pamd(systems, R_target=R, T0=T0, dt=0.002 if prec == 0 else 0.0005, nu=1.0, seed=7, precision=prec,
+                 R_cap=220)
+    st = []
+    for run, sysd in enumerate(systems):
+        rng = np.random.default_rng(40 + run)
+        x = _perturbed(sysd, R, 0.01, 40 + run)
+        v = rng.normal(0, 0.1, size=x.shape)
+        p.set_state(run, x, v, T=T0, E_pot=E, step=17)
+        st.append(dict(x=as_stored(x, prec == 1), v=as_stored(v, prec == 1)))
+    # run 0 overflows (every fractional copy number rounds up); in the two-run
+    # case run 1 is resampled at its own temperature without overflowing
+    u = torch.zeros((p.n_runs, p.R_cap), dtype=torch.float64, device="cuda")
+    if p.n_runs > 1:
+        u[1] = 0.999999
+    p.resample([T1] + [T0] * (p.n_runs - 1), uniforms=u)
+    p.md_steps(5)
+    with pytest.raises(PamdError) as ei:
+        p.observables()
+    assert ei.value.code == PAMD_ERR_CAPACITY
+    g = p.get_state(0, after_error=True)
+    assert g["error"] == PAMD_ERR_CAPACITY and g["R"] == R and g["T"] == T0 and g["step"] == 17
+    assert np.array_equal(g["x"], st[0]["x"]) and np.array_equal(g["v"], st[0]["v"])
+    assert np.array_equal(g["E_pot"], E)
+    if p.n_runs > 1:
+        h = p.get_state(1, after_error=True)
+        assert h["step"] == 17 + 5 and h["R"] == R
+        assert not np.array_equal(h["x"], st[1]["x"])
+    p.close()
+
+
 def test_nonfinite_energy_is_reported(gpu):
     from paper_1806_06016_amd import PamdError, PAMD_ERR_NONFINITE
     sysd = S.c2_system()

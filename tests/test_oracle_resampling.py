@@ -162,11 +162,16 @@ def test_gaussian_chain_free_energy_and_energies():
     bead-chain schedule T 2 -> 0.5 (20 geometric steps): Z_conf ~ beta^(-27/2),
     so sum ln Q -> 13.5 ln(0.25) = -18.715; <U> = 13.5 T and <K> = 15 T at
     every T.  The estimator's bias is O(1/R); the test allows 3 sigma over M
-    independent seeds."""
+    independent seeds.  U is a sum of 27 independent quadratic terms, i.e.
+    Gamma(13.5, T) distributed: Var U = 13.5 T^2, so the heat-capacity
+    observable Cv / kB = Var U / (kB T)^2 = 13.5 at every T, and
+    <U^2> = Var U + <U>^2 = 13.5 T^2 (1 + 13.5).  Population variances are
+    noisy (resampled copies are correlated): each temperature's Cv averaged over
+    the seeds within 12 %, the mean over all temperatures within 3 %."""
     sysd = S.gaussian_chain(10, 100.0, 0.0)
     sched = S.geometric_schedule(2.0, 0.5, 20)
     R, M = 600, 6
-    sums, U = [], []
+    sums, U, Cv, U2 = [], [], [], []
     for seed in range(1, M + 1):
         rng = np.random.default_rng(100 + seed)
         x0 = _chain_boltzmann_start(10, 100.0, 2.0, R, rng)
@@ -174,6 +179,8 @@ def test_gaussian_chain_free_energy_and_energies():
                        seed=seed, x0=x0)
         sums.append(res.sum_lnQ)
         U.append([o["E_mean"] for o in res.obs])
+        Cv.append([o["Cv"] for o in res.obs])
+        U2.append([o["E2_mean"] for o in res.obs])
         Km = np.array([o["K_mean"] for o in res.obs])
         assert np.all(np.abs(Km / (15 * np.array(res.T)) - 1) < 0.05)
     exact = 13.5 * math.log(0.25)
@@ -181,6 +188,12 @@ def test_gaussian_chain_free_energy_and_energies():
     assert abs(mean - exact) < 3 * se + 0.01, (mean, se, exact)
     Um = np.mean(U, axis=0) / (13.5 * sched)
     assert np.all(np.abs(Um - 1) < 0.03), Um
+    cv = np.mean(Cv, axis=0) / 13.5
+    print("Cv / 13.5 per temperature", np.round(cv, 3), "mean", cv.mean())
+    assert np.all(np.abs(cv - 1) < 0.12), cv
+    assert abs(cv.mean() - 1) < 0.03, cv.mean()
+    u2 = np.mean(U2, axis=0) / (13.5 * sched ** 2 * 14.5)
+    assert np.all(np.abs(u2 - 1) < 0.07), u2
 
 
 @pytest.mark.slow
@@ -228,5 +241,10 @@ def test_observables_definitions():
     K = np.array([3.0, 3.0, 6.0])
     o = O.observables(E, K, np.array([0, 0, 2]), n_atoms=2, kB=2.0, T=1.5)
     assert o["E_mean"] == pytest.approx(7 / 3)
+    # <E^2> = (1 + 4 + 16) / 3 = 7; population variance 7 - 49/9 = 14/9;
+    # Cv / kB = var / (kB T)^2 = (14/9) / 3^2 (step 4: population averages)
+    assert o["E2_mean"] == pytest.approx(7.0)
+    assert o["Cv"] == pytest.approx(14.0 / 81.0)
+    assert o["K_mean"] == pytest.approx(4.0)
     assert o["T_measured"] == pytest.approx(2 * 4.0 / (3 * 2 * 2.0))
     assert o["families"] == 2
