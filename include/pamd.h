@@ -31,11 +31,11 @@
  *    synchronisation, capturable into a HIP graph); pamd_init, pamd_observables
  *    and the pamd_get_* / pamd_set_* calls synchronise `stream`.
  *  - Host arrays passed in are only read during the call (copied).
- *  - Device memory: the caller allocates `d_state` and `d_work` (sizes from
- *    pamd_query_sizes, 256-byte aligned) and keeps them alive until
- *    pamd_destroy(); the core calls allocate no device memory.  The optional
- *    learned multiple-time-step surrogate (pamd_nn_*, pamd_set_mts) allocates
- *    its own weights, workspace and per-run buffers with hipMalloc.
+ *  - Device memory is always the caller's: `d_state` and `d_work` of a
+ *    context (sizes from pamd_query_sizes), the surrogate's parameters and
+ *    workspace (pamd_nn_query_sizes) and the r-RESPA buffers
+ *    (pamd_mts_query_sizes), each 256-byte aligned and kept alive until the
+ *    object that uses it is destroyed.  The library allocates no device memory.
  */
 #ifndef PAMD_H
 #define PAMD_H
@@ -348,9 +348,21 @@ pamd_status pamd_fp32_fma_rate(float* d_sink, double* tflops, void* stream);
 
 typedef struct pamd_nn pamd_nn;
 
+/* Device bytes of a surrogate for molecules of n_atoms (1..80) atoms whose
+ * inference, loss and training calls take at most max_conf configurations:
+ * FP32 parameters, gradient and Adam moments, the BF16 weight copies, and a
+ * workspace of about 7.3 KB per (configuration, atom) row plus 4.3 MB of
+ * split-K partial sums.  Pure host function; PAMD_ERR_ARG for sizes out of range. */
+pamd_status pamd_nn_query_sizes(int32_t n_atoms, int64_t max_conf, size_t* bytes);
+
 /* Surrogate for molecule `sys` (its atom count and bonds are used) with
- * atom_type[n_atoms] in 0..7.  Parameters start at zero (F_NN = 0). */
-pamd_status pamd_nn_create(const pamd_system* sys, const int32_t* atom_type, pamd_nn** out);
+ * atom_type[n_atoms] in 0..7, living in the caller's device buffer d_mem
+ * (mem_bytes >= pamd_nn_query_sizes(n_atoms, max_conf), 256-byte aligned,
+ * kept alive until pamd_nn_destroy).  Parameters start at zero (F_NN = 0).
+ * Synchronises `stream`.  PAMD_ERR_ARG for a bad type, bond index, size or
+ * buffer; the calls below refuse batches larger than max_conf (PAMD_ERR_ARG). */
+pamd_status pamd_nn_create(const pamd_system* sys, const int32_t* atom_type, int64_t max_conf, void* d_mem,
+                           size_t mem_bytes, void* stream, pamd_nn** out);
 
 /* Host params[PAMD_NN_PARAMS] -> device masters and BF16 copies; resets the
  * Adam state.  Synchronises `stream`. */
@@ -360,7 +372,7 @@ pamd_status pamd_nn_set_weights(pamd_nn* nn, const float* params, void* stream);
 pamd_status pamd_nn_get_weights(pamd_nn* nn, float* params, void* stream);
 
 /* E_NN (d_E [n_conf], may be NULL) and F_NN (d_F) of the configurations
- * d_x.  Asynchronous (the first call of a larger size allocates). */
+ * d_x, n_conf <= max_conf.  Asynchronous. */
 pamd_status pamd_nn_forces(pamd_nn* nn, int64_t n_conf, const float* d_x, float* d_F, float* d_E, void* stream);
 
 /* Force-matching loss L = mean over configurations, atoms and components of
@@ -378,6 +390,7 @@ pamd_status pamd_nn_loss_grad(pamd_nn* nn, int64_t n_conf, const float* d_x, con
 pamd_status pamd_nn_train_step(pamd_nn* nn, int64_t n_conf, const float* d_x, const float* d_F_target, float lr,
                                float* d_loss, void* stream);
 
+/* Frees the host object; the caller's device buffer is untouched. */
 void pamd_nn_destroy(pamd_nn* nn);
 const char* pamd_nn_last_error(const pamd_nn* nn);
 
@@ -386,6 +399,11 @@ const char* pamd_nn_last_error(const pamd_nn* nn);
  * d_F_nb (training data of the surrogate).  Asynchronous. */
 pamd_status pamd_export_configs(pamd_ctx* ctx, int32_t run, int64_t r0, int64_t count, float* d_x, float* d_F_nb,
                                 void* stream);
+
+/* Device bytes of the r-RESPA buffers of `ctx` (every run: features and
+ * dE/dG rows of R_cap x n_atoms configurations-atoms in BF16, row energies
+ * and F_NN), about 1 KB per replica-atom.  Host function. */
+pamd_status pamd_mts_query_sizes(pamd_ctx* ctx, size_t* bytes);
 
 /* Switch pamd_md_steps of an FP32 context to r-RESPA with surrogate `nn`
  * (every run must have nn's atom count): per outer step of Dt = outer_ratio dt
@@ -396,9 +414,11 @@ pamd_status pamd_export_configs(pamd_ctx* ctx, int32_t run, int64_t r0, int64_t 
  *   with the MD step counter at the start of the outer step as Philox step word.
  * n_steps of pamd_md_steps must then be a multiple of outer_ratio; energies
  * for the resampling weights stay exact.  nn = NULL switches back to plain
- * velocity Verlet.  Allocates per-run buffers of about R_cap * n_atoms KiB;
- * nn must stay alive while attached.  Synchronises `stream`. */
-pamd_status pamd_set_mts(pamd_ctx* ctx, pamd_nn* nn, int32_t outer_ratio, void* stream);
+ * velocity Verlet (d_mem ignored).  d_mem: the caller's device buffer of
+ * mem_bytes >= pamd_mts_query_sizes bytes (256-byte aligned) for the per-run
+ * buffers; it and nn must stay alive while attached.  Synchronises `stream`. */
+pamd_status pamd_set_mts(pamd_ctx* ctx, pamd_nn* nn, int32_t outer_ratio, void* d_mem, size_t mem_bytes,
+                         void* stream);
 
 #ifdef __cplusplus
 }

@@ -91,47 +91,51 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, int n, floa
 hipError_t launch_refresh(const float* p, uint16_t* W1, uint16_t* W1T, uint16_t* W2, uint16_t* W2T, hipStream_t s);
 hipError_t nn_setup();
 
-// a device buffer that only grows (synchronises its stream before a regrowth)
-struct DevBuf {
+// a piece of the caller's device memory
+struct Span {
     void* p = nullptr;
-    size_t bytes = 0;
-    hipError_t need(size_t b, hipStream_t s)
-    {
-        if (b <= bytes)
-            return hipSuccess;
-        if (p) {
-            hipError_t e = hipStreamSynchronize(s);
-            if (e != hipSuccess)
-                return e;
-            (void)hipFree(p);
-            p = nullptr;
-            bytes = 0;
-        }
-        hipError_t e = hipMalloc(&p, b);
-        if (e == hipSuccess)
-            bytes = b;
-        return e;
-    }
-    void release()
-    {
-        if (p)
-            (void)hipFree(p);
-        p = nullptr;
-        bytes = 0;
-    }
     template <typename T>
     T* as() const { return static_cast<T*>(p); }
 };
 
-// per-run buffers of the RESPA inner force
-struct MtsBuffers {
-    DevBuf G, gG, e, fnn;
+// Carves 256-byte aligned pieces off a caller-owned device buffer; with a
+// null base it only adds up their sizes (the size queries).
+struct SpanCarver {
+    char* base;
+    size_t off = 0;
+    explicit SpanCarver(void* b) : base(static_cast<char*>(b)) {}
+    Span take(size_t bytes)
+    {
+        off = (off + 255) / 256 * 256;
+        Span sp;
+        sp.p = base ? base + off : nullptr;
+        off += bytes;
+        return sp;
+    }
 };
+
+// per-run buffers of the RESPA inner force (caller-owned, pamd_set_mts)
+struct MtsBuffers {
+    Span G, gG, e, fnn;
+};
+
+// r-RESPA buffers of one run of R_cap replicas (n atoms, slab width npad)
+inline MtsBuffers carve_mts(SpanCarver& cv, int64_t R_cap, int n, int npad)
+{
+    const size_t rows = (size_t)R_cap * n;
+    MtsBuffers b;
+    b.G = cv.take(rows * kFeat * 2);
+    b.gG = cv.take(rows * kFeat * 2);
+    b.e = cv.take(rows * 4);
+    b.fnn = cv.take((size_t)R_cap * 3 * npad * 4);
+    return b;
+}
 
 }  // namespace nn
 }  // namespace pamd
 
-// the surrogate object behind the opaque pamd_nn handle
+// the surrogate object behind the opaque pamd_nn handle; every device array
+// is a piece of the memory the caller passed to pamd_nn_create
 struct pamd_nn {
     pamd::nn::Topo topo{};
     pamd::nn::Weights w{};
@@ -141,7 +145,8 @@ struct pamd_nn {
     float* adam_v = nullptr;
     uint16_t* wbf = nullptr;   // device BF16 copies: W1T | W1 | W2T | W2
     int64_t adam_t = 0;
-    // inference / training workspace
-    pamd::nn::DevBuf GV, gG, e, F, delta, HD, AD, S1, T1, D2, HB2, DA2, D1, HB1, part, colpart, losspart;
+    int64_t max_conf = 0;      // largest batch of the inference / training calls
+    // inference / training workspace, sized for max_conf configurations
+    pamd::nn::Span GV, gG, e, F, delta, HD, AD, S1, T1, D2, HB2, DA2, D1, HB1, part, colpart, losspart;
     std::string err;
 };

@@ -1,5 +1,7 @@
 // Host side of the learned multiple-time-step surrogate: the pamd_nn_* calls
-// of include/pamd.h (weights, inference, force-matching training).
+// of include/pamd.h (weights, inference, force-matching training).  Every
+// device array lives in the memory the caller hands to pamd_nn_create; this
+// file allocates no device memory.
 #include <math.h>
 #include <string.h>
 
@@ -48,33 +50,94 @@ ConfIO array_io(const float* x, float* f, int64_t count, int n)
     return io;
 }
 
-// energies and forces of n_conf configurations into F (array layout); G rows
-// go to the first half of nn->GV
-pamd_status infer(pamd_nn* nn, int64_t n_conf, const float* d_x, float* d_F, float* d_E, hipStream_t s)
+// Device memory of one surrogate in carve order: FP32 masters, gradient and
+// Adam moments (4 x kParams), the BF16 weight copies, then the workspace of
+// max_conf configurations (M = max_conf n rows: features and their
+// directional derivatives, adjoints, hidden activations of the training
+// products, split-K partial sums).  nn == nullptr only counts the bytes.
+void carve_nn(SpanCarver& cv, pamd_nn* nn, int n, int64_t max_conf)
+{
+    const size_t M = (size_t)max_conf * n, len = 3 * M;
+    pamd_nn tmp;
+    pamd_nn* t = nn ? nn : &tmp;
+    const Span params = cv.take(sizeof(float) * 4 * kParams);
+    const Span wbf = cv.take(sizeof(uint16_t) * 2 * (kFeat * kH + kH * kH));
+    t->GV = cv.take(2 * M * kFeat * 2);
+    t->gG = cv.take(M * kFeat * 2);
+    t->e = cv.take(M * 4);
+    t->F = cv.take(len * 4);
+    t->delta = cv.take(len * 4);
+    t->HD = cv.take(2 * M * kH * 4);
+    t->AD = cv.take(2 * M * kH * 2);
+    t->S1 = cv.take(M * kH * 4);
+    t->T1 = cv.take(M * kH * 4);
+    t->D2 = cv.take(2 * M * kH * 2);
+    t->HB2 = cv.take(M * kH * 4);
+    t->DA2 = cv.take(M * kH * 4);
+    t->D1 = cv.take(2 * M * kH * 2);
+    t->HB1 = cv.take(M * kH * 4);
+    t->part = cv.take((size_t)kSplitK * kFeat * kH * 4);
+    t->colpart = cv.take((size_t)kColBlocks * kH * 4);
+    t->losspart = cv.take((size_t)(kLossBlocks + 1) * 4);
+    if (nn) {
+        nn->params = params.as<float>();
+        nn->wbf = wbf.as<uint16_t>();
+    }
+}
+
+pamd_status check_batch(pamd_nn* nn, int64_t n_conf)
+{
+    if (n_conf > nn->max_conf)
+        return nfail(nn, PAMD_ERR_ARG, "batch of " + std::to_string(n_conf) + " configurations exceeds max_conf = " +
+                                           std::to_string(nn->max_conf) + " given to pamd_nn_create");
+    return PAMD_OK;
+}
+
+// energies and forces of n_conf configurations into F (array layout); the
+// feature rows go to G, dE/dG to gG, row energies to e (M = n_conf n rows each)
+pamd_status infer_into(pamd_nn* nn, int64_t n_conf, const float* d_x, float* d_F, float* d_E, uint16_t* G,
+                       uint16_t* gG, float* e, hipStream_t s)
 {
     const int n = nn->topo.n;
     const int64_t M = n_conf * n;
-    NNCHK(nn, nn->GV.need((size_t)2 * M * kFeat * 2, s));
-    NNCHK(nn, nn->gG.need((size_t)M * kFeat * 2, s));
-    NNCHK(nn, nn->e.need((size_t)M * 4, s));
     const ConfIO io = array_io(d_x, d_F, n_conf, n);
-    NNCHK(nn, launch_features(nn->topo, io, n_conf, nullptr, nn->GV.as<uint16_t>(), s));
-    NNCHK(nn, launch_mlp(nn->w, nn->GV.as<uint16_t>(), nn->gG.as<uint16_t>(), nn->e.as<float>(), nullptr, M, n, s));
-    NNCHK(nn, launch_force(nn->topo, io, n_conf, nn->gG.as<uint16_t>(), nn->e.as<float>(), d_E, s));
+    NNCHK(nn, launch_features(nn->topo, io, n_conf, nullptr, G, s));
+    NNCHK(nn, launch_mlp(nn->w, G, gG, e, nullptr, M, n, s));
+    NNCHK(nn, launch_force(nn->topo, io, n_conf, gG, e, d_E, s));
     return PAMD_OK;
+}
+
+pamd_status infer(pamd_nn* nn, int64_t n_conf, const float* d_x, float* d_F, float* d_E, hipStream_t s)
+{
+    return infer_into(nn, n_conf, d_x, d_F, d_E, nn->GV.as<uint16_t>(), nn->gG.as<uint16_t>(), nn->e.as<float>(), s);
 }
 
 }  // namespace
 
 extern "C" {
 
-pamd_status pamd_nn_create(const pamd_system* sys, const int32_t* atom_type, pamd_nn** out)
+pamd_status pamd_nn_query_sizes(int32_t n_atoms, int64_t max_conf, size_t* bytes)
+{
+    if (!bytes || n_atoms < 1 || n_atoms > kMaxN || max_conf < 1)
+        return PAMD_ERR_ARG;
+    SpanCarver cv(nullptr);
+    carve_nn(cv, nullptr, n_atoms, max_conf);
+    *bytes = cv.off;
+    return PAMD_OK;
+}
+
+pamd_status pamd_nn_create(const pamd_system* sys, const int32_t* atom_type, int64_t max_conf, void* d_mem,
+                           size_t mem_bytes, void* stream, pamd_nn** out)
 {
     if (!sys || !atom_type || !out)
         return PAMD_ERR_ARG;
     *out = nullptr;
     const int n = sys->n_atoms;
-    if (n < 1 || n > kMaxN || (sys->n_bonds > 0 && !sys->bond_idx))
+    if (n < 1 || n > kMaxN || (sys->n_bonds > 0 && !sys->bond_idx) || max_conf < 1 || !d_mem ||
+        (reinterpret_cast<uintptr_t>(d_mem) & 255) != 0)
+        return PAMD_ERR_ARG;
+    size_t need = 0;
+    if (pamd_nn_query_sizes(n, max_conf, &need) != PAMD_OK || mem_bytes < need)
         return PAMD_ERR_ARG;
     for (int a = 0; a < n; ++a)
         if (atom_type[a] < 0 || atom_type[a] >= kTypes)
@@ -121,18 +184,20 @@ pamd_status pamd_nn_create(const pamd_system* sys, const int32_t* atom_type, pam
         for (int q = 0; q < n; ++q)
             if (excl[order[p]][order[q]])
                 tp.excl[p][q >> 5] |= 1u << (q & 31);
-    // device parameters (zero) and BF16 copies
-    hipError_t e = hipMalloc(&nn->params, sizeof(float) * 4 * kParams);
+    // parameters (zero) and BF16 copies in the caller's memory
+    SpanCarver cv(d_mem);
+    carve_nn(cv, nn, n, max_conf);
+    nn->max_conf = max_conf;
+    hipStream_t s = as_stream(stream);
+    hipError_t e = hipMemsetAsync(nn->params, 0, sizeof(float) * 4 * kParams, s);
     if (e == hipSuccess)
-        e = hipMalloc(&nn->wbf, sizeof(uint16_t) * 2 * (kFeat * kH + kH * kH));
+        e = hipMemsetAsync(nn->wbf, 0, sizeof(uint16_t) * 2 * (kFeat * kH + kH * kH), s);
     if (e == hipSuccess)
-        e = hipMemset(nn->params, 0, sizeof(float) * 4 * kParams);
-    if (e == hipSuccess)
-        e = hipMemset(nn->wbf, 0, sizeof(uint16_t) * 2 * (kFeat * kH + kH * kH));
+        e = hipStreamSynchronize(s);
     if (e == hipSuccess)
         e = nn_setup();
     if (e != hipSuccess) {
-        pamd_nn_destroy(nn);
+        delete nn;
         return PAMD_ERR_HIP;
     }
     nn->grad = nn->params + kParams;
@@ -183,6 +248,8 @@ pamd_status pamd_nn_forces(pamd_nn* nn, int64_t n_conf, const float* d_x, float*
         return nfail(nn, PAMD_ERR_ARG, "bad configuration arrays");
     if (n_conf == 0)
         return PAMD_OK;
+    if (check_batch(nn, n_conf) != PAMD_OK)
+        return PAMD_ERR_ARG;
     return infer(nn, n_conf, d_x, d_F, d_E, as_stream(stream));
 }
 
@@ -193,13 +260,12 @@ pamd_status pamd_nn_loss_grad(pamd_nn* nn, int64_t n_conf, const float* d_x, con
         return PAMD_ERR_ARG;
     if (n_conf < 1 || !d_x || !d_F_target || !d_loss)
         return nfail(nn, PAMD_ERR_ARG, "bad arguments");
+    if (check_batch(nn, n_conf) != PAMD_OK)
+        return PAMD_ERR_ARG;
     hipStream_t s = as_stream(stream);
     const int n = nn->topo.n;
     const int64_t M = n_conf * n;
     const int64_t len = M * 3;
-    NNCHK(nn, nn->F.need((size_t)len * 4, s));
-    NNCHK(nn, nn->delta.need((size_t)len * 4, s));
-    NNCHK(nn, nn->losspart.need((size_t)kLossBlocks * 4, s));
     pamd_status st = infer(nn, n_conf, d_x, nn->F.as<float>(), nullptr, s);
     if (st != PAMD_OK)
         return st;
@@ -213,17 +279,6 @@ pamd_status pamd_nn_loss_grad(pamd_nn* nn, int64_t n_conf, const float* d_x, con
     uint16_t* GV = nn->GV.as<uint16_t>();
     const ConfIO io = array_io(d_x, nullptr, n_conf, n);
     NNCHK(nn, launch_features(nn->topo, io, n_conf, nn->delta.as<float>(), GV + (size_t)M * kFeat, s));
-    NNCHK(nn, nn->HD.need((size_t)2 * M * kH * 4, s));
-    NNCHK(nn, nn->AD.need((size_t)2 * M * kH * 2, s));
-    NNCHK(nn, nn->S1.need((size_t)M * kH * 4, s));
-    NNCHK(nn, nn->T1.need((size_t)M * kH * 4, s));
-    NNCHK(nn, nn->D2.need((size_t)2 * M * kH * 2, s));
-    NNCHK(nn, nn->HB2.need((size_t)M * kH * 4, s));
-    NNCHK(nn, nn->DA2.need((size_t)M * kH * 4, s));
-    NNCHK(nn, nn->D1.need((size_t)2 * M * kH * 2, s));
-    NNCHK(nn, nn->HB1.need((size_t)M * kH * 4, s));
-    NNCHK(nn, nn->part.need((size_t)kSplitK * kFeat * kH * 4, s));
-    NNCHK(nn, nn->colpart.need((size_t)kColBlocks * kH * 4, s));
     float* HD = nn->HD.as<float>();
     uint16_t* AD = nn->AD.as<uint16_t>();
     uint16_t* D2 = nn->D2.as<uint16_t>();
@@ -264,7 +319,6 @@ pamd_status pamd_nn_train_step(pamd_nn* nn, int64_t n_conf, const float* d_x, co
     if (!(lr > 0.0f))
         return nfail(nn, PAMD_ERR_ARG, "lr must be > 0");
     hipStream_t s = as_stream(stream);
-    NNCHK(nn, nn->losspart.need((size_t)(kLossBlocks + 1) * 4, s));
     float* loss = d_loss ? d_loss : nn->losspart.as<float>() + kLossBlocks;
     pamd_status st = pamd_nn_loss_grad(nn, n_conf, d_x, d_F_target, loss, nn->grad, stream);
     if (st != PAMD_OK)
@@ -280,18 +334,9 @@ pamd_status pamd_nn_train_step(pamd_nn* nn, int64_t n_conf, const float* d_x, co
     return PAMD_OK;
 }
 
+// The caller's memory stays the caller's: only the host object is freed.
 void pamd_nn_destroy(pamd_nn* nn)
 {
-    if (!nn)
-        return;
-    (void)hipDeviceSynchronize();
-    if (nn->params)
-        (void)hipFree(nn->params);
-    if (nn->wbf)
-        (void)hipFree(nn->wbf);
-    for (DevBuf* b : {&nn->GV, &nn->gG, &nn->e, &nn->F, &nn->delta, &nn->HD, &nn->AD, &nn->S1, &nn->T1, &nn->D2,
-                      &nn->HB2, &nn->DA2, &nn->D1, &nn->HB1, &nn->part, &nn->colpart, &nn->losspart})
-        b->release();
     delete nn;
 }
 

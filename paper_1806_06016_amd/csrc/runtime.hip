@@ -1611,7 +1611,32 @@ pamd_status pamd_export_configs(pamd_ctx* c, int32_t run, int64_t r0, int64_t co
     return PAMD_OK;
 }
 
-pamd_status pamd_set_mts(pamd_ctx* c, pamd_nn* nn, int32_t outer_ratio, void* stream)
+// r-RESPA buffers of every run, carved in run order
+static size_t carve_mts_all(pamd_ctx* c, void* base)
+{
+    nn::SpanCarver cv(base);
+    for (auto& run : c->runs) {
+        const RunDev<float>& d = run.f;
+        const nn::MtsBuffers b = nn::carve_mts(cv, d.R_cap, d.n, d.npad);
+        if (base)
+            run.mts = b;
+    }
+    return cv.off;
+}
+
+pamd_status pamd_mts_query_sizes(pamd_ctx* c, size_t* bytes)
+{
+    pamd_status st = check_ctx(c);
+    if (st != PAMD_OK)
+        return st;
+    if (!bytes)
+        return fail(c, PAMD_ERR_ARG, "null output");
+    *bytes = carve_mts_all(c, nullptr);
+    return PAMD_OK;
+}
+
+pamd_status pamd_set_mts(pamd_ctx* c, pamd_nn* nn, int32_t outer_ratio, void* d_mem, size_t mem_bytes,
+                         void* stream)
 {
     pamd_status st = check_ctx(c);
     if (st != PAMD_OK)
@@ -1620,8 +1645,7 @@ pamd_status pamd_set_mts(pamd_ctx* c, pamd_nn* nn, int32_t outer_ratio, void* st
     HIPCHK(c, hipStreamSynchronize(s));
     if (!nn) {
         for (auto& run : c->runs)
-            for (nn::DevBuf* b : {&run.mts.G, &run.mts.gG, &run.mts.e, &run.mts.fnn})
-                b->release();
+            run.mts = nn::MtsBuffers{};
         c->nn = nullptr;
         c->mts_ratio = 0;
         return PAMD_OK;
@@ -1636,14 +1660,11 @@ pamd_status pamd_set_mts(pamd_ctx* c, pamd_nn* nn, int32_t outer_ratio, void* st
     for (auto& run : c->runs)
         if (run.f.n != nn->topo.n)
             return fail(c, PAMD_ERR_ARG, "surrogate atom count differs from a run's");
-    for (auto& run : c->runs) {
-        const RunDev<float>& d = run.f;
-        const size_t rows = (size_t)d.R_cap * d.n;
-        HIPCHK(c, run.mts.G.need(rows * nn::kFeat * 2, s));
-        HIPCHK(c, run.mts.gG.need(rows * nn::kFeat * 2, s));
-        HIPCHK(c, run.mts.e.need(rows * 4, s));
-        HIPCHK(c, run.mts.fnn.need((size_t)d.R_cap * 3 * d.npad * 4, s));
-    }
+    if (!d_mem || (reinterpret_cast<uintptr_t>(d_mem) & (kAlign - 1)) != 0)
+        return fail(c, PAMD_ERR_ARG, "r-RESPA buffer missing or not 256-byte aligned");
+    if (mem_bytes < carve_mts_all(c, nullptr))
+        return fail(c, PAMD_ERR_ARG, "r-RESPA buffer smaller than pamd_mts_query_sizes");
+    carve_mts_all(c, d_mem);
     c->nn = nn;
     c->mts_ratio = outer_ratio;
     return PAMD_OK;
@@ -1655,11 +1676,6 @@ void pamd_destroy(pamd_ctx* c)
         return;
     for (int g = 0; g < kGraphSlots; ++g)
         drop_graph(c, g);
-    if (c->nn)
-        (void)hipDeviceSynchronize();
-    for (auto& run : c->runs)
-        for (nn::DevBuf* b : {&run.mts.G, &run.mts.gG, &run.mts.e, &run.mts.fnn})
-            b->release();
     delete c;
 }
 

@@ -85,8 +85,9 @@ def train(nn, x, f, steps: int, batch: int = 256, lr0: float = 1e-3, seed: int =
 
     def mean_loss(ids):
         s, m = 0.0, 0
-        for c0 in range(0, ids.numel(), 4096):
-            c = ids[c0:c0 + 4096]
+        chunk = nn.max_conf          # the largest batch the surrogate's workspace takes
+        for c0 in range(0, ids.numel(), chunk):
+            c = ids[c0:c0 + chunk]
             lv, _ = nn.loss_grad(x[c].contiguous(), f[c].contiguous(), want_grad=False)
             s += float(lv.item()) * c.numel()
             m += c.numel()
@@ -175,7 +176,7 @@ def kernel_timing(R: int, reps: int = 5) -> Dict:
     profiles."""
     import torch
     sysd = S.c2_system()
-    nn = B.PamdNN(sysd, sysd.atype)
+    nn = B.PamdNN(sysd, sysd.atype, max_conf=R)
     nn.set_weights(surrogate_weights(3))
     rng = np.random.default_rng(1)
     x = torch.tensor(sysd.x_init[None] + rng.normal(0, 0.01, (R,) + sysd.x_init.shape), dtype=torch.float32,
@@ -226,7 +227,7 @@ def main(argv=None):
     x, f, st = collect(sysd, a.replicas, temps, 1000, 4, seed=11)
     t_collect = time.perf_counter() - t0
     print(f"collected {x.shape[0]} configurations in {t_collect:.1f} s", flush=True)
-    nn = B.PamdNN(sysd, sysd.atype)
+    nn = B.PamdNN(sysd, sysd.atype, max_conf=4096)     # validation loss in chunks of 4096 configurations
     nn.set_weights(surrogate_weights(2024, 0.5))
     tr = train(nn, x, f, a.train_steps)
     print(f"trained: val relative force RMS {tr['val_rel_force_rms']:.3f} in {tr['train_seconds']:.1f} s",

@@ -74,9 +74,10 @@ EXPORTS = ["pamd_query_sizes", "pamd_init", "pamd_md_steps", "pamd_resample", "p
            "pamd_graph_capture", "pamd_graph_launch", "pamd_set_schedule",
            "pamd_get_forces", "pamd_get_state", "pamd_set_state", "pamd_get_counts",
            "pamd_launch_info", "pamd_destroy", "pamd_last_error",
-           "pamd_nn_create", "pamd_nn_set_weights", "pamd_nn_get_weights", "pamd_nn_forces",
+           "pamd_nn_query_sizes", "pamd_nn_create", "pamd_nn_set_weights", "pamd_nn_get_weights",
+           "pamd_nn_forces",
            "pamd_nn_loss_grad", "pamd_nn_train_step", "pamd_nn_destroy", "pamd_nn_last_error",
-           "pamd_export_configs", "pamd_set_mts", "pamd_fp32_fma_rate",
+           "pamd_export_configs", "pamd_mts_query_sizes", "pamd_set_mts", "pamd_fp32_fma_rate",
            "pamd_family_error", "pamd_binning_error", "pamd_wham", "pamd_wham_average"]
 NN_PARAMS = 49537
 NN_FEATURES, NN_HIDDEN, NN_TYPES = 256, 128, 8
@@ -116,7 +117,8 @@ def load_library(path: str = LIB_PATH):
     lib.pamd_destroy.restype = None
     lib.pamd_last_error.argtypes = [vp]
     lib.pamd_last_error.restype = C.c_char_p
-    lib.pamd_nn_create.argtypes = [vp, vp, P(vp)]
+    lib.pamd_nn_query_sizes.argtypes = [i32, i64, P(C.c_size_t)]
+    lib.pamd_nn_create.argtypes = [vp, vp, i64, vp, C.c_size_t, vp, P(vp)]
     lib.pamd_nn_set_weights.argtypes = [vp, vp, vp]
     lib.pamd_nn_get_weights.argtypes = [vp, vp, vp]
     lib.pamd_nn_forces.argtypes = [vp, i64, vp, vp, vp, vp]
@@ -127,7 +129,8 @@ def load_library(path: str = LIB_PATH):
     lib.pamd_nn_last_error.argtypes = [vp]
     lib.pamd_nn_last_error.restype = C.c_char_p
     lib.pamd_export_configs.argtypes = [vp, i32, i64, i64, vp, vp, vp]
-    lib.pamd_set_mts.argtypes = [vp, vp, i32, vp]
+    lib.pamd_mts_query_sizes.argtypes = [vp, P(C.c_size_t)]
+    lib.pamd_set_mts.argtypes = [vp, vp, i32, vp, C.c_size_t, vp]
     lib.pamd_fp32_fma_rate.argtypes = [vp, vp, vp]
     lib.pamd_family_error.argtypes = [vp, vp, i64, vp]
     lib.pamd_binning_error.argtypes = [vp, i64, i64, vp]
@@ -430,10 +433,20 @@ class Pamd:
         return x, f
 
     def set_mts(self, nn: Optional["PamdNN"], outer_ratio: int = 4) -> None:
-        """Attach surrogate `nn` (r-RESPA, outer step outer_ratio * dt) or detach (None)."""
-        self._mts_nn = nn
-        self._check(self.lib.pamd_set_mts(self.ctx, nn.handle if nn is not None else None, int(outer_ratio),
+        """Attach surrogate `nn` (r-RESPA, outer step outer_ratio * dt) or detach
+        (None).  The per-run r-RESPA buffers are a torch allocation of the size
+        the library asks for."""
+        if nn is None:
+            self._check(self.lib.pamd_set_mts(self.ctx, None, 0, None, 0, self._s()), self.ctx)
+            self._mts_nn, self._mts_mem = None, None
+            return
+        nb = C.c_size_t()
+        self._check(self.lib.pamd_mts_query_sizes(self.ctx, C.byref(nb)), self.ctx)
+        mem = self.torch.empty(nb.value + 256, dtype=self.torch.uint8, device="cuda")
+        ptr = (mem.data_ptr() + 255) // 256 * 256
+        self._check(self.lib.pamd_set_mts(self.ctx, nn.handle, int(outer_ratio), C.c_void_p(ptr), nb.value,
                                           self._s()), self.ctx)
+        self._mts_nn, self._mts_mem = nn, mem
 
     def get_counts(self, run: int = 0) -> np.ndarray:
         c = np.zeros(self.R_cap, np.int32)
@@ -472,7 +485,10 @@ class PamdNN:
     """The learned surrogate of one molecule (pamd_nn_* calls).  Configuration
     arrays are CUDA float32 tensors [n_conf, n, 3]."""
 
-    def __init__(self, sysd, atom_type: Sequence[int], stream=None):
+    def __init__(self, sysd, atom_type: Sequence[int], max_conf: int = 256, stream=None):
+        """max_conf: the largest batch of forces / loss_grad / train_step; the
+        parameters and workspace are one torch allocation of the size the
+        library asks for."""
         import torch
         self.torch = torch
         self.lib = load_library()
@@ -483,8 +499,16 @@ class PamdNN:
         self.n = int(sysd.n_atoms)
         t = np.ascontiguousarray(np.asarray(atom_type, np.int32))
         self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.max_conf = int(max_conf)
+        nb = C.c_size_t()
+        st = self.lib.pamd_nn_query_sizes(self.n, self.max_conf, C.byref(nb))
+        if st != PAMD_OK:
+            raise PamdError(st, "pamd_nn_query_sizes: atom count or max_conf out of range")
+        self._mem = torch.empty(nb.value + 256, dtype=torch.uint8, device="cuda")
+        ptr = (self._mem.data_ptr() + 255) // 256 * 256
         h = C.c_void_p()
-        st = self.lib.pamd_nn_create(C.byref(self._sys), _ptr(t), C.byref(h))
+        st = self.lib.pamd_nn_create(C.byref(self._sys), _ptr(t), self.max_conf, C.c_void_p(ptr), nb.value,
+                                     self._s(), C.byref(h))
         if st != PAMD_OK:
             raise PamdError(st, "pamd_nn_create failed")
         self.handle = h
