@@ -375,6 +375,20 @@ pamd_status pamd_nn_get_weights(pamd_nn* nn, float* params, void* stream);
  * d_x, n_conf <= max_conf.  Asynchronous. */
 pamd_status pamd_nn_forces(pamd_nn* nn, int64_t n_conf, const float* d_x, float* d_F, float* d_E, void* stream);
 
+/* pamd_nn_forces for callers that cannot allocate device memory or size a
+ * workspace (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation): the same inputs, outputs and results (the same
+ * kernels), but the features and dE/dG rows are staged in a fixed 16 MiB
+ * device array of the library (one per GPU, set up by pamd_nn_create, held
+ * until the process ends) instead of the surrogate's workspace.  Requires
+ * n_conf * n_atoms <= PAMD_NN_STATIC_ROWS (PAMD_ERR_ARG beyond, with the
+ * sizes in pamd_nn_last_error).  Every call on one GPU uses that one array:
+ * calls that overlap in time on one GPU (several streams or threads) race.
+ * Allocates nothing.  Asynchronous. */
+#define PAMD_NN_STATIC_ROWS 16000
+pamd_status pamd_nn_forces_static(pamd_nn* nn, int64_t n_conf, const float* d_x, float* d_F, float* d_E,
+                                  void* stream);
+
 /* Force-matching loss L = mean over configurations, atoms and components of
  * (F_NN - F_target)^2 into device float *d_loss, and its gradient with
  * respect to the FP32 parameters into d_grad (device [PAMD_NN_PARAMS]; NULL:

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -112,6 +113,41 @@ pamd_status infer(pamd_nn* nn, int64_t n_conf, const float* d_x, float* d_F, flo
     return infer_into(nn, n_conf, d_x, d_F, d_E, nn->GV.as<uint16_t>(), nn->gG.as<uint16_t>(), nn->e.as<float>(), s);
 }
 
+// ---- allocation-free inference (pamd_nn_forces_static) -------------------
+// Its staging rows live in one file-scope device array, a copy per GPU held
+// until the process ends.  In host code the array's name is no device
+// address: each device's copy is looked up once with hipGetSymbolAddress
+// (with that device current) and only that pointer is handed to kernels.
+constexpr size_t kStaticBytes = (size_t)16 << 20;
+static_assert((size_t)PAMD_NN_STATIC_ROWS * (2 * kFeat * 2 + 4) + 3 * 256 <= kStaticBytes,
+              "static staging rows exceed the fixed array");
+static __device__ __align__(256) unsigned char scratch[kStaticBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
+
+// this device's copy of `scratch` (looked up on the first call per device)
+hipError_t static_scratch(void** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return e;
+    if (dev < 0 || dev >= kMaxDevices)
+        return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return e;
+        g_scratch[dev] = p;
+    }
+    *out = g_scratch[dev];
+    return hipSuccess;
+}
+
 }  // namespace
 
 extern "C" {
@@ -196,6 +232,9 @@ pamd_status pamd_nn_create(const pamd_system* sys, const int32_t* atom_type, int
         e = hipStreamSynchronize(s);
     if (e == hipSuccess)
         e = nn_setup();
+    void* sp = nullptr;   // this device's allocation-free staging array (set up once per device)
+    if (e == hipSuccess)
+        e = static_scratch(&sp);
     if (e != hipSuccess) {
         delete nn;
         return PAMD_ERR_HIP;
@@ -251,6 +290,32 @@ pamd_status pamd_nn_forces(pamd_nn* nn, int64_t n_conf, const float* d_x, float*
     if (check_batch(nn, n_conf) != PAMD_OK)
         return PAMD_ERR_ARG;
     return infer(nn, n_conf, d_x, d_F, d_E, as_stream(stream));
+}
+
+pamd_status pamd_nn_forces_static(pamd_nn* nn, int64_t n_conf, const float* d_x, float* d_F, float* d_E,
+                                  void* stream)
+{
+    if (!nn)
+        return PAMD_ERR_ARG;
+    if (n_conf < 0 || (n_conf > 0 && (!d_x || !d_F)))
+        return nfail(nn, PAMD_ERR_ARG, "bad configuration arrays");
+    const int64_t rows = n_conf * nn->topo.n;
+    if (rows > PAMD_NN_STATIC_ROWS)
+        return nfail(nn, PAMD_ERR_ARG, "n_conf * n_atoms = " + std::to_string(rows) +
+                                           " exceeds the fixed staging of PAMD_NN_STATIC_ROWS = " +
+                                           std::to_string(PAMD_NN_STATIC_ROWS) + " rows");
+    if (n_conf == 0)
+        return PAMD_OK;
+    void* base = nullptr;
+    NNCHK(nn, static_scratch(&base));
+    // every staged value is written by the features / MLP kernels of this
+    // call before it is read, so nothing needs clearing between calls
+    SpanCarver cv(base);
+    const Span G = cv.take((size_t)rows * kFeat * 2);
+    const Span gG = cv.take((size_t)rows * kFeat * 2);
+    const Span e = cv.take((size_t)rows * 4);
+    return infer_into(nn, n_conf, d_x, d_F, d_E, G.as<uint16_t>(), gG.as<uint16_t>(), e.as<float>(),
+                      as_stream(stream));
 }
 
 pamd_status pamd_nn_loss_grad(pamd_nn* nn, int64_t n_conf, const float* d_x, const float* d_F_target,

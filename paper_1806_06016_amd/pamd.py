@@ -75,12 +75,13 @@ EXPORTS = ["pamd_query_sizes", "pamd_init", "pamd_md_steps", "pamd_resample", "p
            "pamd_get_forces", "pamd_get_state", "pamd_set_state", "pamd_get_counts",
            "pamd_launch_info", "pamd_destroy", "pamd_last_error",
            "pamd_nn_query_sizes", "pamd_nn_create", "pamd_nn_set_weights", "pamd_nn_get_weights",
-           "pamd_nn_forces",
+           "pamd_nn_forces", "pamd_nn_forces_static",
            "pamd_nn_loss_grad", "pamd_nn_train_step", "pamd_nn_destroy", "pamd_nn_last_error",
            "pamd_export_configs", "pamd_mts_query_sizes", "pamd_set_mts", "pamd_fp32_fma_rate",
            "pamd_family_error", "pamd_binning_error", "pamd_wham", "pamd_wham_average"]
 NN_PARAMS = 49537
 NN_FEATURES, NN_HIDDEN, NN_TYPES = 256, 128, 8
+NN_STATIC_ROWS = 16000      # configuration-atom rows of pamd_nn_forces_static
 _NO_STATUS = ("pamd_destroy", "pamd_last_error", "pamd_nn_destroy", "pamd_nn_last_error")
 
 _lib = None
@@ -122,6 +123,7 @@ def load_library(path: str = LIB_PATH):
     lib.pamd_nn_set_weights.argtypes = [vp, vp, vp]
     lib.pamd_nn_get_weights.argtypes = [vp, vp, vp]
     lib.pamd_nn_forces.argtypes = [vp, i64, vp, vp, vp, vp]
+    lib.pamd_nn_forces_static.argtypes = [vp, i64, vp, vp, vp, vp]
     lib.pamd_nn_loss_grad.argtypes = [vp, i64, vp, vp, vp, vp, vp]
     lib.pamd_nn_train_step.argtypes = [vp, i64, vp, vp, C.c_float, vp, vp]
     lib.pamd_nn_destroy.argtypes = [vp]
@@ -536,6 +538,18 @@ class PamdNN:
         F = torch.empty_like(x)
         E = torch.empty(B, dtype=torch.float32, device=x.device)
         self._check(self.lib.pamd_nn_forces(self.handle, B, x.data_ptr(), F.data_ptr(), E.data_ptr(), self._s()))
+        return E, F
+
+    def forces_static(self, x, F=None, E=None):
+        """forces() through the allocation-free entry point (fixed library
+        staging, n_conf * n <= NN_STATIC_ROWS); F and E may be given."""
+        torch = self.torch
+        assert x.is_cuda and x.dtype == torch.float32 and x.is_contiguous()
+        B = x.shape[0]
+        F = torch.empty_like(x) if F is None else F
+        E = torch.empty(B, dtype=torch.float32, device=x.device) if E is None else E
+        self._check(self.lib.pamd_nn_forces_static(self.handle, B, x.data_ptr(), F.data_ptr(), E.data_ptr(),
+                                                   self._s()))
         return E, F
 
     def loss_grad(self, x, F_target, want_grad: bool = True):

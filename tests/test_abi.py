@@ -134,6 +134,7 @@ def test_surrogate_parameter_count_matches_layout():
     assert vals["PAMD_NN_PARAMS"] == F * H + H + H * H + H + H + 1
     from paper_1806_06016_amd import pamd as B
     assert B.NN_PARAMS == vals["PAMD_NN_PARAMS"] and B.NN_FEATURES == F and B.NN_HIDDEN == H
+    assert B.NN_STATIC_ROWS == vals["PAMD_NN_STATIC_ROWS"]
     w = {"W1": np.zeros((F, H)), "b1": np.zeros(H), "W2": np.zeros((H, H)), "b2": np.zeros(H),
          "w3": np.arange(H, dtype=float), "b3": np.ones(1)}
     back = B.unpack_params(B.pack_params(w))
