@@ -124,10 +124,12 @@ def _attainable(result):
 
 def batched(args):
     """Eight independent runs of seeded peptides with 40, 75, 75, 120, 150,
-    200, 250 and 300 atoms, R = 4096 each, in one persistent launch per MD
-    phase (wide layout); geometric schedule 700 K -> 250 K over 40 steps
-    (the device schedule, replayed from HIP graphs); theta = 1000 steps of
-    0.5 fs."""
+    200, 250 and 300 atoms, R = 4096 each, in one context: the runs above 80
+    atoms share one persistent wide launch per MD phase, and the autotuner
+    chooses for the runs of at most 80 atoms between that launch and
+    register-tile launches of their own, and the wide launch's waves per
+    workgroup; geometric schedule 700 K -> 250 K over 40 steps (the device
+    schedule, replayed from HIP graphs); theta = 1000 steps of 0.5 fs."""
     import numpy as np
     import torch
     from pamd_inputs import systems as S
@@ -138,11 +140,18 @@ def batched(args):
     # dt = 0.5 fs: at 1 fs the FP64 oracle itself blows up within 200 steps at
     # 700 K for the 120-250-atom molecules (oppositely charged hydrogens fall
     # into the steep Lennard-Jones wall); at 0.5 fs 2048-replica oracle runs stay finite
+    tuned = None
+    layout, wide_waves = "auto", args.waves
+    if args.waves == 0 and not args.no_autotune:
+        from paper_1806_06016_amd.autotune import autotune_batched
+        tuned = autotune_batched(systems, R)
+        layout, wide_waves = tuned["layout"], tuned["wide_waves_per_block"]
     p = Pamd(systems, R_target=R, T0=700.0, dt=0.0005, nu=1.0, seed=1806, precision=PAMD_FP32,
-             waves_per_block=args.waves)
+             layout=layout, wide_waves=wide_waves)
     for r in range(len(systems)):
         p.set_schedule(r, sched)
-    info = p.launch_info()
+    info = dict(p.launch_info(), runs=[dict(atoms=s.n_atoms, **p.run_launch(r)) for r, s in enumerate(systems)],
+                autotune=tuned)
     stream = torch.cuda.current_stream()
     p.md_steps(args.theta_eq)
     p.observables()

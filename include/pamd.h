@@ -54,7 +54,10 @@ enum {
     PAMD_ERR_HIP = 2,        /* a HIP runtime call failed; message holds hipGetErrorString */
     PAMD_ERR_CAPACITY = 3,   /* resampled population larger than R_cap (or extinct) */
     PAMD_ERR_NONFINITE = 4,  /* NaN / Inf potential energy */
-    PAMD_ERR_STATE = 5       /* call-order violation or context already failed */
+    PAMD_ERR_STATE = 5,      /* call-order violation or context already failed */
+    PAMD_ERR_INTERNAL = 6    /* bounds-checked build only (libpamd_check.so): a resampling index
+                                (destination offset of the scan, source slot of the gather) was
+                                out of range; nothing out of range was written */
 };
 
 enum { PAMD_FP64 = 0, PAMD_FP32 = 1 };
@@ -77,12 +80,18 @@ enum { PAMD_RESAMPLE_NEAREST = 0, PAMD_RESAMPLE_MULTINOMIAL = 1, PAMD_RESAMPLE_N
  *             F = F(x); v += dt/2 F/m.  Not combined with pamd_set_mts. */
 enum { PAMD_THERMOSTAT_ANDERSEN = 0, PAMD_THERMOSTAT_LANGEVIN = 1 };
 enum { PAMD_DIELECTRIC_VACUUM = 0, PAMD_DIELECTRIC_4R = 1 };
+/* MD layout of a run (pamd_params.layout):
+ *   AUTO  register tile when every molecule of the context has at most
+ *         PAMD_TILE_ATOMS atoms, else wide;
+ *   TILE  register tile: one replica per 16-lane row, four per wavefront, one
+ *         persistent launch per run (molecules up to PAMD_TILE_ATOMS atoms);
+ *   WIDE  one replica per wavefront; every wide run of a context shares one
+ *         persistent launch (FP32 only).
+ * A context may mix both (an autotuner picks per run). */
+enum { PAMD_LAYOUT_AUTO = 0, PAMD_LAYOUT_TILE = 1, PAMD_LAYOUT_WIDE = 2 };
 
 #define PAMD_MAX_ATOMS 320   /* FP32; FP64 runs take at most 32 atoms */
-#define PAMD_TILE_ATOMS 80   /* contexts whose molecules all have at most this many atoms use the
-                                register-tile MD kernel (one replica per 16 lanes, run by run);
-                                a context holding a larger molecule runs every run in one
-                                persistent launch with one replica per wavefront */
+#define PAMD_TILE_ATOMS 80   /* the largest molecule of the register-tile layout (PAMD_LAYOUT_*) */
 #define PAMD_FORCE_CHUNK 256 /* replicas per pamd_get_forces call */
 
 /*
@@ -133,11 +142,13 @@ typedef struct pamd_params {
                                       (1/time; 0: NVE) */
     uint64_t seed;                 /* Philox key = (seed_lo, seed_hi + run) */
     int32_t precision;             /* PAMD_FP32 (positions, velocities, forces FP32) or PAMD_FP64 */
-    int32_t waves_per_block;       /* 0: automatic; else 1..16 (autotuner override) */
+    int32_t waves_per_block;       /* register-tile kernel: 0 automatic, else 1..16 (from run 0) */
     double V_target;               /* adaptive schedule: normalised weight variance per step */
     double T_final;                /* adaptive schedule: lowest temperature T_N */
     int32_t resampling;            /* PAMD_RESAMPLE_*: how pamd_resample draws the copy numbers */
     int32_t thermostat;            /* PAMD_THERMOSTAT_*: the same for every run of a context */
+    int32_t layout;                /* PAMD_LAYOUT_* of this run */
+    int32_t wide_waves_per_block;  /* batched wide launch: 0 automatic (4), else 1..4 (from run 0) */
 } pamd_params;
 
 /* Population observables of one run (PAMD step 4), all FP64. */
@@ -265,9 +276,16 @@ pamd_status pamd_set_state(pamd_ctx* ctx, int32_t run, const double* x, const do
 /* Copy numbers c_j of the last resampling of `run` (host [R_{i-1}]). */
 pamd_status pamd_get_counts(pamd_ctx* ctx, int32_t run, int32_t* host_c, int64_t* n, void* stream);
 
-/* Launch shape chosen at init: waves per workgroup and workgroups (informational). */
+/* Launch shape chosen at init: waves per workgroup, workgroups and LDS bytes
+ * of the batched wide launch if the context has one, else of the
+ * register-tile kernel (informational). */
 pamd_status pamd_launch_info(const pamd_ctx* ctx, int32_t* waves_per_block, int32_t* blocks,
                              int32_t* lds_bytes);
+
+/* Layout (PAMD_LAYOUT_TILE or PAMD_LAYOUT_WIDE) and launch shape of the
+ * kernel that advances `run`.  Host function. */
+pamd_status pamd_run_launch(const pamd_ctx* ctx, int32_t run, int32_t* layout, int32_t* waves_per_block,
+                            int32_t* blocks, int32_t* lds_bytes);
 
 void pamd_destroy(pamd_ctx* ctx);
 const char* pamd_last_error(const pamd_ctx* ctx);

@@ -1,10 +1,19 @@
-"""Launch-shape autotuner for the persistent MD kernel.
+"""Launch-shape autotuner for the persistent MD kernels.
 
 Times ``pamd_md_steps`` of a probe population on the GPU for each candidate
-number of waves per workgroup (which sets replicas per workgroup, LDS per
-workgroup and therefore waves per CU) and keeps the fastest.  The probe runs
-the kernel of the run's thermostat (the Langevin variant holds more registers).
-Results are cached per (system size, dielectric, precision, thermostat, GPU
+launch shape and keeps the fastest:
+
+* one molecule (``autotune``): waves per workgroup of the register-tile
+  kernel (which sets replicas per workgroup, LDS per workgroup and therefore
+  waves per CU); the probe runs the kernel of the run's thermostat (the
+  Langevin variant holds more registers);
+* several independent runs in one context (``autotune_batched``): the layout
+  of every run small enough for the register tile (the batched wide launch,
+  one replica per wavefront, or register-tile launches of four replicas per
+  wavefront) and the waves per workgroup of the wide launch, timed on the
+  whole context at its real population sizes.
+
+Results are cached per (system sizes, dielectric, precision, thermostat, GPU
 architecture, library build, probe size) in a JSON file, so a run pays for the
 sweep once.
 """
@@ -15,9 +24,10 @@ import json
 import os
 from typing import Dict, Optional, Sequence
 
-from .pamd import LIB_PATH, Pamd, PAMD_FP32
+from .pamd import LIB_PATH, Pamd, PAMD_FP32, TILE_ATOMS
 
 CANDIDATES = (16, 12, 8, 4)
+WIDE_CANDIDATES = (4, 3, 2, 1)
 
 
 def _cache_path() -> str:
@@ -25,12 +35,49 @@ def _cache_path() -> str:
     return os.path.join(base, "pamd_autotune.json")
 
 
-def _key(sysd, precision: int, R_probe: int, thermostat: str) -> str:
+def _key(systems, precision: int, R_probe: int, thermostat: str) -> str:
     import torch
     arch = torch.cuda.get_device_properties(0).gcnArchName
     with open(LIB_PATH, "rb") as f:
         lib = hashlib.sha256(f.read()).hexdigest()[:16]
-    return f"N{sysd.n_atoms}-diel{int(sysd.dielectric)}-p{precision}-{thermostat}-{arch}-{lib}-R{R_probe}"
+    sizes = "_".join(str(s.n_atoms) for s in systems)
+    return f"N{sizes}-diel{int(systems[0].dielectric)}-p{precision}-{thermostat}-{arch}-{lib}-R{R_probe}"
+
+
+def _load(path: str) -> Dict:
+    if os.path.exists(path):
+        try:
+            return json.load(open(path))
+        except (OSError, ValueError):
+            pass
+    return {}
+
+
+def _store(path: str, cache: Dict) -> None:
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        with open(path, "w") as f:
+            json.dump(cache, f, indent=1)
+    except OSError:
+        pass
+
+
+def _time_md(p, theta_probe: int, reps: int = 3) -> float:
+    """Best of `reps` timed pamd_md_steps(theta_probe) calls after one untimed one (ms)."""
+    import torch
+    p.md_steps(theta_probe)
+    torch.cuda.synchronize()
+    best = None
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(p.stream)
+        p.md_steps(theta_probe)
+        e1.record(p.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    return best
 
 
 def autotune(sysd, precision: int = PAMD_FP32, R_probe: int = 65536, theta_probe: int = 100,
@@ -43,41 +90,63 @@ def autotune(sysd, precision: int = PAMD_FP32, R_probe: int = 65536, theta_probe
     and a probe with about one item per wave times the tail, not the rate."""
     import torch
     path = cache_path or _cache_path()
-    key = _key(sysd, precision, R_probe, thermostat)
-    cache = {}
-    if use_cache and os.path.exists(path):
-        try:
-            cache = json.load(open(path))
-        except (OSError, ValueError):
-            cache = {}
-        if key in cache:
-            return dict(cache[key], cached=True)
+    key = _key([sysd], precision, R_probe, thermostat)
+    cache = _load(path) if use_cache else {}
+    if key in cache:
+        return dict(cache[key], cached=True)
     timings = {}
     for w in candidates:
         p = Pamd([sysd], R_target=R_probe, T0=T0, dt=dt, nu=1.0, seed=1, precision=precision,
                  waves_per_block=w, thermostat=thermostat)
-        p.md_steps(theta_probe)
-        torch.cuda.synchronize()
-        best = None
-        for _ in range(3):
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(p.stream)
-            p.md_steps(theta_probe)
-            e1.record(p.stream)
-            torch.cuda.synchronize()
-            ms = e0.elapsed_time(e1)
-            best = ms if best is None else min(best, ms)
-        timings[w] = R_probe * theta_probe / (best / 1e3)
+        timings[w] = R_probe * theta_probe / (_time_md(p, theta_probe) / 1e3)
         p.close()
     choice = max(timings, key=timings.get)
     entry = {"waves_per_block": int(choice), "timings": {str(k): v for k, v in timings.items()}}
     if use_cache:
         cache[key] = entry
-        try:
-            os.makedirs(os.path.dirname(path), exist_ok=True)
-            with open(path, "w") as f:
-                json.dump(cache, f, indent=1)
-        except OSError:
-            pass
+        _store(path, cache)
+    return dict(entry, cached=False)
+
+
+def autotune_batched(systems: Sequence, R_each: int, precision: int = PAMD_FP32, theta_probe: int = 100,
+                     wide_candidates: Sequence[int] = WIDE_CANDIDATES, T0: float = 700.0, dt: float = 0.0005,
+                     use_cache: bool = True, cache_path: Optional[str] = None,
+                     thermostat: str = "andersen") -> Dict:
+    """Launch shape of a context of several runs (R_each replicas each).
+
+    Candidates: every run in the batched wide launch, or the runs that fit
+    the register tile (at most 80 atoms) in register-tile launches and the
+    rest in the wide launch; in both cases the wide launch with 4, 3, 2 or 1
+    waves per workgroup.  Each candidate times the whole context's MD step
+    at the run's population sizes.  Returns {"layout": [per run "wide" /
+    "tile"], "wide_waves_per_block": w, "timings": {candidate: replica-steps/s},
+    "cached": bool}."""
+    import torch
+    systems = list(systems)
+    path = cache_path or _cache_path()
+    key = "batched-" + _key(systems, precision, R_each, thermostat)
+    cache = _load(path) if use_cache else {}
+    if key in cache:
+        return dict(cache[key], cached=True)
+    small = [s.n_atoms <= TILE_ATOMS for s in systems]
+    layouts = {"wide": ["wide"] * len(systems)}
+    if any(small) and not all(small):
+        layouts["tile_small"] = ["tile" if sm else "wide" for sm in small]
+    timings, shapes = {}, {}
+    for lname, lay in layouts.items():
+        for w in wide_candidates:
+            p = Pamd(systems, R_target=R_each, T0=T0, dt=dt, nu=1.0, seed=1, precision=precision,
+                     thermostat=thermostat, layout=lay, wide_waves=w)
+            ms = _time_md(p, theta_probe)
+            cand = f"{lname}/w{w}"
+            timings[cand] = R_each * len(systems) * theta_probe / (ms / 1e3)
+            shapes[cand] = (lay, w)
+            p.close()
+    torch.cuda.synchronize()
+    choice = max(timings, key=timings.get)
+    entry = {"layout": shapes[choice][0], "wide_waves_per_block": int(shapes[choice][1]), "choice": choice,
+             "timings": timings}
+    if use_cache:
+        cache[key] = entry
+        _store(path, cache)
     return dict(entry, cached=False)

@@ -1,4 +1,7 @@
-"""Build libpamd.so (HIP, gfx950) in-tree with hipcc.
+"""Build libpamd.so (HIP, gfx950) in-tree with hipcc, and its bounds-checked
+variant libpamd_check.so (the resampling kernels compiled with
+PAMD_BOUNDS_CHECK: every scan offset and gather source index is verified on
+the device and reported as PAMD_ERR_INTERNAL; otherwise the same objects).
 
     python -m paper_1806_06016_amd.build
 """
@@ -14,6 +17,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libpamd.so")
+CHECK_LIB = os.path.join(HERE, "libpamd_check.so")
+CHECKED_SOURCES = ["resample.hip"]   # the sources that hold bounds checks
 SOURCES = ["md_kernel.hip", "resample.hip", "runtime.hip", "nn_kernel.hip", "nn_runtime.hip", "calib.hip", "analysis.cpp"]
 ARCH = os.environ.get("PAMD_OFFLOAD_ARCH", "gfx950")
 
@@ -34,14 +39,18 @@ def _hipcc() -> str:
 
 
 def build(verbose: bool = False, extra_flags=()) -> str:
-    """Compile every source (always) and link libpamd.so.  Returns its path."""
+    """Compile every source (always) and link libpamd.so and libpamd_check.so.
+    Returns the path of libpamd.so."""
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
     hipcc = _hipcc()
 
-    def compile_one(src):
-        obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
-        cmd = [hipcc, *FLAGS, *extra_flags, "-c", os.path.join(CSRC, src), "-o", obj]
+    def compile_one(job):
+        src, checked = job
+        stem = os.path.splitext(src)[0] + ("_check" if checked else "")
+        obj = os.path.join(objdir, stem + ".o")
+        cmd = [hipcc, *FLAGS, *extra_flags, *(["-DPAMD_BOUNDS_CHECK"] if checked else []), "-c",
+               os.path.join(CSRC, src), "-o", obj]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
@@ -49,17 +58,20 @@ def build(verbose: bool = False, extra_flags=()) -> str:
             print(r.stderr, file=sys.stderr)
         return obj
 
-    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(compile_one, SOURCES))
-    tmp = LIB + ".tmp"
+    jobs = [(src, False) for src in SOURCES] + [(src, True) for src in CHECKED_SOURCES]
+    with ThreadPoolExecutor(max_workers=len(jobs)) as ex:
+        objs = dict(zip(jobs, ex.map(compile_one, jobs)))
     rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
-    # roctx: named ranges of the C-ABI calls in rocprofv3 marker traces
-    cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp, f"-L{rocm}/lib",
-           "-lrocprofiler-sdk-roctx"]
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        raise RuntimeError(f"link failed:\n{r.stderr}")
-    os.replace(tmp, LIB)
+    for lib, checked in ((LIB, False), (CHECK_LIB, True)):
+        parts = [objs[(src, checked and src in CHECKED_SOURCES)] for src in SOURCES]
+        tmp = lib + ".tmp"
+        # roctx: named ranges of the C-ABI calls in rocprofv3 marker traces
+        cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *parts, "-o", tmp, f"-L{rocm}/lib",
+               "-lrocprofiler-sdk-roctx"]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"link failed:\n{r.stderr}")
+        os.replace(tmp, lib)
     return LIB
 
 

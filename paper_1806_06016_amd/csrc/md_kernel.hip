@@ -1501,24 +1501,27 @@ __global__ __launch_bounds__(256, 3) void k_md_wide(const RunDev<float>* runs, c
     }
 }
 
-// start of a batched MD call: every run whose sticky error is set stays
-// frozen for the whole call
-__global__ void k_wide_begin(RunDev<float>* runs, int n_runs)
+// start of a batched MD call: every run of the launch (order[0 .. n_runs))
+// whose sticky error is set stays frozen for the whole call
+__global__ void k_wide_begin(RunDev<float>* runs, const int32_t* order, int n_runs)
 {
     for (int q = threadIdx.x; q < n_runs; q += blockDim.x)
-        runs[q].ctl->frozen = runs[q].ctl->error != 0;
+        runs[order[q]].ctl->frozen = runs[order[q]].ctl->error != 0;
 }
 
-// reset of the batch work counter and every run's step counter after k_md_wide
-__global__ void k_wide_finalize(RunDev<float>* runs, int n_runs, int32_t* counter, int n_steps)
+// reset of the batch work counter and the step counter of every run of the
+// launch after k_md_wide
+__global__ void k_wide_finalize(RunDev<float>* runs, const int32_t* order, int n_runs, int32_t* counter,
+                                int n_steps)
 {
     if (threadIdx.x != 0)
         return;
     *counter = 0;
     for (int q = 0; q < n_runs; ++q) {
-        if (!runs[q].ctl->frozen)
-            runs[q].ctl->step += (uint32_t)n_steps;
-        runs[q].ctl->work = 0;
+        RunCtl* ctl = runs[order[q]].ctl;
+        if (!ctl->frozen)
+            ctl->step += (uint32_t)n_steps;
+        ctl->work = 0;
     }
 }
 
@@ -1749,7 +1752,7 @@ hipError_t launch_md_wide(const RunDev<float>* runs, const int32_t* order, int n
 {
     const size_t lds = wide_lds_bytes(nmax, waves);
     const dim3 g(blocks), b(waves * 64);
-    hipLaunchKernelGGL(k_wide_begin, dim3(1), dim3(64), 0, s, const_cast<RunDev<float>*>(runs), n_runs);
+    hipLaunchKernelGGL(k_wide_begin, dim3(1), dim3(64), 0, s, const_cast<RunDev<float>*>(runs), order, n_runs);
     switch (diel * 2 + lang) {
     case 0: hipLaunchKernelGGL((k_md_wide<0, 0>), g, b, lds, s, runs, order, n_runs, counter, nmax, n_steps); break;
     case 1: hipLaunchKernelGGL((k_md_wide<0, 1>), g, b, lds, s, runs, order, n_runs, counter, nmax, n_steps); break;
@@ -1759,8 +1762,8 @@ hipError_t launch_md_wide(const RunDev<float>* runs, const int32_t* order, int n
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL(k_wide_finalize, dim3(1), dim3(64), 0, s, const_cast<RunDev<float>*>(runs), n_runs, counter,
-                       n_steps);
+    hipLaunchKernelGGL(k_wide_finalize, dim3(1), dim3(64), 0, s, const_cast<RunDev<float>*>(runs), order, n_runs,
+                       counter, n_steps);
     return hipGetLastError();
 }
 

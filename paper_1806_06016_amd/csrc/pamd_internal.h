@@ -45,7 +45,12 @@ struct alignas(64) RunCtl {
     int32_t error;       // sticky PAMD_ERR_* code
     int32_t work;        // persistent-kernel work counter
     int32_t frozen;      // error != 0 when the current MD call began: its kernels leave the run unchanged
-    int32_t pad[2];
+    uint32_t ticket;     // blocks done in the current multi-block reduction (the last one finishes it)
+    int32_t w_phase;     // adaptive step: 0 probe at the largest step, 1 Newton iterations, 2 T_next fixed
+    int32_t w_iter;      // Newton iterations done
+    int32_t pad;
+    double w_b, w_lo, w_hi;   // adaptive step: current dbeta and its bracket
+    double w_var;        // population variance of E (start of the Newton iteration)
 };
 
 // operations of one r-RESPA kernel pass (k_respa), applied in this order
@@ -62,6 +67,8 @@ struct RunDev {
     int32_t* counts;        // [R_cap]
     int32_t* src_of;        // [R_cap]
     double* cdf;            // [R_cap] running weight sums W_j (multinomial resampling)
+    double* part;           // per-block partial sums of the multi-block reductions
+    int64_t* cpart;         // per-block copy-number sums / family counts [ceil(R_cap / 256)]
     uint8_t* fam;           // [R_target] family flags
     const double* unif;     // optional caller uniforms for this run
     // topology / parameters

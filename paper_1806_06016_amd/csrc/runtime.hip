@@ -44,6 +44,8 @@ hipError_t launch_init(const RunDev<float>& d, hipStream_t s);
 hipError_t launch_init(const RunDev<double>& d, hipStream_t s);
 hipError_t launch_resample(const RunDev<float>& d, double T_req, double mtot, int gb, hipStream_t s);
 hipError_t launch_resample(const RunDev<double>& d, double T_req, double mtot, int gb, hipStream_t s);
+size_t part_doubles(int64_t R_cap);
+size_t cpart_count(int64_t R_cap);
 hipError_t launch_md_begin(const RunDev<float>& d, hipStream_t s);
 hipError_t launch_md_begin(const RunDev<double>& d, hipStream_t s);
 hipError_t launch_md_finalize(const RunDev<float>& d, int n, hipStream_t s);
@@ -116,13 +118,17 @@ struct pamd_ctx {
     std::vector<Run> runs;
     std::string err;
     int failed = 0;
-    int n_cu = 0, waves = 0, blocks = 0, gather_blocks = 0;
-    size_t lds = 0;
+    int n_cu = 0, gather_blocks = 0;
     int have_energy = 0;     // some pamd_md_steps (or a state with energies) since init
     pamd_nn* nn = nullptr;   // learned surrogate of the r-RESPA inner force (null: plain MD)
     int mts_ratio = 0;       // inner steps per outer step
-    // wide layout: every run in one persistent k_md_wide launch
-    int wide = 0, nmax = 0, diel = 0;
+    // launch shapes: register-tile runs (k_md, one launch per run) and wide
+    // runs (every one of them in one persistent k_md_wide launch)
+    int tile_waves = 0, tile_blocks = 0;
+    size_t tile_lds = 0;
+    int wide_waves = 0, wide_blocks = 0;
+    size_t wide_lds = 0;
+    int wide = 0, n_wide = 0, nmax = 0, diel = 0;   // wide: some run is wide; nmax: largest wide molecule
     RunDev<float>* d_runs = nullptr;   // device copies of the runs' descriptors
     int32_t* d_order = nullptr;        // runs in decreasing pair work
     int32_t* d_counter = nullptr;      // work-queue counter
@@ -150,13 +156,18 @@ pamd_status fail(pamd_ctx* c, pamd_status st, const std::string& msg)
 int nslot_of(int n) { return (n + kRow - 1) / kRow; }
 int npad_of(int n, int wide) { return wide ? (n + kWide - 1) / kWide * kWide : nslot_of(n) * kRow; }
 
-// the wide layout serves contexts with a molecule above the register-tile limit
-int wide_mode(const pamd_system* sys, int n_runs, int fp32)
+// MD layout of run r: PAMD_LAYOUT_WIDE / TILE as asked; AUTO takes the wide
+// layout when the context holds a molecule above the register-tile limit
+int run_is_wide(const pamd_system* sys, const pamd_params* p, int n_runs, int r)
 {
-    if (!fp32)
+    if (p[0].precision != PAMD_FP32)
         return 0;
-    for (int r = 0; r < n_runs; ++r)
-        if (sys[r].n_atoms > PAMD_TILE_ATOMS)
+    if (sys[r].n_atoms > PAMD_TILE_ATOMS || p[r].layout == PAMD_LAYOUT_WIDE)
+        return 1;
+    if (p[r].layout == PAMD_LAYOUT_TILE)
+        return 0;
+    for (int q = 0; q < n_runs; ++q)
+        if (sys[q].n_atoms > PAMD_TILE_ATOMS)
             return 1;
     return 0;
 }
@@ -233,6 +244,15 @@ pamd_status validate(pamd_ctx* c, const pamd_system& s, const pamd_params& p, in
         return fail(c, PAMD_ERR_ARG, "unknown resampling mode");
     if (p.thermostat != PAMD_THERMOSTAT_ANDERSEN && p.thermostat != PAMD_THERMOSTAT_LANGEVIN)
         return fail(c, PAMD_ERR_ARG, "unknown thermostat");
+    if (p.layout < PAMD_LAYOUT_AUTO || p.layout > PAMD_LAYOUT_WIDE)
+        return fail(c, PAMD_ERR_ARG, "unknown layout");
+    if (p.layout == PAMD_LAYOUT_TILE && s.n_atoms > PAMD_TILE_ATOMS)
+        return fail(c, PAMD_ERR_ARG, "the register-tile layout takes at most " + std::to_string(PAMD_TILE_ATOMS) +
+                                         " atoms");
+    if (p.layout == PAMD_LAYOUT_WIDE && !fp32)
+        return fail(c, PAMD_ERR_ARG, "the wide layout is FP32 only");
+    if (p.wide_waves_per_block < 0 || p.wide_waves_per_block > 4)
+        return fail(c, PAMD_ERR_ARG, "wide_waves_per_block must be 0..4");
     return PAMD_OK;
 }
 
@@ -837,6 +857,8 @@ void carve(Carver& st, Carver& wk, const pamd_system& s, const pamd_params& p, i
     d.counts = wk.take<int32_t>(Rc);
     d.src_of = wk.take<int32_t>(Rc);
     d.cdf = wk.take<double>(Rc);
+    d.part = wk.take<double>(part_doubles(Rc));
+    d.cpart = wk.take<int64_t>(cpart_count(Rc));
     d.fam = wk.take<uint8_t>(p.R_target);
     d.nb_ab = wk.take<real>((size_t)steps * 32);
     d.nb_c = wk.take<real>((size_t)steps * 16);
@@ -946,11 +968,13 @@ pamd_status layout(const pamd_system* sys, int32_t n_runs, const pamd_params* p,
 {
     Carver st(d_state), wk(d_work);
     const int fp32 = p[0].precision == PAMD_FP32;
-    const int wide = wide_mode(sys, n_runs, fp32);
+    int wide = 0;
     for (int r = 0; r < n_runs; ++r) {
         if (fp32) {
             RunDev<float> d{};
-            carve<float>(st, wk, sys[r], p[r], r, d, wide);
+            const int w = run_is_wide(sys, p, n_runs, r);
+            wide |= w;
+            carve<float>(st, wk, sys[r], p[r], r, d, w);
             if (runs)
                 (*runs)[r].f = d;
         } else {
@@ -1009,6 +1033,7 @@ pamd_status surface_device_error(pamd_ctx* c, int code)
         return PAMD_OK;
     const char* what = code == PAMD_ERR_CAPACITY   ? "resampled population over capacity (or extinct)"
                        : code == PAMD_ERR_NONFINITE ? "non-finite potential energy"
+                       : code == PAMD_ERR_INTERNAL  ? "an index check of the bounds-checked build failed"
                                                     : "device error";
     return fail(c, code, what);
 }
@@ -1038,21 +1063,23 @@ static pamd_status init_runs(pamd_ctx* c, const pamd_system* sys, hipStream_t s)
 {
     for (int r = 0; r < c->n_runs; ++r) {
         Run& run = c->runs[r];
-        build_tables(sys[r], run.tab, c->wide);
+        build_tables(sys[r], run.tab, c->fp32 ? run.f.wide : 0);
         run.mtot = run.tab.mtot;
         HIPCHK(c, upload<real>(dev<real>(run), run.tab, s));
         HIPCHK(c, launch_init(dev<real>(run), s));
     }
     if (c->wide) {
-        // the batched launch's descriptors and its largest-first run order
+        // the batched launch's descriptors and its largest-first order of the wide runs
         std::vector<RunDev<float>> rd(c->n_runs);
-        std::vector<int32_t> order(c->n_runs);
+        std::vector<int32_t> order;
         for (int r = 0; r < c->n_runs; ++r) {
             rd[r] = c->runs[r].f;
-            order[r] = r;
+            if (c->runs[r].f.wide)
+                order.push_back(r);
         }
         std::stable_sort(order.begin(), order.end(),
                          [&](int a, int b) { return sys[a].n_atoms > sys[b].n_atoms; });
+        c->n_wide = (int)order.size();
         HIPCHK(c, hipMemcpyAsync(c->d_runs, rd.data(), rd.size() * sizeof(RunDev<float>), hipMemcpyHostToDevice, s));
         HIPCHK(c, hipMemcpyAsync(c->d_order, order.data(), order.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
         HIPCHK(c, hipMemsetAsync(c->d_counter, 0, sizeof(int32_t), s));
@@ -1092,47 +1119,61 @@ pamd_status pamd_init(const pamd_system* sys, int32_t n_runs, const pamd_params*
     int max_lds = 0;
     HIPCHK(c, hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev_id));
 
-    // launch shape: the largest workgroup (<= 16 waves) whose LDS fits, all
-    // runs sharing it; enough resident blocks to fill every CU
-    int n_max = 0, ns_max = 0;
+    // launch shapes.  Register-tile runs: the largest workgroup (<= 16 waves)
+    // whose LDS fits, shared by those runs.  Wide runs: one replica per
+    // wavefront, at most 4 waves (256 threads) per workgroup.  Both with
+    // enough resident blocks to fill every CU.
+    int tn_max = 0, ts_max = 0, wn_max = 0, n_tile = 0;
     for (int r = 0; r < n_runs; ++r) {
-        n_max = std::max(n_max, sys[r].n_atoms);
-        ns_max = std::max(ns_max, nslot_of(sys[r].n_atoms));
+        if (c->fp32 && c->runs[r].f.wide) {
+            wn_max = std::max(wn_max, sys[r].n_atoms);
+        } else {
+            ++n_tile;
+            tn_max = std::max(tn_max, sys[r].n_atoms);
+            ts_max = std::max(ts_max, nslot_of(sys[r].n_atoms));
+        }
     }
-    int waves = p[0].waves_per_block;
-    int bpc = 0;
-    c->nmax = n_max;
+    c->nmax = wn_max;
     c->diel = sys[0].dielectric;
+    for (int r = 1; r < n_runs; ++r)
+        if (c->wide && sys[r].dielectric != sys[0].dielectric)
+            return fail(c, PAMD_ERR_ARG, "runs of a context with a batched launch must share the dielectric model");
     if (c->wide) {
-        // one replica per wavefront; at most 4 waves (256 threads) per workgroup
-        for (int r = 1; r < n_runs; ++r)
-            if (sys[r].dielectric != sys[0].dielectric)
-                return fail(c, PAMD_ERR_ARG, "runs of one batched launch must share the dielectric model");
-        if (waves == 0 || waves > 4)
+        int waves = p[0].wide_waves_per_block;
+        if (waves == 0)
             waves = 4;
-        while (waves > 1 && wide_lds_bytes(n_max, waves) > (size_t)max_lds)
+        while (waves > 1 && wide_lds_bytes(wn_max, waves) > (size_t)max_lds)
             --waves;
-        c->lds = wide_lds_bytes(n_max, waves);
-        HIPCHK(c, wide_setup(c->diel, n_max, waves, &bpc));
-    } else {
+        int bpc = 0;
+        HIPCHK(c, wide_setup(c->diel, wn_max, waves, &bpc));
+        if (bpc < 1)
+            return fail(c, PAMD_ERR_ARG, "batched MD kernel cannot be resident with this launch shape");
+        c->wide_waves = waves;
+        c->wide_blocks = c->n_cu * bpc;
+        c->wide_lds = wide_lds_bytes(wn_max, waves);
+    }
+    if (n_tile > 0) {
+        int waves = p[0].waves_per_block;
         if (waves == 0) {
             waves = 16;
-            while (waves > 1 && md_lds(c->fp32, ns_max, n_max, waves) > (size_t)max_lds)
+            while (waves > 1 && md_lds(c->fp32, ts_max, tn_max, waves) > (size_t)max_lds)
                 --waves;
         }
-        c->lds = md_lds(c->fp32, ns_max, n_max, waves);
-        if (c->lds > (size_t)max_lds)
+        c->tile_lds = md_lds(c->fp32, ts_max, tn_max, waves);
+        if (c->tile_lds > (size_t)max_lds)
             return fail(c, PAMD_ERR_ARG, "system too large for the LDS of one workgroup");
-        HIPCHK(c, md_occupancy(c->fp32, ns_max, sys[0].dielectric, n_max, waves, &bpc));
+        int bpc = 0;
+        HIPCHK(c, md_occupancy(c->fp32, ts_max, sys[0].dielectric, tn_max, waves, &bpc));
+        if (bpc < 1)
+            return fail(c, PAMD_ERR_ARG, "MD kernel cannot be resident with this launch shape");
+        c->tile_waves = waves;
+        c->tile_blocks = c->n_cu * bpc;
     }
-    if (bpc < 1)
-        return fail(c, PAMD_ERR_ARG, "MD kernel cannot be resident with this launch shape");
-    c->waves = waves;
-    c->blocks = c->n_cu * bpc;
     c->gather_blocks = c->n_cu * 8;
     for (int r = 0; r < n_runs; ++r) {
-        c->runs[r].f.waves_per_block = waves;
-        c->runs[r].d.waves_per_block = waves;
+        const int w = c->fp32 && c->runs[r].f.wide;
+        c->runs[r].f.waves_per_block = w ? c->wide_waves : c->tile_waves;
+        c->runs[r].d.waves_per_block = c->tile_waves;
         c->runs[r].nu = p[r].nu;
     }
     return c->fp32 ? init_runs<float>(c, sys, s) : init_runs<double>(c, sys, s);
@@ -1178,21 +1219,21 @@ static pamd_status respa_steps(pamd_ctx* c, Run& run, int n_steps, hipStream_t s
     if (n_outer > 0) {
         if ((st = nn_force(c, run, s)) != PAMD_OK)
             return st;
-        HIPCHK(c, launch_respa(d, fnn, kRespaOuterStart | kRespaDrift, 0, Dt, p24, c->blocks, c->waves, s));
+        HIPCHK(c, launch_respa(d, fnn, kRespaOuterStart | kRespaDrift, 0, Dt, p24, c->tile_blocks, c->tile_waves, s));
         for (int o = 0; o < n_outer; ++o) {
             for (int q = 0; q < M; ++q) {
                 if ((st = nn_force(c, run, s)) != PAMD_OK)
                     return st;
                 if (q < M - 1)
-                    HIPCHK(c, launch_respa(d, fnn, kRespaInnerKick | kRespaDrift, 0, Dt, p24, c->blocks, c->waves, s));
+                    HIPCHK(c, launch_respa(d, fnn, kRespaInnerKick | kRespaDrift, 0, Dt, p24, c->tile_blocks, c->tile_waves, s));
             }
             int ops = kRespaInnerKick | kRespaOuterEnd | kRespaCollide;
             if (o < n_outer - 1)
                 ops |= kRespaOuterStart | kRespaDrift;
-            HIPCHK(c, launch_respa(d, fnn, ops, (uint32_t)(o * M), Dt, p24, c->blocks, c->waves, s));
+            HIPCHK(c, launch_respa(d, fnn, ops, (uint32_t)(o * M), Dt, p24, c->tile_blocks, c->tile_waves, s));
         }
     }
-    HIPCHK(c, launch_energy(d, c->blocks, c->waves, s));
+    HIPCHK(c, launch_energy(d, c->tile_blocks, c->tile_waves, s));
     HIPCHK(c, launch_md_finalize(d, n_steps, s));
     return PAMD_OK;
 }
@@ -1207,11 +1248,10 @@ pamd_status pamd_md_steps(pamd_ctx* c, int32_t n_steps, void* stream)
         return fail(c, PAMD_ERR_ARG, "n_steps < 0");
     c->have_energy = 1;
     hipStream_t s = as_stream(stream);
-    if (c->wide) {
-        HIPCHK(c, launch_md_wide(c->d_runs, c->d_order, c->n_runs, c->d_counter, c->nmax, n_steps, c->diel,
-                                 c->runs[0].f.thermostat == PAMD_THERMOSTAT_LANGEVIN, c->blocks, c->waves, s));
-        return PAMD_OK;
-    }
+    if (c->wide)
+        HIPCHK(c, launch_md_wide(c->d_runs, c->d_order, c->n_wide, c->d_counter, c->nmax, n_steps, c->diel,
+                                 c->runs[0].f.thermostat == PAMD_THERMOSTAT_LANGEVIN, c->wide_blocks, c->wide_waves,
+                                 s));
     if (c->nn && n_steps > 0) {
         if (n_steps % c->mts_ratio != 0)
             return fail(c, PAMD_ERR_ARG, "n_steps must be a multiple of the r-RESPA outer ratio");
@@ -1223,15 +1263,17 @@ pamd_status pamd_md_steps(pamd_ctx* c, int32_t n_steps, void* stream)
         return PAMD_OK;
     }
     for (auto& run : c->runs) {
+        if (c->fp32 && run.f.wide)
+            continue;   // advanced by the batched launch above
         if (c->fp32) {
             HIPCHK(c, launch_md_begin(run.f, s));
-            HIPCHK(c, launch_md(run.f, n_steps, c->blocks, c->waves, s));
-            HIPCHK(c, launch_energy(run.f, c->blocks, c->waves, s));
+            HIPCHK(c, launch_md(run.f, n_steps, c->tile_blocks, c->tile_waves, s));
+            HIPCHK(c, launch_energy(run.f, c->tile_blocks, c->tile_waves, s));
             HIPCHK(c, launch_md_finalize(run.f, n_steps, s));
         } else {
             HIPCHK(c, launch_md_begin(run.d, s));
-            HIPCHK(c, launch_md(run.d, n_steps, c->blocks, c->waves, s));
-            HIPCHK(c, launch_energy(run.d, c->blocks, c->waves, s));
+            HIPCHK(c, launch_md(run.d, n_steps, c->tile_blocks, c->tile_waves, s));
+            HIPCHK(c, launch_energy(run.d, c->tile_blocks, c->tile_waves, s));
             HIPCHK(c, launch_md_finalize(run.d, n_steps, s));
         }
     }
@@ -1305,12 +1347,12 @@ static pamd_status get_forces_t(pamd_ctx* c, Run& run, int64_t r0, int32_t count
         return fail(c, PAMD_ERR_ARG, "replica range outside the population or chunk");
     RunDev<real>& d = dev<real>(run);
     if constexpr (sizeof(real) == 4) {
-        if (c->wide)
-            HIPCHK(c, launch_forces_wide(d, r0, count, c->nmax, c->waves, s));
+        if (d.wide)
+            HIPCHK(c, launch_forces_wide(d, r0, count, c->nmax, c->wide_waves, s));
         else
-            HIPCHK(c, launch_forces(d, r0, count, c->waves, s));
+            HIPCHK(c, launch_forces(d, r0, count, c->tile_waves, s));
     } else {
-        HIPCHK(c, launch_forces(d, r0, count, c->waves, s));
+        HIPCHK(c, launch_forces(d, r0, count, c->tile_waves, s));
     }
     std::vector<double> buf((size_t)count * d.npad * 4);
     HIPCHK(c, hipMemcpyAsync(buf.data(), d.dbg, buf.size() * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1504,12 +1546,30 @@ pamd_status pamd_launch_info(const pamd_ctx* c, int32_t* waves_per_block, int32_
 {
     if (!c)
         return PAMD_ERR_ARG;
+    // the batched launch when there is one, else the register-tile kernel
     if (waves_per_block)
-        *waves_per_block = c->waves;
+        *waves_per_block = c->wide ? c->wide_waves : c->tile_waves;
     if (blocks)
-        *blocks = c->blocks;
+        *blocks = c->wide ? c->wide_blocks : c->tile_blocks;
     if (lds_bytes)
-        *lds_bytes = (int32_t)c->lds;
+        *lds_bytes = (int32_t)(c->wide ? c->wide_lds : c->tile_lds);
+    return PAMD_OK;
+}
+
+pamd_status pamd_run_launch(const pamd_ctx* c, int32_t run, int32_t* layout, int32_t* waves_per_block,
+                            int32_t* blocks, int32_t* lds_bytes)
+{
+    if (!c || run < 0 || run >= c->n_runs)
+        return PAMD_ERR_ARG;
+    const int w = c->fp32 && c->runs[run].f.wide;
+    if (layout)
+        *layout = w ? PAMD_LAYOUT_WIDE : PAMD_LAYOUT_TILE;
+    if (waves_per_block)
+        *waves_per_block = w ? c->wide_waves : c->tile_waves;
+    if (blocks)
+        *blocks = w ? c->wide_blocks : c->tile_blocks;
+    if (lds_bytes)
+        *lds_bytes = (int32_t)(w ? c->wide_lds : c->tile_lds);
     return PAMD_OK;
 }
 
@@ -1597,17 +1657,17 @@ pamd_status pamd_export_configs(pamd_ctx* c, int32_t run, int64_t r0, int64_t co
     pamd_status st = check_ctx(c);
     if (st != PAMD_OK)
         return st;
-    if (!c->fp32 || c->wide)
-        return fail(c, PAMD_ERR_ARG, "configuration export needs an FP32 context of molecules up to " +
-                                         std::to_string(PAMD_TILE_ATOMS) + " atoms");
     if (run < 0 || run >= c->n_runs)
         return fail(c, PAMD_ERR_ARG, "run index out of range");
+    if (!c->fp32 || c->runs[run].f.wide)
+        return fail(c, PAMD_ERR_ARG, "configuration export needs an FP32 run in the register-tile layout (up to " +
+                                         std::to_string(PAMD_TILE_ATOMS) + " atoms)");
     const RunDev<float>& d = c->runs[run].f;
     if (r0 < 0 || count < 0 || r0 + count > d.R_cap || (count > 0 && (!d_x || !d_F_nb)))
         return fail(c, PAMD_ERR_ARG, "replica range or output arrays invalid");
     if (count == 0)
         return PAMD_OK;
-    HIPCHK(c, launch_export(d, r0, count, d_x, d_F_nb, c->waves, as_stream(stream)));
+    HIPCHK(c, launch_export(d, r0, count, d_x, d_F_nb, c->tile_waves, as_stream(stream)));
     return PAMD_OK;
 }
 
@@ -1651,8 +1711,9 @@ pamd_status pamd_set_mts(pamd_ctx* c, pamd_nn* nn, int32_t outer_ratio, void* d_
         return PAMD_OK;
     }
     if (!c->fp32 || c->wide)
-        return fail(c, PAMD_ERR_ARG, "r-RESPA with the surrogate needs an FP32 context of molecules up to " +
-                                         std::to_string(PAMD_TILE_ATOMS) + " atoms");
+        return fail(c, PAMD_ERR_ARG, "r-RESPA with the surrogate needs an FP32 context whose runs all use the "
+                                     "register-tile layout (molecules up to " + std::to_string(PAMD_TILE_ATOMS) +
+                                     " atoms)");
     if (outer_ratio < 1)
         return fail(c, PAMD_ERR_ARG, "outer_ratio must be >= 1");
     if (c->runs[0].f.thermostat != PAMD_THERMOSTAT_ANDERSEN)

@@ -9,12 +9,19 @@ through the C ABI (argument marshalling and bookkeeping only here).
    nonbonded forces (pamd_export_configs).
 2. Training: force-matching loss, Adam with a cosine-decayed step size,
    random batches of 256 configurations, 10 % held out.
-3. Evaluation at equal physical time, NVE from a 300 K population: energy
-   drift (RMS of E_tot(t) - E_tot(0) over replicas and samples) and
-   throughput (replica time steps of dt per second and simulated time per
-   second) for plain velocity Verlet at dt = 1 and 2 fs, r-RESPA with the
-   trained surrogate (inner 1 fs, outer 2 and 4 fs) and r-RESPA with a zero
-   surrogate (the whole nonbonded force in the outer impulse).
+3. Evaluation at equal physical time, NVE from 256 replicas of the final
+   300 K population over a 10 ps window: energy drift as the mean over
+   replicas of |slope| of a least-squares line through E_tot(t) per atom
+   (kJ/mol/ps/atom) and the RMS of E_tot(t) - E_tot(0), and throughput
+   (replica time steps per second, simulated time per second, R = 1e5) for
+   plain velocity Verlet at dt = 0.5, 1, 1.5 and 2 fs, r-RESPA with the
+   trained surrogate (inner 1 fs, outer 2, 3 and 4 fs) and r-RESPA with a
+   zero surrogate (the whole nonbonded force in the outer impulse: the method
+   without the network).
+4. Equal drift: a straight line through log(drift) against log(dt) of the
+   plain runs gives the plain time step with the drift of each r-RESPA case;
+   plain velocity Verlet's simulated time per second there (its cost per
+   step does not depend on dt) is set against the r-RESPA case's.
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -116,6 +123,7 @@ def nve_run(sysd, x0, v0, dt: float, nn=None, M: int = 1, window_ps: float = 10.
     if nn is not None:
         k = max(M, k // M * M)
     dev = []
+    times = []
     s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ms = 0.0
     unstable = False
@@ -133,13 +141,22 @@ def nve_run(sysd, x0, v0, dt: float, nn=None, M: int = 1, window_ps: float = 10.
         ms += s0.elapsed_time(s1)
         E = st["E_pot"] + st["E_kin"]
         dev.append(E - E0)
+        times.append(len(dev) * k * dt)
     done = len(dev) * k
     out = dict(dt_fs=dt * 1000.0, outer_fs=(M * dt * 1000.0 if nn is not None else dt * 1000.0),
                replicas=R, steps=done, md_ms=ms, unstable=unstable)
     if unstable or not dev:
         out["rms_drift_kJmol"] = float("inf")
+        out["drift_kJmol_ps_atom"] = float("inf")
     else:
-        out["rms_drift_kJmol"] = float(np.sqrt(np.mean(np.array(dev) ** 2)))
+        dv = np.array(dev)                                   # [samples, replicas]
+        out["rms_drift_kJmol"] = float(np.sqrt(np.mean(dv ** 2)))
+        # least-squares slope of E_tot(t) - E_tot(0) through (0, 0) and the samples, per replica
+        t = np.concatenate([[0.0], times])
+        y = np.vstack([np.zeros(dv.shape[1]), dv])
+        tc = t - t.mean()
+        slope = (tc[:, None] * (y - y.mean(0))).sum(0) / (tc * tc).sum()
+        out["drift_kJmol_ps_atom"] = float(np.mean(np.abs(slope)) / sysd.n_atoms)
     if done > 0 and ms > 0:
         out["replica_steps_per_s"] = R * done / (ms / 1000.0)
         out["replica_ps_per_s"] = out["replica_steps_per_s"] * dt
@@ -168,6 +185,46 @@ def throughput(sysd, x0, v0, dt: float, nn=None, M: int = 1, R: int = 100000, st
     p.close()
     return dict(R=R, steps=steps, ms=ms, replica_steps_per_s=R * steps / (ms / 1000.0),
                 replica_ps_per_s=R * steps * dt / (ms / 1000.0))
+
+
+def anneal_curve(sysd, R: int, sched, theta: int, theta_eq: int, seed: int, nn=None, M: int = 1,
+                 dt: float = 0.001) -> np.ndarray:
+    """<E_pot>(T) of one PAMD run (nearest-integer resampling, Andersen
+    1/ps): theta_eq plain velocity-Verlet steps at sched[0], then for every
+    further temperature a resampling and theta steps of dt, by plain velocity
+    Verlet or, with a surrogate, by r-RESPA with outer step M dt."""
+    p = B.Pamd([sysd], R_target=R, T0=sched[0], dt=dt, nu=1.0, seed=seed, precision=B.PAMD_FP32)
+    p.md_steps(theta_eq)
+    E = [p.observables()[0]["E_mean"]]
+    if nn is not None:
+        p.set_mts(nn, M)
+    for T in sched[1:]:
+        p.resample([T])
+        p.md_steps(theta)
+        E.append(p.observables()[0]["E_mean"])
+    p.close()
+    return np.array(E)
+
+
+def equal_drift(plain: Dict[float, Dict], case: Dict) -> Dict:
+    """Plain velocity Verlet at the drift of `case`: a least-squares line
+    through log(drift) against log(dt) of the plain runs (dt in fs -> result)
+    gives the time step dt* with that drift; plain MD costs the same per step
+    at any dt, so its simulated time per second at dt* is its measured
+    replica-steps/s times dt*.  Returns dt*, that rate and the case's rate
+    over it."""
+    pts = [(dt, r) for dt, r in plain.items() if np.isfinite(r["drift_kJmol_ps_atom"]) and r["drift_kJmol_ps_atom"] > 0]
+    d = case["drift_kJmol_ps_atom"]
+    if len(pts) < 2 or not np.isfinite(d) or d <= 0:
+        return dict(dt_equal_fs=None, plain_replica_ps_per_s=None, speedup=None)
+    lx = np.log([p[0] for p in pts])
+    ly = np.log([p[1]["drift_kJmol_ps_atom"] for p in pts])
+    b, a = np.polyfit(lx, ly, 1)                 # log drift = a + b log dt
+    dt_eq = float(np.exp((math.log(d) - a) / b))
+    steps_per_s = float(np.mean([p[1]["throughput"]["replica_steps_per_s"] for p in pts]))
+    plain_rate = steps_per_s * dt_eq * 1e-3      # replica-ps/s
+    return dict(dt_equal_fs=dt_eq, drift_exponent=float(b), plain_replica_ps_per_s=plain_rate,
+                speedup=case["throughput"]["replica_ps_per_s"] / plain_rate)
 
 
 def kernel_timing(R: int, reps: int = 5) -> Dict:
@@ -240,9 +297,9 @@ def main(argv=None):
     R0 = 256
     x0, v0 = st["x"][:R0], st["v"][:R0]
     zero = B.PamdNN(sysd, sysd.atype)
-    cases = [("vv_1fs", 0.001, None, 1), ("vv_2fs", 0.002, None, 1),
-             ("respa_nn_2fs", 0.001, nn, 2), ("respa_nn_4fs", 0.001, nn, 4),
-             ("respa_zero_2fs", 0.001, zero, 2), ("respa_zero_4fs", 0.001, zero, 4)]
+    cases = [(f"vv_{dt}fs", dt * 1e-3, None, 1) for dt in (0.5, 1.0, 1.5, 2.0)]
+    cases += [(f"respa_nn_{M}fs", 0.001, nn, M) for M in (2, 3, 4)]
+    cases += [(f"respa_zero_{M}fs", 0.001, zero, M) for M in (2, 3, 4)]
     res = {}
     for name, dt, net, M in cases:
         d = nve_run(sysd, x0, v0, dt, net, M, window_ps=a.window_ps)
@@ -251,8 +308,12 @@ def main(argv=None):
         res[name] = d
         print(name, json.dumps({k: v for k, v in d.items() if k != "throughput"}),
               "throughput", json.dumps(thr), flush=True)
+    plain = {float(n[3:-2]): r for n, r in res.items() if n.startswith("vv_")}
+    eq = {n: equal_drift(plain, r) for n, r in res.items() if n.startswith("respa_")}
+    for n, e in eq.items():
+        print(n, "at equal drift:", json.dumps(e), flush=True)
     line = dict(metric="replica_ps_per_s", data="synthetic", config=dict(workload="peptide75 MTS surrogate",
-                collect_replicas=a.replicas, temperatures=41), training=tr, cases=res,
+                collect_replicas=a.replicas, temperatures=41), training=tr, cases=res, equal_drift=eq,
                 collect_seconds=t_collect)
     print(json.dumps(line))
     nn.close()

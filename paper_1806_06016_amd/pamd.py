@@ -14,11 +14,14 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpamd.so")
+CHECK_LIB_PATH = os.path.join(_HERE, "libpamd_check.so")   # resampling indices verified on the device
 
-PAMD_OK, PAMD_ERR_ARG, PAMD_ERR_HIP, PAMD_ERR_CAPACITY, PAMD_ERR_NONFINITE, PAMD_ERR_STATE = range(6)
+PAMD_OK, PAMD_ERR_ARG, PAMD_ERR_HIP, PAMD_ERR_CAPACITY, PAMD_ERR_NONFINITE, PAMD_ERR_STATE, PAMD_ERR_INTERNAL = range(7)
 PAMD_FP64, PAMD_FP32 = 0, 1
 PAMD_RESAMPLE_NEAREST, PAMD_RESAMPLE_MULTINOMIAL, PAMD_RESAMPLE_NONE = 0, 1, 2
 PAMD_THERMOSTAT_ANDERSEN, PAMD_THERMOSTAT_LANGEVIN = 0, 1
+PAMD_LAYOUT_AUTO, PAMD_LAYOUT_TILE, PAMD_LAYOUT_WIDE = 0, 1, 2
+LAYOUTS = {"auto": PAMD_LAYOUT_AUTO, "tile": PAMD_LAYOUT_TILE, "wide": PAMD_LAYOUT_WIDE}
 THERMOSTATS = {"andersen": PAMD_THERMOSTAT_ANDERSEN, "langevin": PAMD_THERMOSTAT_LANGEVIN}
 RESAMPLING_MODES = {"nearest": PAMD_RESAMPLE_NEAREST, "multinomial": PAMD_RESAMPLE_MULTINOMIAL,
                     "none": PAMD_RESAMPLE_NONE}
@@ -51,7 +54,8 @@ class pamd_params(C.Structure):
         ("R_target", C.c_int64), ("R_cap", C.c_int64), ("T0", C.c_double), ("dt", C.c_double),
         ("nu", C.c_double), ("seed", C.c_uint64), ("precision", C.c_int32),
         ("waves_per_block", C.c_int32), ("V_target", C.c_double), ("T_final", C.c_double),
-        ("resampling", C.c_int32), ("thermostat", C.c_int32),
+        ("resampling", C.c_int32), ("thermostat", C.c_int32), ("layout", C.c_int32),
+        ("wide_waves_per_block", C.c_int32),
     ]
 
 
@@ -73,7 +77,7 @@ class pamd_run_scalars(C.Structure):
 EXPORTS = ["pamd_query_sizes", "pamd_init", "pamd_md_steps", "pamd_resample", "pamd_observables",
            "pamd_graph_capture", "pamd_graph_launch", "pamd_set_schedule",
            "pamd_get_forces", "pamd_get_state", "pamd_set_state", "pamd_get_counts",
-           "pamd_launch_info", "pamd_destroy", "pamd_last_error",
+           "pamd_launch_info", "pamd_run_launch", "pamd_destroy", "pamd_last_error",
            "pamd_nn_query_sizes", "pamd_nn_create", "pamd_nn_set_weights", "pamd_nn_get_weights",
            "pamd_nn_forces", "pamd_nn_forces_static",
            "pamd_nn_loss_grad", "pamd_nn_train_step", "pamd_nn_destroy", "pamd_nn_last_error",
@@ -85,13 +89,17 @@ NN_STATIC_ROWS = 16000      # configuration-atom rows of pamd_nn_forces_static
 _NO_STATUS = ("pamd_destroy", "pamd_last_error", "pamd_nn_destroy", "pamd_nn_last_error")
 
 _lib = None
+_other_libs: Dict[str, object] = {}
 
 
 def load_library(path: str = LIB_PATH):
-    """Load libpamd.so (built by ``python -m paper_1806_06016_amd.build``)."""
+    """Load libpamd.so (built by ``python -m paper_1806_06016_amd.build``), or
+    another build of it such as CHECK_LIB_PATH."""
     global _lib
-    if _lib is not None:
+    if path == LIB_PATH and _lib is not None:
         return _lib
+    if path != LIB_PATH and path in _other_libs:
+        return _other_libs[path]
     # torch first: libpamd then binds to the HIP runtime torch already loaded
     # (one runtime per process)
     import torch  # noqa: F401
@@ -114,6 +122,7 @@ def load_library(path: str = LIB_PATH):
     lib.pamd_set_state.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
     lib.pamd_get_counts.argtypes = [vp, i32, vp, P(i64), vp]
     lib.pamd_launch_info.argtypes = [vp, P(i32), P(i32), P(i32)]
+    lib.pamd_run_launch.argtypes = [vp, i32, P(i32), P(i32), P(i32), P(i32)]
     lib.pamd_destroy.argtypes = [vp]
     lib.pamd_destroy.restype = None
     lib.pamd_last_error.argtypes = [vp]
@@ -141,7 +150,10 @@ def load_library(path: str = LIB_PATH):
     for name in EXPORTS:
         if name not in _NO_STATUS:
             getattr(lib, name).restype = i32
-    _lib = lib
+    if path == LIB_PATH:
+        _lib = lib
+    else:
+        _other_libs[path] = lib
     return lib
 
 
@@ -251,13 +263,19 @@ class Pamd:
     def __init__(self, systems: Sequence, R_target: int, T0: float, dt: float, nu: float, seed: int,
                  precision: int = PAMD_FP32, R_cap: Optional[int] = None, V_target: float = 0.1,
                  T_final: Optional[float] = None, waves_per_block: int = 0, stream=None,
-                 resampling="nearest", thermostat: str = "andersen"):
+                 resampling="nearest", thermostat: str = "andersen", layout="auto", wide_waves: int = 0,
+                 library: Optional[str] = None):
         """resampling: "nearest", "multinomial" or "none" for every run, or one
         mode per run (a sequence).  thermostat: "andersen" (nu = collision
-        frequency) or "langevin" (nu = friction gamma), one for the context."""
+        frequency) or "langevin" (nu = friction gamma), one for the context.
+        layout: "auto", "tile" or "wide" for every run, or one per run.
+        waves_per_block / wide_waves: workgroup size of the register-tile and
+        of the batched wide kernel (0: automatic).  library: path of the
+        library build to run (default libpamd.so; CHECK_LIB_PATH: the
+        bounds-checked resampling)."""
         import torch
         self.torch = torch
-        self.lib = load_library()
+        self.lib = load_library(library or LIB_PATH)
         if not torch.cuda.is_available():
             raise RuntimeError("the PAMD library needs a ROCm GPU")
         self.systems = list(systems)
@@ -284,6 +302,8 @@ class Pamd:
             mode = resampling if isinstance(resampling, str) else resampling[r]
             p.resampling = RESAMPLING_MODES[mode]
             p.thermostat = THERMOSTATS[thermostat]
+            p.layout = LAYOUTS[layout if isinstance(layout, str) else layout[r]]
+            p.wide_waves_per_block = int(wide_waves)
             prm.append(p)
         self._prm = P(*prm)
         sb, wb = C.c_size_t(), C.c_size_t()
@@ -317,6 +337,14 @@ class Pamd:
         w, b, l = C.c_int32(), C.c_int32(), C.c_int32()
         self._check(self.lib.pamd_launch_info(self.ctx, C.byref(w), C.byref(b), C.byref(l)), self.ctx)
         return dict(waves_per_block=w.value, blocks=b.value, lds_bytes=l.value)
+
+    def run_launch(self, run: int) -> Dict:
+        """Layout ("tile" / "wide") and launch shape of the kernel advancing `run`."""
+        lay, w, b, l = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        self._check(self.lib.pamd_run_launch(self.ctx, int(run), C.byref(lay), C.byref(w), C.byref(b), C.byref(l)),
+                    self.ctx)
+        return dict(layout={PAMD_LAYOUT_TILE: "tile", PAMD_LAYOUT_WIDE: "wide"}[lay.value], waves_per_block=w.value,
+                    blocks=b.value, lds_bytes=l.value)
 
     # -- PAMD steps -----------------------------------------------------------
     def md_steps(self, n: int) -> None:

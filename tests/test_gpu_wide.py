@@ -1,8 +1,11 @@
 """GPU: the wide layout (one replica per wavefront) and the batched launch of
 several uneven runs, against the FP64 oracle, through the C ABI.
 
-A context holding a molecule above the register-tile limit runs every run in
-one persistent launch (items handed out largest molecule first).  Same
+A context holding a molecule above the register-tile limit runs its wide runs
+in one persistent launch (items handed out largest molecule first); its runs
+of at most 80 atoms take that launch too (layout "auto") or register-tile
+launches of their own (layout "tile", the mixed case the autotuner may
+choose).  Every test runs both.  Same
 tolerances as the register-tile parity tests: per-atom forces within
 1e-4 (|F_a| + F_rms), energies within 1e-5 of sum |terms|, positions within
 1e-4 nm after 100 NVT steps with identical Philox streams, copy numbers
@@ -47,6 +50,17 @@ def _batched_systems():
     return [_peptide(1806 + k, n) for k, n in enumerate(S.C4_SIZES)]
 
 
+def _layouts(syss, mode):
+    """per-run layout: "auto" everywhere, or "tile" for the runs that fit the register tile"""
+    return ["tile" if (mode == "mixed" and s.n_atoms <= 80) else "auto" for s in syss]
+
+
+def _check_layouts(p, syss, mode):
+    for r, sysd in enumerate(syss):
+        want = "wide" if (sysd.n_atoms > 80 or mode == "auto") else "tile"
+        assert p.run_launch(r)["layout"] == want
+
+
 def _perturbed(sysd, R, scale, seed):
     rng = np.random.default_rng(seed)
     return np.ascontiguousarray(sysd.x_init[None] + rng.normal(0, scale, size=(R,) + sysd.x_init.shape))
@@ -60,12 +74,15 @@ def test_batched_context_uses_the_wide_layout(B):
     p.close()
 
 
-def test_wide_forces_and_energies(B):
+@pytest.mark.parametrize("mode", ["auto", "mixed"])
+def test_wide_forces_and_energies(B, mode):
     """Every molecule size of the batched workload (40 ... 300 atoms), batched."""
     syss = _batched_systems()
     R = 13
-    print("wide forces", S.C4_SIZES, flush=True)
-    p = B.Pamd(syss, R_target=R, T0=700.0, dt=0.001, nu=1.0, seed=3, precision=B.PAMD_FP32)
+    print("wide forces", S.C4_SIZES, mode, flush=True)
+    p = B.Pamd(syss, R_target=R, T0=700.0, dt=0.001, nu=1.0, seed=3, precision=B.PAMD_FP32,
+               layout=_layouts(syss, mode))
+    _check_layouts(p, syss, mode)
     for r, sysd in enumerate(syss):
         x = _perturbed(sysd, R, 0.01, 5 + r)
         p.set_state(r, x, np.zeros_like(x), T=700.0)
@@ -82,13 +99,16 @@ def test_wide_forces_and_energies(B):
     p.close()
 
 
-def test_wide_trajectories_match_oracle(B):
-    """All runs advance in one launch; each matches its own oracle run
+@pytest.mark.parametrize("mode", ["auto", "mixed"])
+def test_wide_trajectories_match_oracle(B, mode):
+    """All runs advance in one call; each matches its own oracle run
     (Philox key seed_hi + run)."""
     syss = _systems()
     R, T, nu, seed, n_steps = 11, 700.0, 1.0, 77, 100
-    print("wide trajectories", SIZES, flush=True)
-    p = B.Pamd(syss, R_target=R, T0=T, dt=0.001, nu=nu, seed=seed, precision=B.PAMD_FP32)
+    print("wide trajectories", SIZES, mode, flush=True)
+    p = B.Pamd(syss, R_target=R, T0=T, dt=0.001, nu=nu, seed=seed, precision=B.PAMD_FP32,
+               layout=_layouts(syss, mode))
+    _check_layouts(p, syss, mode)
     starts = []
     for r, sysd in enumerate(syss):
         osys = O.OracleSystem(sysd)
@@ -114,14 +134,16 @@ def test_wide_trajectories_match_oracle(B):
     p.close()
 
 
-def test_batched_anneal_matches_oracle_per_run(B):
+@pytest.mark.parametrize("mode", ["auto", "mixed"])
+def test_batched_anneal_matches_oracle_per_run(B, mode):
     """Two temperature steps of every run: per-run resampling (counts bit-exact,
     ancestors) and MD in the shared launch."""
     syss = _systems()
     R, seed, theta = 64, 31, 40
     temps = [700.0, 690.0, 680.0]
-    print("batched anneal", SIZES, flush=True)
-    p = B.Pamd(syss, R_target=R, T0=temps[0], dt=0.001, nu=1.0, seed=seed, precision=B.PAMD_FP32)
+    print("batched anneal", SIZES, mode, flush=True)
+    p = B.Pamd(syss, R_target=R, T0=temps[0], dt=0.001, nu=1.0, seed=seed, precision=B.PAMD_FP32,
+               layout=_layouts(syss, mode))
     p.md_steps(theta)
     ora = []
     for r, sysd in enumerate(syss):
@@ -156,13 +178,14 @@ def test_batched_anneal_matches_oracle_per_run(B):
     p.close()
 
 
-def test_batched_graph_replay_is_identical(B):
+@pytest.mark.parametrize("mode", ["auto", "mixed"])
+def test_batched_graph_replay_is_identical(B, mode):
     syss = _systems()
     R = 48
 
     def run(use_graph):
         p = B.Pamd(syss, R_target=R, T0=700.0, dt=0.001, nu=1.0, seed=9, precision=B.PAMD_FP32,
-                   T_final=600.0)
+                   T_final=600.0, layout=_layouts(syss, mode))
         p.md_steps(20)
         if use_graph:
             p.graph_capture(20, mode="adaptive", slot=0, parts="both")
@@ -182,3 +205,45 @@ def test_batched_graph_replay_is_identical(B):
     for r in range(len(syss)):
         assert np.array_equal(a[r]["x"], b[r]["x"])
         assert oa[r]["T"] == ob[r]["T"] and oa[r]["sum_lnQ"] == ob[r]["sum_lnQ"]
+
+
+def test_forced_wide_layout_of_a_small_molecule(B):
+    """The 75-atom peptide alone, forced into the wide layout: forces and a
+    short trajectory as in the register-tile layout (both against the oracle)."""
+    sysd = S.c2_system()
+    R, T, nu, seed = 9, 700.0, 1.0, 5
+    p = B.Pamd([sysd], R_target=R, T0=T, dt=0.001, nu=nu, seed=seed, precision=B.PAMD_FP32, layout="wide")
+    assert p.run_launch(0)["layout"] == "wide"
+    osys = O.OracleSystem(sysd)
+    x = _perturbed(sysd, R, 0.003, 2)
+    v = O.init_velocities(osys, R, T, seed=4)
+    p.set_state(0, x, v, T=T)
+    xo, vo = as_stored(x, True), as_stored(v, True)
+    F, E = p.get_forces(0)
+    Eo, Fo = O.energy_forces(osys, xo)[:2]
+    frms = np.sqrt((Fo ** 2).sum(-1).mean(-1))[:, None]
+    assert (np.linalg.norm(F - Fo, axis=-1) <= 1e-4 * (np.linalg.norm(Fo, axis=-1) + frms)).all()
+    p.md_steps(50)
+    O.md_steps(osys, xo, vo, 50, T, 0.001, nu, seed, step0=0)
+    assert np.abs(p.get_state(0)["x"] - xo).max() < 1e-4
+    p.close()
+
+
+def test_autotuner_picks_a_layout_and_wide_launch_shape(B):
+    """The batched autotuner times every candidate (all runs wide, or the
+    small runs in register-tile launches; 4..1 waves per workgroup of the
+    wide launch) and the chosen shape builds a working context."""
+    from paper_1806_06016_amd.autotune import autotune_batched
+    syss = [_peptide(1806, 40), _peptide(1807, 120)]
+    t = autotune_batched(syss, 512, theta_probe=10, use_cache=False)
+    print("autotune", t)
+    assert set(t["timings"]) == {f"{l}/w{w}" for l in ("wide", "tile_small") for w in (4, 3, 2, 1)}
+    assert all(v > 0 for v in t["timings"].values())
+    assert t["timings"][t["choice"]] == max(t["timings"].values())
+    p = B.Pamd(syss, R_target=64, T0=700.0, dt=0.0005, nu=1.0, seed=2, precision=B.PAMD_FP32,
+               layout=t["layout"], wide_waves=t["wide_waves_per_block"])
+    assert [p.run_launch(r)["layout"] for r in range(2)] == t["layout"]
+    assert p.run_launch(1)["waves_per_block"] == t["wide_waves_per_block"]
+    p.md_steps(5)
+    assert p.observables()[1]["step"] == 5
+    p.close()
