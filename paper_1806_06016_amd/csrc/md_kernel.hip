@@ -306,6 +306,80 @@ __device__ __forceinline__ void add3(real* frc, int a, real fx, real fy, real fz
     }
 }
 
+// One lane per centre atom j with up to NO outer atoms (NO = 4: the six
+// angles of the outer pairs; NO = 3: the three pairs of outer roles 0..2):
+// each bond vector u_a = x_a - x_j is normalised once (e_a), and the force on
+// outer atom a of angle (a, j, c) is -k dth (cos theta e_a - e_c) / (|u_a| sin theta);
+// the centre takes minus the sum.
+template <typename real, bool ENERGY, int NO>
+__device__ __forceinline__ void angle_group(const RunDev<real>& d, const real* pos, real* frc, int t, double& eacc)
+{
+    const int4 ga = d.agrp[2 * t];
+    if (ga.x < 0)
+        return;
+    const int oa[4] = {ga.y, ga.z, ga.w, NO == 4 ? d.agrp[2 * t + 1].x : -1};
+    const real* par = d.agpar + 12 * t;
+    real pj[3];
+    ld3(pos, ga.x, pj);
+    real e[NO][3], iu[NO];
+#pragma unroll
+    for (int a = 0; a < NO; ++a) {
+        real pa[3];
+        ld3(pos, oa[a] >= 0 ? oa[a] : ga.x, pa);
+        const real ux = pa[0] - pj[0], uy = pa[1] - pj[1], uz = pa[2] - pj[2];
+        // absent outer atoms (their angles carry k = 0): a unit vector along x
+        iu[a] = oa[a] >= 0 ? rsq_(ux * ux + uy * uy + uz * uz) : (real)1;
+        e[a][0] = oa[a] >= 0 ? ux * iu[a] : (real)1;
+        e[a][1] = uy * iu[a];
+        e[a][2] = uz * iu[a];
+    }
+    real S[NO][3];
+#pragma unroll
+    for (int a = 0; a < NO; ++a)
+        S[a][0] = S[a][1] = S[a][2] = (real)0;
+    constexpr int NQ = NO * (NO - 1) / 2;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        // outer pairs (0,1) (0,2) (0,3) (1,2) (1,3) (2,3) at parameter slots 0..5;
+        // with three outer atoms (0,1) (0,2) (1,2) at slots 0, 1, 3
+        constexpr int A4[6] = {0, 0, 0, 1, 1, 2}, C4[6] = {1, 2, 3, 2, 3, 3};
+        constexpr int A3[3] = {0, 0, 1}, C3[3] = {1, 2, 2}, P3[3] = {0, 1, 3};
+        const int a = NO == 4 ? A4[q] : A3[q], c = NO == 4 ? C4[q] : C3[q];
+        const int ps = NO == 4 ? q : P3[q];
+        const real k = par[2 * ps], th0 = par[2 * ps + 1];
+        const real cs = e[a][0] * e[c][0] + e[a][1] * e[c][1] + e[a][2] * e[c][2];
+        const real cx = e[a][1] * e[c][2] - e[a][2] * e[c][1];
+        const real cy = e[a][2] * e[c][0] - e[a][0] * e[c][2];
+        const real cz = e[a][0] * e[c][1] - e[a][1] * e[c][0];
+        const real sn = sqrt_(cx * cx + cy * cy + cz * cz);
+        const real dth = angle_yx(sn, cs) - th0;
+        if constexpr (ENERGY) {
+            eacc += (double)((real)0.5 * k * dth * dth);
+        } else {
+            const real g = k * dth * rcp_(sn < (real)1e-8 ? (real)1e-8 : sn);
+            S[a][0] += g * (cs * e[a][0] - e[c][0]);
+            S[a][1] += g * (cs * e[a][1] - e[c][1]);
+            S[a][2] += g * (cs * e[a][2] - e[c][2]);
+            S[c][0] += g * (cs * e[c][0] - e[a][0]);
+            S[c][1] += g * (cs * e[c][1] - e[a][1]);
+            S[c][2] += g * (cs * e[c][2] - e[a][2]);
+        }
+    }
+    if constexpr (!ENERGY) {
+        real fj[3] = {(real)0, (real)0, (real)0};
+#pragma unroll
+        for (int a = 0; a < NO; ++a) {
+            const real fx = -S[a][0] * iu[a], fy = -S[a][1] * iu[a], fz = -S[a][2] * iu[a];
+            fj[0] -= fx;
+            fj[1] -= fy;
+            fj[2] -= fz;
+            if (oa[a] >= 0)
+                add3<real, ENERGY>(frc, oa[a], fx, fy, fz);
+        }
+        add3<real, ENERGY>(frc, ga.x, fj[0], fj[1], fj[2]);
+    }
+}
+
 // W: lanes per pass (16 in the register-tile layout, 64 in the wide layout);
 // the host packs the records in passes of W
 template <typename real, bool ENERGY, int W = kRow>
@@ -333,73 +407,13 @@ __device__ __forceinline__ void bonded_terms(const RunDev<real>& d, const real* 
             }
         }
     }
-    // angles: U = 1/2 k (theta - theta0)^2, theta = atan2(|e_a x e_c|, e_a . e_c).
-    // One lane per centre atom j with up to four outer atoms: each bond vector
-    // u_a = x_a - x_j is normalised once (e_a), and the force on outer atom a
-    // of angle (a, j, c) is -k dth (cos theta e_a - e_c) / (|u_a| sin theta);
-    // the centre takes minus the sum.
-    for (int t0 = 0; t0 < d.nag; t0 += W) {
-        const int t = t0 + l16;
-        const int4 ga = d.agrp[2 * t];
-        if (ga.x >= 0) {
-            const int oa[4] = {ga.y, ga.z, ga.w, d.agrp[2 * t + 1].x};
-            const real* par = d.agpar + 12 * t;
-            real pj[3];
-            ld3(pos, ga.x, pj);
-            real e[4][3], iu[4];
-#pragma unroll
-            for (int a = 0; a < 4; ++a) {
-                real pa[3];
-                ld3(pos, oa[a] >= 0 ? oa[a] : ga.x, pa);
-                const real ux = pa[0] - pj[0], uy = pa[1] - pj[1], uz = pa[2] - pj[2];
-                // absent outer atoms (their angles carry k = 0): a unit vector along x
-                iu[a] = oa[a] >= 0 ? rsq_(ux * ux + uy * uy + uz * uz) : (real)1;
-                e[a][0] = oa[a] >= 0 ? ux * iu[a] : (real)1;
-                e[a][1] = uy * iu[a];
-                e[a][2] = uz * iu[a];
-            }
-            real S[4][3];
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-                S[a][0] = S[a][1] = S[a][2] = (real)0;
-#pragma unroll
-            for (int q = 0; q < 6; ++q) {
-                constexpr int A[6] = {0, 0, 0, 1, 1, 2}, C[6] = {1, 2, 3, 2, 3, 3};
-                const int a = A[q], c = C[q];
-                const real k = par[2 * q], th0 = par[2 * q + 1];
-                const real cs = e[a][0] * e[c][0] + e[a][1] * e[c][1] + e[a][2] * e[c][2];
-                const real cx = e[a][1] * e[c][2] - e[a][2] * e[c][1];
-                const real cy = e[a][2] * e[c][0] - e[a][0] * e[c][2];
-                const real cz = e[a][0] * e[c][1] - e[a][1] * e[c][0];
-                const real sn = sqrt_(cx * cx + cy * cy + cz * cz);
-                const real dth = angle_yx(sn, cs) - th0;
-                if constexpr (ENERGY) {
-                    eacc += (double)((real)0.5 * k * dth * dth);
-                } else {
-                    const real g = k * dth * rcp_(sn < (real)1e-8 ? (real)1e-8 : sn);
-                    S[a][0] += g * (cs * e[a][0] - e[c][0]);
-                    S[a][1] += g * (cs * e[a][1] - e[c][1]);
-                    S[a][2] += g * (cs * e[a][2] - e[c][2]);
-                    S[c][0] += g * (cs * e[c][0] - e[a][0]);
-                    S[c][1] += g * (cs * e[c][1] - e[a][1]);
-                    S[c][2] += g * (cs * e[c][2] - e[a][2]);
-                }
-            }
-            if constexpr (!ENERGY) {
-                real fj[3] = {(real)0, (real)0, (real)0};
-#pragma unroll
-                for (int a = 0; a < 4; ++a) {
-                    const real fx = -S[a][0] * iu[a], fy = -S[a][1] * iu[a], fz = -S[a][2] * iu[a];
-                    fj[0] -= fx;
-                    fj[1] -= fy;
-                    fj[2] -= fz;
-                    if (oa[a] >= 0)
-                        add3<real, ENERGY>(frc, oa[a], fx, fy, fz);
-                }
-                add3<real, ENERGY>(frc, ga.x, fj[0], fj[1], fj[2]);
-            }
-        }
-    }
+    // angles: U = 1/2 k (theta - theta0)^2, theta = atan2(|e_a x e_c|, e_a . e_c):
+    // the groups with four outer atoms (six angles), then those with at most
+    // three (three angles)
+    for (int t0 = 0; t0 < d.nag6; t0 += W)
+        angle_group<real, ENERGY, 4>(d, pos, frc, t0 + l16, eacc);
+    for (int t0 = d.nag6; t0 < d.nag; t0 += W)
+        angle_group<real, ENERGY, 3>(d, pos, frc, t0 + l16, eacc);
     // dihedrals: U = k (1 + cos(n phi - delta)) = |kc| + kc cos(n phi), kc = k cos(delta), delta in {0, pi}.
     // One lane per group of torsions around one central bond j-k (up to three
     // outer atoms i on the j side, three l on the k side, every (i, l) one
@@ -417,7 +431,7 @@ __device__ __forceinline__ void bonded_terms(const RunDev<real>& d, const real* 
         if (ga.x >= 0) {
             const int ia[3] = {ga.z, ga.w, gb.x};
             const int la[3] = {gb.y, gb.z, gb.w};
-            const real* par = d.dgpar + 18 * t;
+            const real* par = d.dgpar + 45 * t;
             real pj[3], pk[3];
             ld3(pos, ga.x, pj);
             ld3(pos, ga.y, pk);
@@ -458,27 +472,38 @@ __device__ __forceinline__ void bonded_terms(const RunDev<real>& d, const real* 
                 real El = (real)0;
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
-                    const real kc = par[2 * (3 * a + c)];
-                    const int nmul = (int)par[2 * (3 * a + c) + 1];
+                    const real* tp_ = par + 5 * (3 * a + c);
+                    const real kc = tp_[0];
                     const real inn = rsq_(n1sq[a] * n2sq);
                     const real cphi = (n1[a][0] * n2x + n1[a][1] * n2y + n1[a][2] * n2z) * inn;
-                    // Chebyshev: T_n(c) = cos(n phi), U_{n-1}(c) = sin(n phi) / sin(phi)
-                    real tp = (real)1, tc = cphi, up = (real)0, uc = (real)1;
-                    for (int q = 1; q < nmul; ++q) {
-                        const real tn = (real)2 * cphi * tc - tp;
-                        const real un = (real)2 * cphi * uc - up;
-                        tp = tc;
-                        tc = tn;
-                        up = uc;
-                        uc = un;
-                    }
                     if constexpr (ENERGY) {
+                        // Chebyshev: T_n(c) = cos(n phi)
+                        const int nmul = (int)tp_[1];
+                        real tp = (real)1, tc = cphi;
+                        for (int q = 1; q < nmul; ++q) {
+                            const real tn = (real)2 * cphi * tc - tp;
+                            tp = tc;
+                            tc = tn;
+                        }
                         eacc += (double)(fabs(kc) + kc * tc);
                     } else {
                         // sin phi = |b2| b1.(b2 x b3) / (|n1| |n2|), and b1.(b2 x b3) = n1.b3
                         const real sphi = lb2 * (n1[a][0] * b3x + n1[a][1] * b3y + n1[a][2] * b3z) * inn;
-                        // dU/dphi = -kc n sin(n phi) = -kc n sin(phi) U_{n-1}(cos phi)
-                        const real dU = -kc * (real)nmul * sphi * uc;
+                        // dU/dphi = -kc n sin(n phi) = -kc n sin(phi) U_{n-1}(cos phi), with
+                        // kc n U_{n-1}(c) = c0 + c1 c + c2 c^2 for n <= 3
+                        real poly = fma_(fma_(tp_[4], cphi, tp_[3]), cphi, tp_[2]);
+                        if (d.dih_general) {
+                            // some torsion has n > 3: U_{n-1} by the Chebyshev recurrence
+                            const int nmul = (int)tp_[1];
+                            real up = (real)0, uc = (real)1;
+                            for (int q = 1; q < nmul; ++q) {
+                                const real un = (real)2 * cphi * uc - up;
+                                up = uc;
+                                uc = un;
+                            }
+                            poly = kc * (real)nmul * uc;
+                        }
+                        const real dU = -sphi * poly;
                         Di[a] += dU;
                         El += dU;
                     }

@@ -76,10 +76,12 @@ struct RunDev {
     const real* nb_c;       // [steps][16]      Coulomb coefficient
     const int4* bidx;       // [nb]   (i, j, -, -)
     const real* bpar;       // [nb][2] (k, r0)
-    const int4* agrp;       // [nag][2] angle groups: (j, o0, o1, o2), (o3, -, -, -), -1 = none
+    const int4* agrp;       // [nag][2] angle groups: (j, o0, o1, o2), (o3, -, -, -), -1 = none;
+                            // slots [0, nag6) hold four outer atoms, the rest at most three (o0..o2)
     const real* agpar;      // [nag][6][2] (k, theta0) of the outer pairs (0,1) (0,2) (0,3) (1,2) (1,3) (2,3)
     const int4* dgrp;       // [ng][2] dihedral groups: (j, k, i0, i1), (i2, l0, l1, l2), -1 = none
-    const real* dgpar;      // [ng][9][2] (k cos(delta), n) of (i_a, l_c) at 3 a + c
+    const real* dgpar;      // [ng][9][5] (k cos(delta), n, c0, c1, c2) of (i_a, l_c) at 3 a + c, with
+                            // k cos(delta) n U_{n-1}(c) = c0 + c1 c + c2 c^2 when n <= 3
     const double* mass;     // [npad] (0 for padding)
     const double* x_init;   // [n][3]
     const double* sched;    // device temperature schedule [kMaxSched]
@@ -87,6 +89,8 @@ struct RunDev {
     double* dbg;            // force-debug scratch [PAMD_FORCE_CHUNK][npad][4]
     void* obs;              // device pamd_obs
     int32_t n, npad, nslot, nb, nag, ng;
+    int32_t nag6;           // angle slots of the six-angle body
+    int32_t dih_general;    // some torsion has n > 3: its derivative by the Chebyshev recurrence
     int64_t R_target, R_cap;
     double kB, dt, T0, V_target, T_final;
     uint32_t p24;           // Andersen threshold: collide iff (w >> 8) < p24

@@ -92,7 +92,8 @@ struct HostTables {
     std::vector<uint64_t> stepmask;      // wide layout: [t][s] rotation steps that need the masks
     std::vector<double> ab, c;           // [steps][16][2], [steps][16]
     std::vector<int32_t> bidx, aidx, didx;  // int4 records (dihedrals: two per group slot)
-    std::vector<double> bpar, apar, dpar;   // dihedrals: 18 per group slot
+    std::vector<double> bpar, apar, dpar;   // dihedrals: 45 per group slot
+    int n6 = 0;                          // angle slots of the six-angle body
     std::vector<double> mass, x_init;
     double mtot = 0;
 };
@@ -541,20 +542,17 @@ int pack_dihedral_groups(const pamd_system& s, int W, std::vector<int32_t>* rec,
     const int slots = (int)best.size() * W;
     if (rec && par) {
         rec->assign((size_t)slots * 8, -1);
-        par->assign((size_t)slots * 18, 0.0);
+        par->assign((size_t)slots * 45, 0.0);
         for (int q = 0; q < slots; ++q)
-            (*par)[(size_t)q * 18 + 1] = 1.0;
+            for (int u = 0; u < 9; ++u)
+                (*par)[(size_t)q * 45 + 5 * u + 1] = 1.0;
         for (size_t b = 0; b < best.size(); ++b)
             for (size_t q = 0; q < best[b].size(); ++q) {
                 const Placed& P = best[b][q];
                 const DihGroup& G = g[P.grp];
                 const size_t sl = b * W + q;
                 int32_t* r = rec->data() + sl * 8;
-                double* pp = par->data() + sl * 18;
-                for (int u = 0; u < 9; ++u) {
-                    pp[2 * u] = 0.0;
-                    pp[2 * u + 1] = 1.0;
-                }
+                double* pp = par->data() + sl * 45;
                 r[0] = P.flip ? G.k : G.j;
                 r[1] = P.flip ? G.j : G.k;
                 const int ni = P.flip ? G.nl : G.ni, nl = P.flip ? G.ni : G.nl;
@@ -568,8 +566,20 @@ int pack_dihedral_groups(const pamd_system& s, int W, std::vector<int32_t>* rec,
                         if (t < 0)
                             continue;
                         const int u = 3 * P.ri[a] + P.rl[c];
-                        pp[2 * u] = s.dih_k[t] * (cos(s.dih_delta[t]) > 0 ? 1.0 : -1.0);   // k cos(delta)
-                        pp[2 * u + 1] = (double)s.dih_n[t];
+                        const double kc = s.dih_k[t] * (cos(s.dih_delta[t]) > 0 ? 1.0 : -1.0);   // k cos(delta)
+                        const int nm = s.dih_n[t];
+                        pp[5 * u] = kc;
+                        pp[5 * u + 1] = (double)nm;
+                        // kc n U_{n-1}(c) = c0 + c1 c + c2 c^2 for n <= 3 (U_0 = 1, U_1 = 2c,
+                        // U_2 = 4c^2 - 1); n > 3 takes the Chebyshev recurrence in the kernel
+                        if (nm == 1) {
+                            pp[5 * u + 2] = kc;
+                        } else if (nm == 2) {
+                            pp[5 * u + 3] = 4.0 * kc;
+                        } else if (nm == 3) {
+                            pp[5 * u + 2] = -3.0 * kc;
+                            pp[5 * u + 4] = 12.0 * kc;
+                        }
                     }
             }
     }
@@ -643,7 +653,7 @@ static std::vector<AngGroup> angle_groups(const pamd_system& s)
 }
 
 static std::vector<std::vector<std::pair<int, std::array<int, 4>>>> pack_angle_passes(
-    const std::vector<AngGroup>& g, const std::vector<int>& order, int W)
+    const std::vector<AngGroup>& g, const std::vector<int>& order, int W, int nroles)
 {
     constexpr int kWords = (PAMD_MAX_ATOMS + 63) / 64;
     struct Used {
@@ -663,7 +673,7 @@ static std::vector<std::vector<std::pair<int, std::array<int, 4>>>> pack_angle_p
             do {
                 bool ok = true;
                 for (int a = 0; a < G.no && ok; ++a)
-                    ok = !used[b].has(1 + perm[a], G.o[a]);
+                    ok = perm[a] < nroles && !used[b].has(1 + perm[a], G.o[a]);
                 if (ok) {
                     used[b].set(0, G.j);
                     for (int a = 0; a < G.no; ++a)
@@ -686,33 +696,53 @@ static std::vector<std::vector<std::pair<int, std::array<int, 4>>>> pack_angle_p
     return passes;
 }
 
-int pack_angle_groups(const pamd_system& s, int W, std::vector<int32_t>* rec, std::vector<double>* par)
+// Angle groups packed in two classes: groups with four outer atoms (six
+// angles) first, then groups with at most three (three angles, outer roles
+// 0..2), so the kernel runs the cheaper three-angle body on the second
+// class.  *n6 (optional) = slots of the first class (a multiple of W).
+int pack_angle_groups(const pamd_system& s, int W, std::vector<int32_t>* rec, std::vector<double>* par,
+                      int* n6 = nullptr)
 {
     if (s.n_angles <= 0) {
         if (rec)
             rec->clear();
         if (par)
             par->clear();
+        if (n6)
+            *n6 = 0;
         return 0;
     }
     const std::vector<AngGroup> g = angle_groups(s);
-    const int ng = (int)g.size();
-    std::vector<int> order(ng);
-    for (int q = 0; q < ng; ++q)
-        order[q] = q;
-    auto best = pack_angle_passes(g, order, W);
-    uint64_t st = 0xA0761D6478BD642Full ^ (uint64_t)ng;
-    for (int trial = 0; trial < 63; ++trial) {
-        for (int i = ng - 1; i > 0; --i) {
-            st ^= st << 13;
-            st ^= st >> 7;
-            st ^= st << 17;
-            std::swap(order[i], order[(int)(st % (uint64_t)(i + 1))]);
+    std::vector<std::vector<std::pair<int, std::array<int, 4>>>> best;
+    size_t passes6 = 0;
+    for (int cls = 0; cls < 2; ++cls) {
+        std::vector<int> order;
+        for (int q = 0; q < (int)g.size(); ++q)
+            if ((g[q].no == 4) == (cls == 0))
+                order.push_back(q);
+        if (order.empty())
+            continue;
+        const int nroles = cls == 0 ? 4 : 3;
+        auto cbest = pack_angle_passes(g, order, W, nroles);
+        uint64_t st = 0xA0761D6478BD642Full ^ (uint64_t)(order.size() + 977 * cls);
+        for (int trial = 0; trial < 63; ++trial) {
+            for (int i = (int)order.size() - 1; i > 0; --i) {
+                st ^= st << 13;
+                st ^= st >> 7;
+                st ^= st << 17;
+                std::swap(order[i], order[(int)(st % (uint64_t)(i + 1))]);
+            }
+            auto p = pack_angle_passes(g, order, W, nroles);
+            if (p.size() < cbest.size())
+                cbest = std::move(p);
         }
-        auto p = pack_angle_passes(g, order, W);
-        if (p.size() < best.size())
-            best = std::move(p);
+        if (cls == 0)
+            passes6 = cbest.size();
+        for (auto& pass : cbest)
+            best.push_back(std::move(pass));
     }
+    if (n6)
+        *n6 = (int)passes6 * W;
     const int slots = (int)best.size() * W;
     if (rec && par) {
         rec->assign((size_t)slots * 8, -1);
@@ -824,7 +854,7 @@ void build_tables(const pamd_system& s, HostTables& t, int wide)
             }
     }
     pack_terms(s.n_bonds, 2, s.bond_idx, s.bond_k, s.bond_r0, t.bidx, t.bpar, W);
-    pack_angle_groups(s, W, &t.aidx, &t.apar);
+    pack_angle_groups(s, W, &t.aidx, &t.apar, &t.n6);
     pack_dihedral_groups(s, W, &t.didx, &t.dpar);
     t.mass.assign(t.npad, 0.0);
     t.mtot = 0;
@@ -868,14 +898,15 @@ void carve(Carver& st, Carver& wk, const pamd_system& s, const pamd_params& p, i
     std::vector<double> zeros(std::max({s.n_bonds, s.n_angles, s.n_dihedrals, 1}), 0.0);
     pack_terms(s.n_bonds, 2, s.bond_idx, zeros.data(), zeros.data(), rec, par, W);
     const int nb_slots = (int)(rec.size() / 4);
-    const int na_slots = std::max(pack_angle_groups(s, W, nullptr, nullptr), 1);
+    int na6 = 0;
+    const int na_slots = std::max(pack_angle_groups(s, W, nullptr, nullptr, &na6), 1);
     const int nd_slots = std::max(pack_dihedral_groups(s, W, nullptr, nullptr), 1);
     d.bidx = wk.take<int4>(nb_slots);
     d.bpar = wk.take<real>((size_t)nb_slots * 2);
     d.agrp = wk.take<int4>((size_t)na_slots * 2);
     d.agpar = wk.take<real>((size_t)na_slots * 12);
     d.dgrp = wk.take<int4>((size_t)nd_slots * 2);
-    d.dgpar = wk.take<real>((size_t)nd_slots * 18);
+    d.dgpar = wk.take<real>((size_t)nd_slots * 45);
     d.mass = wk.take<double>(npad);
     d.x_init = wk.take<double>((size_t)3 * n);
     d.sched = wk.take<double>(kMaxSched);
@@ -888,6 +919,11 @@ void carve(Carver& st, Carver& wk, const pamd_system& s, const pamd_params& p, i
     d.nslot = nslot;
     d.nb = s.n_bonds > 0 ? nb_slots : 0;
     d.nag = s.n_angles > 0 ? na_slots : 0;
+    d.nag6 = s.n_angles > 0 ? na6 : 0;
+    d.dih_general = 0;
+    for (int t = 0; t < s.n_dihedrals; ++t)
+        if (s.dih_n[t] > 3)
+            d.dih_general = 1;
     d.ng = s.n_dihedrals > 0 ? nd_slots : 0;
     d.R_target = p.R_target;
     d.R_cap = Rc;
