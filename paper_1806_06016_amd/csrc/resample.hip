@@ -23,7 +23,7 @@
 // sequence of such passes (a probe at the largest step, then Newton
 // iterations that turn into no-ops once converged), so it replays from a HIP
 // graph.  The gather is HBM bound: one wavefront per destination slab, 16-byte
-// accesses.
+// streaming accesses.
 //
 // Built with PAMD_BOUNDS_CHECK (the checked library variant), the scan and the
 // gather verify every destination offset and source index and raise
@@ -39,7 +39,7 @@ namespace pamd {
 constexpr int kRB = 256;             // threads per block of the multi-block passes
 constexpr int kMaxPassBlocks = 256;  // blocks of a pass over the energies (<= kRB)
 constexpr int kCdfT = 16;            // consecutive weights one thread sums (multinomial running sums)
-constexpr int kWeightPasses = 10;    // adaptive step: probe + Newton passes launched per resampling
+constexpr int kWeightPasses = 6;     // adaptive step: Newton passes launched per resampling (typically 3-5 work)
 constexpr int kMaxNewton = 64;       // Newton / bisection iterations before the step is taken as found
 
 __host__ __device__ inline int pass_blocks(int64_t R_cap)
@@ -54,7 +54,7 @@ __host__ __device__ inline int64_t count_blocks(int64_t R_cap) { return (R_cap +
 size_t part_doubles(int64_t R_cap)
 {
     const int64_t c = cdf_blocks(R_cap);
-    return (size_t)(c > 4 * kMaxPassBlocks ? c : 4 * kMaxPassBlocks);
+    return (size_t)(c > 8 * kMaxPassBlocks ? c : 8 * kMaxPassBlocks);
 }
 size_t cpart_count(int64_t R_cap) { return (size_t)count_blocks(R_cap); }
 
@@ -204,87 +204,6 @@ __global__ void k_init(RunDev<real> d)
 // --------------------------------------------------------------------------
 // PAMD step 2a: minimum, next temperature, normaliser
 // --------------------------------------------------------------------------
-// pass 0: min E, non-finite check and the variance of E; the last block fixes
-// the next temperature when it is given (explicit or from the device
-// schedule) or sets up the adaptive search
-template <typename real>
-__global__ __launch_bounds__(kRB) void k_w_stats(RunDev<real> d, double T_req)
-{
-    __shared__ double sh[4 * 3];
-    __shared__ int sflag;
-    RunCtl* c = d.ctl;
-    if (c->error)
-        return;
-    const int64_t R = c->R_cur;
-    const double* E = d.epot[c->cur];
-    const double e0 = E[0];   // shift against cancellation in the variance
-    double mn = INFINITY;
-    double v[3] = {0.0, 0.0, 0.0};   // sum (E - E_0), sum (E - E_0)^2, non-finite count
-    for (int64_t j = (int64_t)blockIdx.x * kRB + threadIdx.x; j < R; j += (int64_t)gridDim.x * kRB) {
-        const double e = E[j];
-        if (!isfinite(e))
-            v[2] += 1.0;
-        mn = fmin(mn, e);
-        v[0] += e - e0;
-        v[1] += (e - e0) * (e - e0);
-    }
-    mn = block_min(mn, sh);
-    block_sums<3>(v, sh);
-    double* part = d.part + 4 * (size_t)blockIdx.x;
-    if (threadIdx.x == 0) {
-        part[0] = mn;
-        part[1] = v[0];
-        part[2] = v[1];
-        part[3] = v[2];
-    }
-    if (!last_block(&c->ticket, &sflag))
-        return;
-    // combine the block partials (fixed order)
-    const int t = threadIdx.x;
-    mn = INFINITY;
-    v[0] = v[1] = v[2] = 0.0;
-    if (t < (int)gridDim.x) {
-        const double* q = d.part + 4 * (size_t)t;
-        mn = q[0];
-        v[0] = q[1];
-        v[1] = q[2];
-        v[2] = q[3];
-    }
-    mn = block_min(mn, sh);
-    block_sums<3>(v, sh);
-    if (t != 0)
-        return;
-    if (v[2] > 0.0) {
-        raise_error(c, PAMD_ERR_NONFINITE);
-        return;
-    }
-    const double Rd = (double)R;
-    const double mean = v[0] / Rd;
-    c->m = mn;
-    c->w_var = v[1] / Rd - mean * mean;
-    c->T_req = T_req;
-    const double T = c->T_cur, kB = d.kB;
-    if (T_req > 0.0) {
-        c->T_next = T_req;
-        c->w_phase = 2;
-    } else if (T_req < 0.0) {
-        // device schedule: the next entry, or stay at the last one
-        const int64_t nx = (int64_t)c->temp_index + 1;
-        c->T_next = (d.sched && nx < d.n_sched) ? d.sched[nx] : T;
-        c->w_phase = 2;
-    } else {
-        const double dmax = 1.0 / (kB * d.T_final) - 1.0 / (kB * T);
-        if (!(dmax > 0.0)) {
-            c->T_next = T;
-            c->w_phase = 2;
-        } else {
-            c->w_b = dmax;
-            c->w_phase = 0;
-            c->w_iter = 0;
-        }
-    }
-}
-
 // One update of the adaptive step from the weight moments at dbeta = c->w_b
 // (S = sum w, S1 = sum w e, S2 = sum w^2, S21 = sum w^2 e, w = exp(-b e),
 // e = E - m): phase 0 tests the largest step (to T_final) and starts Newton
@@ -333,6 +252,107 @@ __device__ void newton_update(const RunDev<real>& d, RunCtl* c, int64_t R, doubl
     if (done || c->w_iter >= kMaxNewton) {
         c->T_next = 1.0 / (kB * (bn + 1.0 / (kB * T)));
         c->w_phase = 2;
+    }
+}
+
+// pass 0: min E, non-finite check and the variance of E; for the adaptive
+// choice also the weight sums at the largest step dmax (to T_final), each
+// block relative to its own minimum and merged log-sum-exp style.  The last
+// block fixes the next temperature when it is given (explicit or from the
+// device schedule) or when the largest step is within the target variance,
+// and starts the Newton iterations otherwise.
+template <typename real>
+__global__ __launch_bounds__(kRB) void k_w_stats(RunDev<real> d, double T_req)
+{
+    __shared__ double sh[4 * 3];
+    __shared__ int sflag;
+    RunCtl* c = d.ctl;
+    if (c->error)
+        return;
+    const int64_t R = c->R_cur;
+    const double* E = d.epot[c->cur];
+    const double kB = d.kB, T = c->T_cur;
+    const double dmax = 1.0 / (kB * d.T_final) - 1.0 / (kB * T);
+    const bool probe = T_req == 0.0 && dmax > 0.0;
+    const double e0 = E[0];   // shift against cancellation in the variance
+    double mn = INFINITY;
+    double v[3] = {0.0, 0.0, 0.0};   // sum (E - E_0), sum (E - E_0)^2, non-finite count
+    const int64_t j0 = (int64_t)blockIdx.x * kRB + threadIdx.x, stride = (int64_t)gridDim.x * kRB;
+    for (int64_t j = j0; j < R; j += stride) {
+        const double e = E[j];
+        if (!isfinite(e))
+            v[2] += 1.0;
+        mn = fmin(mn, e);
+        v[0] += e - e0;
+        v[1] += (e - e0) * (e - e0);
+    }
+    mn = block_min(mn, sh);
+    block_sums<3>(v, sh);
+    double p[2] = {0.0, 0.0};   // sum w, sum w^2 at dmax, w relative to this block's minimum
+    if (probe && isfinite(mn)) {
+        for (int64_t j = j0; j < R; j += stride) {
+            const double w = exp(-dmax * (E[j] - mn));
+            p[0] += w;
+            p[1] += w * w;
+        }
+        block_sums<2>(p, sh);
+    }
+    double* part = d.part + 8 * (size_t)blockIdx.x;
+    if (threadIdx.x == 0) {
+        part[0] = mn;
+        part[1] = v[0];
+        part[2] = v[1];
+        part[3] = v[2];
+        part[4] = p[0];
+        part[5] = p[1];
+    }
+    if (!last_block(&c->ticket, &sflag))
+        return;
+    // combine the block partials (fixed order)
+    const int t = threadIdx.x;
+    const bool have = t < (int)gridDim.x;
+    const double* q = d.part + 8 * (size_t)t;
+    double mb = have ? q[0] : INFINITY;
+    mn = block_min(mb, sh);
+    v[0] = have ? q[1] : 0.0;
+    v[1] = have ? q[2] : 0.0;
+    v[2] = have ? q[3] : 0.0;
+    block_sums<3>(v, sh);
+    if (v[2] > 0.0) {
+        if (t == 0)
+            raise_error(c, PAMD_ERR_NONFINITE);
+        return;
+    }
+    if (probe) {
+        // a block without elements has mb = inf and sums 0
+        const double f = have && isfinite(mb) ? exp(-dmax * (mb - mn)) : 0.0;
+        p[0] = have ? q[4] * f : 0.0;
+        p[1] = have ? q[5] * f * f : 0.0;
+        block_sums<2>(p, sh);
+    }
+    if (t != 0)
+        return;
+    const double Rd = (double)R;
+    const double mean = v[0] / Rd;
+    c->m = mn;
+    c->w_var = v[1] / Rd - mean * mean;
+    c->T_req = T_req;
+    if (T_req > 0.0) {
+        c->T_next = T_req;
+        c->w_phase = 2;
+    } else if (T_req < 0.0) {
+        // device schedule: the next entry, or stay at the last one
+        const int64_t nx = (int64_t)c->temp_index + 1;
+        c->T_next = (d.sched && nx < d.n_sched) ? d.sched[nx] : T;
+        c->w_phase = 2;
+    } else if (!probe) {
+        c->T_next = T;
+        c->w_phase = 2;
+    } else {
+        c->w_b = dmax;
+        c->w_phase = 0;
+        c->w_iter = 0;
+        newton_update(d, c, R, p[0], 0.0, p[1], 0.0);   // phase 0 reads V(dmax) from S and S2 only
     }
 }
 
@@ -692,6 +712,10 @@ struct Vec16<double> {
     }
 };
 
+// 16-byte access of the gather: a native vector type for the streaming
+// (non-temporal) loads and stores, each slab being read and written once
+typedef uint32_t Nt16 __attribute__((ext_vector_type(4)));
+
 template <typename real, int K>
 __global__ __launch_bounds__(256) void k_gather(RunDev<real> d, double mtot)
 {
@@ -723,7 +747,7 @@ __global__ __launch_bounds__(256) void k_gather(RunDev<real> d, double mtot)
     for (int k = 0; k < K; ++k) {
         const int q = lane + 64 * k;
         if (q < nv)
-            v[k] = src[q];
+            v[k] = __builtin_bit_cast(VT, __builtin_nontemporal_load(reinterpret_cast<const Nt16*>(src) + q));
     }
     // mass-weighted centre of the source positions (FP64)
     double cm[3] = {0.0, 0.0, 0.0};
@@ -760,7 +784,7 @@ __global__ __launch_bounds__(256) void k_gather(RunDev<real> d, double mtot)
                     Vec16<real>::set(o, e, comp < 3 ? x - cx[comp] : x * vs);
                 }
             }
-            dst[q] = o;
+            __builtin_nontemporal_store(__builtin_bit_cast(Nt16, o), reinterpret_cast<Nt16*>(dst) + q);
         }
     }
     if (lane == 0) {
