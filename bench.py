@@ -58,10 +58,43 @@ def measured_traffic(name: str = "k_md_traffic.txt"):
         return None
 
 
+def _oracle_sample(R: int, seconds_target: float):
+    """R replicas of the 75-atom peptide at 700 K through the FP64 oracle for
+    about seconds_target: (replica-steps/s, steps, seconds)."""
+    import numpy as np
+    from oracle import oracle as O
+    from pamd_inputs import systems as S
+    sysd = S.c2_system()
+    osys = O.OracleSystem(sysd)
+    x = np.ascontiguousarray(np.broadcast_to(sysd.x_init, (R, sysd.n_atoms, 3)).astype(np.float64))
+    v = O.init_velocities(osys, R, 700.0, seed=1806)
+    t0 = time.perf_counter()
+    O.md_steps(osys, x, v, 20, 700.0, 0.001, 1.0, 1806, 0)
+    dt1 = time.perf_counter() - t0
+    steps = max(20, int(seconds_target / max(dt1, 1e-6) * 20))
+    t0 = time.perf_counter()
+    O.md_steps(osys, x, v, steps, 700.0, 0.001, 1.0, 1806, 20)
+    el = time.perf_counter() - t0
+    return R * steps / el, steps, el
+
+
+def cpu_baseline_one_core(seconds_target: float = 8.0):
+    """The same oracle sample on one core: a child process with OpenMP held
+    to one thread."""
+    import subprocess
+    code = ("import json, sys; sys.path.insert(0, %r); import bench; "
+            "r, n, el = bench._oracle_sample(16, %r); print(json.dumps([r, n, el]))") % (ROOT, seconds_target)
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=300)
+    r, n, el = json.loads(out.stdout.strip().splitlines()[-1])
+    return dict(value=r, cores=1, sample=f"16 replicas x {n} steps of the 75-atom peptide at 700 K (FP64 oracle, "
+                                         f"one thread, {el:.1f} s)")
+
+
 def cpu_baseline(sysd, seconds_target: float = 15.0):
     """The FP64 oracle (plain C, OpenMP over replicas) on the host cores, on a
     bounded sample of the same workload: R_s replicas x theta_s steps of the
-    same peptide at 700 K.  Returns replica-steps/s."""
+    same peptide at 700 K, and the same on one core.  Returns replica-steps/s."""
     import numpy as np
     from oracle import oracle as O
     osys = O.OracleSystem(sysd)
@@ -79,7 +112,7 @@ def cpu_baseline(sysd, seconds_target: float = 15.0):
     el = time.perf_counter() - t0
     return dict(value=R * steps / el, unit="replica-MD steps/s", cores=threads, kind="oracle",
                 sample=f"{R} replicas x {steps} steps of the 75-atom peptide at 700 K (FP64 oracle, "
-                       f"{el:.1f} s)")
+                       f"{el:.1f} s)", one_core=cpu_baseline_one_core())
 
 
 def cpu_baseline_batched(systems, R_each: int, seconds_target: float = 15.0):

@@ -14,7 +14,7 @@ through the C ABI (argument marshalling and bookkeeping only here).
    replicas of |slope| of a least-squares line through E_tot(t) per atom
    (kJ/mol/ps/atom) and the RMS of E_tot(t) - E_tot(0), and throughput
    (replica time steps per second, simulated time per second, R = 1e5) for
-   plain velocity Verlet at dt = 0.5, 1, 1.5 and 2 fs, r-RESPA with the
+   plain velocity Verlet at dt = 0.5, 1, 1.5, 2 and 2.5 fs, r-RESPA with the
    trained surrogate (inner 1 fs, outer 2, 3 and 4 fs) and r-RESPA with a
    zero surrogate (the whole nonbonded force in the outer impulse: the method
    without the network).
@@ -167,6 +167,7 @@ def nve_run(sysd, x0, v0, dt: float, nn=None, M: int = 1, window_ps: float = 10.
 def throughput(sysd, x0, v0, dt: float, nn=None, M: int = 1, R: int = 100000, steps: int = 400) -> Dict:
     """Replica time steps per second at population size R (inputs resident)."""
     import torch
+    steps = max(M, steps // max(M, 1) * max(M, 1))   # whole outer steps
     rep = int(math.ceil(R / x0.shape[0]))
     x = np.concatenate([x0] * rep)[:R]
     v = np.concatenate([v0] * rep)[:R]
@@ -224,7 +225,8 @@ def equal_drift(plain: Dict[float, Dict], case: Dict) -> Dict:
     steps_per_s = float(np.mean([p[1]["throughput"]["replica_steps_per_s"] for p in pts]))
     plain_rate = steps_per_s * dt_eq * 1e-3      # replica-ps/s
     return dict(dt_equal_fs=dt_eq, drift_exponent=float(b), plain_replica_ps_per_s=plain_rate,
-                speedup=case["throughput"]["replica_ps_per_s"] / plain_rate)
+                speedup=case["throughput"]["replica_ps_per_s"] / plain_rate,
+                extrapolated=bool(dt_eq > max(p[0] for p in pts) or dt_eq < min(p[0] for p in pts)))
 
 
 def kernel_timing(R: int, reps: int = 5) -> Dict:
@@ -297,7 +299,7 @@ def main(argv=None):
     R0 = 256
     x0, v0 = st["x"][:R0], st["v"][:R0]
     zero = B.PamdNN(sysd, sysd.atype)
-    cases = [(f"vv_{dt}fs", dt * 1e-3, None, 1) for dt in (0.5, 1.0, 1.5, 2.0)]
+    cases = [(f"vv_{dt}fs", dt * 1e-3, None, 1) for dt in (0.5, 1.0, 1.5, 2.0, 2.5)]
     cases += [(f"respa_nn_{M}fs", 0.001, nn, M) for M in (2, 3, 4)]
     cases += [(f"respa_zero_{M}fs", 0.001, zero, M) for M in (2, 3, 4)]
     res = {}

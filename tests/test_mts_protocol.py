@@ -28,6 +28,8 @@ def test_equal_drift_recovers_the_time_step_of_a_power_law():
     assert e["drift_exponent"] == pytest.approx(2.0, rel=1e-9)
     assert e["plain_replica_ps_per_s"] == pytest.approx(4e8 * 1.3e-3, rel=1e-9)
     assert e["speedup"] == pytest.approx(1e4 / (4e8 * 1.3e-3), rel=1e-9)
+    assert not e["extrapolated"]
+    assert mts.equal_drift(plain, _case(c * 3.0 ** 2, ps_per_s=1.0))["extrapolated"]
 
 
 def test_equal_drift_without_a_finite_case_drift():
