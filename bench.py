@@ -174,13 +174,14 @@ def batched(args):
     # 700 K for the 120-250-atom molecules (oppositely charged hydrogens fall
     # into the steep Lennard-Jones wall); at 0.5 fs 2048-replica oracle runs stay finite
     tuned = None
-    layout, wide_waves = "auto", args.waves
+    layout, wide_waves, tile_waves = "auto", args.waves, 0
     if args.waves == 0 and not args.no_autotune:
         from paper_1806_06016_amd.autotune import autotune_batched
         tuned = autotune_batched(systems, R)
         layout, wide_waves = tuned["layout"], tuned["wide_waves_per_block"]
+        tile_waves = tuned.get("waves_per_block", 0)
     p = Pamd(systems, R_target=R, T0=700.0, dt=0.0005, nu=1.0, seed=1806, precision=PAMD_FP32,
-             layout=layout, wide_waves=wide_waves)
+             layout=layout, wide_waves=wide_waves, waves_per_block=tile_waves)
     for r in range(len(systems)):
         p.set_schedule(r, sched)
     info = dict(p.launch_info(), runs=[dict(atoms=s.n_atoms, **p.run_launch(r)) for r, s in enumerate(systems)],
@@ -383,7 +384,9 @@ def main():
         "launch": dict(info, graph=use_graph, autotune=tuned),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_VALU_TFLOPS,
-                     "traffic": measured_traffic() if R == 100000 and args.theta == 1000 else None,
+                     # counters of the Andersen-bath kernel at the default workload only
+                     "traffic": measured_traffic() if R == 100000 and args.theta == 1000
+                     and args.thermostat == "andersen" else None,
                      "flops_per_replica_step": flops_rs},
     }
     p.close()

@@ -108,6 +108,9 @@ def autotune(sysd, precision: int = PAMD_FP32, R_probe: int = 65536, theta_probe
     return dict(entry, cached=False)
 
 
+TILE_SMALL_CANDIDATES = (8, 4)   # register-tile waves per workgroup tried for small populations
+
+
 def autotune_batched(systems: Sequence, R_each: int, precision: int = PAMD_FP32, theta_probe: int = 100,
                      wide_candidates: Sequence[int] = WIDE_CANDIDATES, T0: float = 700.0, dt: float = 0.0005,
                      use_cache: bool = True, cache_path: Optional[str] = None,
@@ -117,14 +120,19 @@ def autotune_batched(systems: Sequence, R_each: int, precision: int = PAMD_FP32,
     Candidates: every run in the batched wide launch, or the runs that fit
     the register tile (at most 80 atoms) in register-tile launches and the
     rest in the wide launch; in both cases the wide launch with 4, 3, 2 or 1
-    waves per workgroup.  Each candidate times the whole context's MD step
+    waves per workgroup (register-tile launches at 16 waves per workgroup).
+    When the register-tile split wins, its launches are then also timed at
+    8 and 4 waves per workgroup: a small population (R_each / 4 work items
+    against 16 waves on every CU) otherwise lands on the few CUs whose waves
+    claim the items first.  Each candidate times the whole context's MD step
     at the run's population sizes.  Returns {"layout": [per run "wide" /
-    "tile"], "wide_waves_per_block": w, "timings": {candidate: replica-steps/s},
-    "cached": bool}."""
+    "tile"], "wide_waves_per_block": w, "waves_per_block": register-tile
+    waves (0: the library's default), "timings": {candidate:
+    replica-steps/s}, "cached": bool}."""
     import torch
     systems = list(systems)
     path = cache_path or _cache_path()
-    key = "batched-" + _key(systems, precision, R_each, thermostat)
+    key = "batched-tw-" + _key(systems, precision, R_each, thermostat)
     cache = _load(path) if use_cache else {}
     if key in cache:
         return dict(cache[key], cached=True)
@@ -133,19 +141,27 @@ def autotune_batched(systems: Sequence, R_each: int, precision: int = PAMD_FP32,
     if any(small) and not all(small):
         layouts["tile_small"] = ["tile" if sm else "wide" for sm in small]
     timings, shapes = {}, {}
+
+    def probe(cand, lay, w, tw):
+        p = Pamd(systems, R_target=R_each, T0=T0, dt=dt, nu=1.0, seed=1, precision=precision,
+                 thermostat=thermostat, layout=lay, wide_waves=w, waves_per_block=tw)
+        ms = _time_md(p, theta_probe)
+        timings[cand] = R_each * len(systems) * theta_probe / (ms / 1e3)
+        shapes[cand] = (lay, w, tw)
+        p.close()
+
     for lname, lay in layouts.items():
         for w in wide_candidates:
-            p = Pamd(systems, R_target=R_each, T0=T0, dt=dt, nu=1.0, seed=1, precision=precision,
-                     thermostat=thermostat, layout=lay, wide_waves=w)
-            ms = _time_md(p, theta_probe)
-            cand = f"{lname}/w{w}"
-            timings[cand] = R_each * len(systems) * theta_probe / (ms / 1e3)
-            shapes[cand] = (lay, w)
-            p.close()
-    torch.cuda.synchronize()
+            probe(f"{lname}/w{w}", lay, w, 0)
     choice = max(timings, key=timings.get)
-    entry = {"layout": shapes[choice][0], "wide_waves_per_block": int(shapes[choice][1]), "choice": choice,
-             "timings": timings}
+    if shapes[choice][0] != layouts["wide"]:
+        lay, w = shapes[choice][0], shapes[choice][1]
+        for tw in TILE_SMALL_CANDIDATES:
+            probe(f"tile_small/w{w}/t{tw}", lay, w, tw)
+        choice = max(timings, key=timings.get)
+    torch.cuda.synchronize()
+    entry = {"layout": shapes[choice][0], "wide_waves_per_block": int(shapes[choice][1]),
+             "waves_per_block": int(shapes[choice][2]), "choice": choice, "timings": timings}
     if use_cache:
         cache[key] = entry
         _store(path, cache)

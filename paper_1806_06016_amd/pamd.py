@@ -515,13 +515,15 @@ class PamdNN:
     """The learned surrogate of one molecule (pamd_nn_* calls).  Configuration
     arrays are CUDA float32 tensors [n_conf, n, 3]."""
 
-    def __init__(self, sysd, atom_type: Sequence[int], max_conf: int = 256, stream=None):
+    def __init__(self, sysd, atom_type: Sequence[int], max_conf: int = 256, stream=None,
+                 library: Optional[str] = None):
         """max_conf: the largest batch of forces / loss_grad / train_step; the
         parameters and workspace are one torch allocation of the size the
-        library asks for."""
+        library asks for.  library: another build of libpamd (default: the
+        in-tree one)."""
         import torch
         self.torch = torch
-        self.lib = load_library()
+        self.lib = load_library(library or LIB_PATH)
         if not torch.cuda.is_available():
             raise RuntimeError("the PAMD library needs a ROCm GPU")
         self._keep: list = []
