@@ -337,12 +337,34 @@ pamd_status pamd_wham_average(int32_t n_temps, const double* beta, const int64_t
                               const double* lnZ, double beta_q, double* E_mean, double* E2_mean);
 
 /* Roofline calibration (no context): runs a kernel of independent FP32 FMAs
- * (v_fma_f32; every kernel of this library is built without packed FP32
- * instructions) over the whole GPU three times, about 18 ms each, and returns in
- * *tflops the best rate in TFLOP/s (FMA = 2 flop): the ceiling of an FP32
+ * (v_fma_f32 with VGPR operands only; every kernel of this library is built
+ * without packed FP32 instructions) over the whole GPU three times and returns
+ * in *tflops the best rate in TFLOP/s (FMA = 2 flop): the ceiling of an FP32
  * VALU-bound kernel of this library.  d_sink: device pointer to one float the
  * kernel may write.  Synchronises `stream`. */
 pamd_status pamd_fp32_fma_rate(float* d_sink, double* tflops, void* stream);
+
+/* Issue cost of single VALU instruction forms (no context; measurement
+ * infrastructure behind the roofline reading of the MD kernels): for each form
+ * a kernel of eight independent chains per lane of that one instruction,
+ * `waves_per_simd` (1, 2, 4 or 8) waves on every SIMD.  Returns in
+ * cycles_per_instr[PAMD_VALU_FORMS] the shader cycles per wave64 instruction
+ * per SIMD (issue time; lower is faster) and in *clock_ghz the shader clock
+ * measured from one wave alone on its SIMD (s_memtime over the launch time).
+ * d_sink: device buffer of at least 16 bytes the kernels may write.
+ * Synchronises `stream`; about 10 ms. */
+enum {
+    PAMD_VALU_FMA_VGPR = 0,   /* v_fma_f32, all operands VGPRs */
+    PAMD_VALU_FMA_SGPR = 1,   /* v_fma_f32 with one SGPR operand */
+    PAMD_VALU_FMAC_VOP2 = 2,  /* v_fmac_f32_e32 */
+    PAMD_VALU_MUL_VOP2 = 3,   /* v_mul_f32_e32 */
+    PAMD_VALU_ADD_DPP = 4,    /* v_add_f32 with a DPP row-rotated source */
+    PAMD_VALU_MOV_DPP = 5,    /* v_mov_b32 with DPP row rotation */
+    PAMD_VALU_RCP = 6,        /* v_rcp_f32 (transcendental unit) */
+    PAMD_VALU_FORMS = 7
+};
+pamd_status pamd_valu_issue_rates(float* d_sink, int32_t waves_per_simd, double* cycles_per_instr,
+                                  double* clock_ghz, void* stream);
 
 /* ---- learned multiple-time-step (MTS) surrogate --------------------------
  * Not part of the paper's scheme: an optional acceleration of the MD update

@@ -1,10 +1,13 @@
 // Roofline calibration: the FP32 FMA rate this build's kernels can reach.
 //
 // Every kernel of the library is compiled with packed FP32 instructions
-// disabled, so the VALU executes one wave64 FP32 instruction per SIMD every
-// four cycles.  This kernel issues nothing but independent v_fma_f32 (eight
-// chains per lane, enough waves to fill every SIMD) and reports the rate, the
-// ceiling of any FP32 VALU-bound kernel here.
+// disabled.  On gfx950 a wave64 FP32 FMA / MUL / ADD whose operands are all
+// VGPRs still issues every ~2 cycles per SIMD (the published FP32 vector
+// rate), while forms with an SGPR operand, a DPP source and the VOP3 encoding
+// of v_fmac issue every ~4 cycles and transcendentals every ~8.  This kernel
+// issues nothing but independent all-VGPR FMAs (eight chains per lane,
+// enough waves to fill every SIMD) and reports that rate, the ceiling of any
+// FP32 VALU-bound kernel here.
 #include <hip/hip_runtime.h>
 
 #include "pamd.h"
@@ -20,12 +23,16 @@ __global__ __launch_bounds__(kFmaThreads) void k_fma_rate(float* out, int iters,
 #pragma unroll
     for (int q = 0; q < 8; ++q)
         a[q] = tid * 1e-7f + q;
+    // lane-dependent multiplier and addend: the FMAs read VGPRs only (a
+    // uniform kernel argument would stay in an SGPR, the ~4-cycle form)
+    const float vb = b + (float)(threadIdx.x & 1) * 1e-9f;
+    const float vc = c + (float)(threadIdx.x & 2) * 1e-9f;
     for (int i = 0; i < iters; ++i) {
 #pragma unroll
         for (int u = 0; u < kFmaPerIter / 8; ++u) {
 #pragma unroll
             for (int q = 0; q < 8; ++q)
-                a[q] = fmaf(a[q], b, c);
+                a[q] = fmaf(a[q], vb, vc);
         }
     }
     float s = 0.0f;
@@ -37,7 +44,124 @@ __global__ __launch_bounds__(kFmaThreads) void k_fma_rate(float* out, int iters,
         out[0] = s;
 }
 
+// Issue cost of single VALU instruction forms: eight independent chains per
+// lane of one form, 32 instructions per loop iteration.  The forms are written
+// as inline assembly (VALU only, registers only) so the encoding is exact.
+constexpr int kFormIters = 2048;
+
+#define PAMD_FORM_BODY(ASM)                \
+    _Pragma("unroll") for (int q = 0; q < 8; ++q) \
+    {                                      \
+        ASM;                               \
+    }
+
+template <int FORM>
+__global__ __launch_bounds__(1024) void k_valu_form(float* sink, int iters, float bs)
+{
+    float a[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+        a[q] = 1.0f + (float)(threadIdx.x & 7) * 1e-6f + (float)q * 1e-3f;
+    const float vb = 0.9999999f + (float)(threadIdx.x & 1) * 1e-9f;
+    const float vc = 1e-8f * (float)((threadIdx.x & 3) + 1);
+    const uint64_t t0 = __builtin_amdgcn_s_memtime();
+    for (int i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if constexpr (FORM == PAMD_VALU_FMA_VGPR)
+                PAMD_FORM_BODY(asm volatile("v_fma_f32 %0, %0, %1, %2" : "+v"(a[q]) : "v"(vb), "v"(vc)))
+            if constexpr (FORM == PAMD_VALU_FMA_SGPR)
+                PAMD_FORM_BODY(asm volatile("v_fma_f32 %0, %0, %1, %2" : "+v"(a[q]) : "s"(bs), "v"(vc)))
+            if constexpr (FORM == PAMD_VALU_FMAC_VOP2)
+                PAMD_FORM_BODY(asm volatile("v_fmac_f32_e32 %0, %1, %2" : "+v"(a[q]) : "v"(vb), "v"(vc)))
+            if constexpr (FORM == PAMD_VALU_MUL_VOP2)
+                PAMD_FORM_BODY(asm volatile("v_mul_f32_e32 %0, %0, %1" : "+v"(a[q]) : "v"(vb)))
+            if constexpr (FORM == PAMD_VALU_ADD_DPP)
+                PAMD_FORM_BODY(asm volatile("v_add_f32_dpp %0, %1, %0 row_ror:1 row_mask:0xf bank_mask:0xf"
+                                            : "+v"(a[q]) : "v"(vc)))
+            if constexpr (FORM == PAMD_VALU_MOV_DPP)
+                PAMD_FORM_BODY(asm volatile("v_mov_b32_dpp %0, %1 row_ror:1 row_mask:0xf bank_mask:0xf"
+                                            : "=v"(a[q]) : "v"(vc)))
+            if constexpr (FORM == PAMD_VALU_RCP)
+                PAMD_FORM_BODY(asm volatile("v_rcp_f32_e32 %0, %0" : "+v"(a[q])))
+        }
+    }
+    const uint64_t t1 = __builtin_amdgcn_s_memtime();
+    float s = 0.0f;
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+        s += a[q];
+    // values no input produces: keep the chains live, store nothing
+    if (s == -12345.0f)
+        sink[0] = s;
+    // shader cycles of wave 0 of workgroup 0 (used from a one-wave-per-SIMD launch)
+    if (blockIdx.x == 0 && threadIdx.x == 0 && s != -12346.0f)
+        reinterpret_cast<uint64_t*>(sink)[1] = t1 - t0;
+}
+
+template <int FORM>
+hipError_t time_form(float* sink, int n_cu, int waves, hipStream_t s, hipEvent_t e0, hipEvent_t e1, float* ms)
+{
+    const int per_block = waves > 4 ? 4 : waves;            // waves per SIMD per workgroup
+    const dim3 grid((unsigned)(n_cu * (waves / per_block))), block((unsigned)(256 * per_block));
+    hipLaunchKernelGGL(k_valu_form<FORM>, grid, block, 0, s, sink, kFormIters / 8, 0.9999999f);   // warm
+    hipEventRecord(e0, s);
+    hipLaunchKernelGGL(k_valu_form<FORM>, grid, block, 0, s, sink, kFormIters, 0.9999999f);
+    hipEventRecord(e1, s);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess)
+        e = hipEventSynchronize(e1);
+    if (e == hipSuccess)
+        e = hipEventElapsedTime(ms, e0, e1);
+    return e;
+}
+
 }  // namespace
+
+extern "C" pamd_status pamd_valu_issue_rates(float* d_sink, int32_t waves_per_simd, double* cycles_per_instr,
+                                             double* clock_ghz, void* stream)
+{
+    if (!d_sink || !cycles_per_instr || !clock_ghz ||
+        !(waves_per_simd == 1 || waves_per_simd == 2 || waves_per_simd == 4 || waves_per_simd == 8))
+        return PAMD_ERR_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    int dev = 0, n_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n_cu < 1)
+        return PAMD_ERR_HIP;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess)
+        return PAMD_ERR_HIP;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return PAMD_ERR_HIP;
+    }
+    hipError_t e = hipSuccess;
+    // the clock: shader cycles of one wave alone on its SIMD over the launch time
+    float ms = 0.0f;
+    e = time_form<PAMD_VALU_FMAC_VOP2>(d_sink, n_cu, 1, s, e0, e1, &ms);
+    uint64_t cyc = 0;
+    if (e == hipSuccess)
+        e = hipMemcpy(&cyc, reinterpret_cast<uint64_t*>(d_sink) + 1, sizeof(cyc), hipMemcpyDeviceToHost);
+    const double ghz = (e == hipSuccess && ms > 0.0f) ? (double)cyc / (ms * 1e6) : 0.0;
+    const double instr = (double)waves_per_simd * kFormIters * 32.0;   // wave-instructions per SIMD
+    float t[PAMD_VALU_FORMS] = {};
+    if (e == hipSuccess) e = time_form<PAMD_VALU_FMA_VGPR>(d_sink, n_cu, waves_per_simd, s, e0, e1, &t[0]);
+    if (e == hipSuccess) e = time_form<PAMD_VALU_FMA_SGPR>(d_sink, n_cu, waves_per_simd, s, e0, e1, &t[1]);
+    if (e == hipSuccess) e = time_form<PAMD_VALU_FMAC_VOP2>(d_sink, n_cu, waves_per_simd, s, e0, e1, &t[2]);
+    if (e == hipSuccess) e = time_form<PAMD_VALU_MUL_VOP2>(d_sink, n_cu, waves_per_simd, s, e0, e1, &t[3]);
+    if (e == hipSuccess) e = time_form<PAMD_VALU_ADD_DPP>(d_sink, n_cu, waves_per_simd, s, e0, e1, &t[4]);
+    if (e == hipSuccess) e = time_form<PAMD_VALU_MOV_DPP>(d_sink, n_cu, waves_per_simd, s, e0, e1, &t[5]);
+    if (e == hipSuccess) e = time_form<PAMD_VALU_RCP>(d_sink, n_cu, waves_per_simd, s, e0, e1, &t[6]);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (e != hipSuccess || !(ghz > 0.0))
+        return PAMD_ERR_HIP;
+    for (int f = 0; f < PAMD_VALU_FORMS; ++f)
+        cycles_per_instr[f] = (double)t[f] * 1e-3 * ghz * 1e9 / instr;
+    *clock_ghz = ghz;
+    return PAMD_OK;
+}
 
 extern "C" pamd_status pamd_fp32_fma_rate(float* d_sink, double* tflops, void* stream)
 {

@@ -81,7 +81,7 @@ EXPORTS = ["pamd_query_sizes", "pamd_init", "pamd_md_steps", "pamd_resample", "p
            "pamd_nn_query_sizes", "pamd_nn_create", "pamd_nn_set_weights", "pamd_nn_get_weights",
            "pamd_nn_forces", "pamd_nn_forces_static",
            "pamd_nn_loss_grad", "pamd_nn_train_step", "pamd_nn_destroy", "pamd_nn_last_error",
-           "pamd_export_configs", "pamd_mts_query_sizes", "pamd_set_mts", "pamd_fp32_fma_rate",
+           "pamd_export_configs", "pamd_mts_query_sizes", "pamd_set_mts", "pamd_fp32_fma_rate", "pamd_valu_issue_rates",
            "pamd_family_error", "pamd_binning_error", "pamd_wham", "pamd_wham_average"]
 NN_PARAMS = 49537
 NN_FEATURES, NN_HIDDEN, NN_TYPES = 256, 128, 8
@@ -143,6 +143,7 @@ def load_library(path: str = LIB_PATH):
     lib.pamd_mts_query_sizes.argtypes = [vp, P(C.c_size_t)]
     lib.pamd_set_mts.argtypes = [vp, vp, i32, vp, C.c_size_t, vp]
     lib.pamd_fp32_fma_rate.argtypes = [vp, vp, vp]
+    lib.pamd_valu_issue_rates.argtypes = [vp, i32, vp, vp, vp]
     lib.pamd_family_error.argtypes = [vp, vp, i64, vp]
     lib.pamd_binning_error.argtypes = [vp, i64, i64, vp]
     lib.pamd_wham.argtypes = [i32, vp, vp, vp, vp, i32, C.c_double, vp]
@@ -224,6 +225,26 @@ def fp32_fma_rate() -> float:
     if st != PAMD_OK:
         raise PamdError(st, "FMA-rate calibration failed")
     return out.value
+
+
+VALU_FORMS = ("v_fma_f32 (VGPR operands)", "v_fma_f32 (one SGPR operand)", "v_fmac_f32_e32", "v_mul_f32_e32",
+              "v_add_f32 (DPP row-rotated source)", "v_mov_b32 (DPP row rotation)", "v_rcp_f32")
+
+
+def valu_issue_rates(waves_per_simd: int = 4) -> Dict:
+    """Shader cycles per wave64 instruction per SIMD of single VALU
+    instruction forms (pamd_valu_issue_rates) and the measured shader clock."""
+    import torch
+    lib = load_library()
+    sink = torch.zeros(4, dtype=torch.float32, device="cuda")
+    cyc = (C.c_double * len(VALU_FORMS))()
+    ghz = C.c_double()
+    st = lib.pamd_valu_issue_rates(C.c_void_p(sink.data_ptr()), int(waves_per_simd), cyc, C.byref(ghz),
+                                   C.c_void_p(torch.cuda.current_stream().cuda_stream))
+    if st != PAMD_OK:
+        raise PamdError(st, "VALU issue-rate calibration failed")
+    return {"waves_per_simd": int(waves_per_simd), "clock_ghz": ghz.value,
+            "cycles_per_instr": {name: cyc[f] for f, name in enumerate(VALU_FORMS)}}
 
 
 def _ptr(a: Optional[np.ndarray]):
