@@ -119,8 +119,10 @@ def autotune_batched(systems: Sequence, R_each: int, precision: int = PAMD_FP32,
 
     Candidates: every run in the batched wide launch, or the runs that fit
     the register tile (at most 80 atoms) in register-tile launches and the
-    rest in the wide launch; in both cases the wide launch with 4, 3, 2 or 1
-    waves per workgroup (register-tile launches at 16 waves per workgroup).
+    rest in the wide launch (all of them in register-tile launches when no
+    molecule needs the wide layout); the wide launch, where some run takes
+    it, with 4, 3, 2 or 1 waves per workgroup (register-tile launches at 16
+    waves per workgroup).
     When the register-tile split wins, its launches are then also timed at
     8 and 4 waves per workgroup: a small population (R_each / 4 work items
     against 16 waves on every CU) otherwise lands on the few CUs whose waves
@@ -138,7 +140,9 @@ def autotune_batched(systems: Sequence, R_each: int, precision: int = PAMD_FP32,
         return dict(cache[key], cached=True)
     small = [s.n_atoms <= TILE_ATOMS for s in systems]
     layouts = {"wide": ["wide"] * len(systems)}
-    if any(small) and not all(small):
+    if any(small):
+        # every run of at most 80 atoms in register-tile launches (all of them
+        # when no molecule needs the wide layout)
         layouts["tile_small"] = ["tile" if sm else "wide" for sm in small]
     timings, shapes = {}, {}
 
@@ -151,10 +155,11 @@ def autotune_batched(systems: Sequence, R_each: int, precision: int = PAMD_FP32,
         p.close()
 
     for lname, lay in layouts.items():
-        for w in wide_candidates:
+        # the wide launch's shape only matters when some run takes it
+        for w in (wide_candidates if "wide" in lay else (0,)):
             probe(f"{lname}/w{w}", lay, w, 0)
     choice = max(timings, key=timings.get)
-    if shapes[choice][0] != layouts["wide"]:
+    if "tile" in shapes[choice][0]:
         lay, w = shapes[choice][0], shapes[choice][1]
         for tw in TILE_SMALL_CANDIDATES:
             probe(f"tile_small/w{w}/t{tw}", lay, w, tw)
