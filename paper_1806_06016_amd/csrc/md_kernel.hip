@@ -76,8 +76,6 @@ __device__ __forceinline__ float sqrt_(float x) { return __builtin_sqrtf(x); }
 __device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
 __device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
-__device__ __forceinline__ float atan2_(float y, float x) { return atan2f(y, x); }
-__device__ __forceinline__ double atan2_(double y, double x) { return atan2(y, x); }
 
 // Angle in [0, pi] from y = |u x w| >= 0 and x = u.w.  FP32: the octant is
 // reduced to t = min / max in [0, 1] and atan(t) = t P(t^2) with an odd
@@ -104,8 +102,6 @@ __device__ __forceinline__ float angle_yx(float y, float x)
     return x < 0.0f ? 3.141592653589793f - a : a;
 }
 __device__ __forceinline__ double angle_yx(double y, double x) { return atan2(y, x); }
-__device__ __forceinline__ float log_(float x) { return logf(x); }
-__device__ __forceinline__ double log_(double x) { return log(x); }
 __device__ __forceinline__ void sincos_(float a, float* s, float* c) { sincosf(a, s, c); }
 __device__ __forceinline__ void sincos_(double a, double* s, double* c) { sincos(a, s, c); }
 
@@ -116,12 +112,6 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-template <typename real>
-__device__ __forceinline__ void lds_add(real* p, real v)
-{
-    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 // Tile schedule, column-major over blocks: for block J, first its diagonal
