@@ -1006,11 +1006,11 @@ hipError_t launch_observables_t(const RunDev<real>& d, hipStream_t s)
 
 hipError_t launch_init(const RunDev<float>& d, hipStream_t s) { return launch_init_t(d, s); }
 hipError_t launch_init(const RunDev<double>& d, hipStream_t s) { return launch_init_t(d, s); }
-hipError_t launch_resample(const RunDev<float>& d, double T_req, double mtot, int, hipStream_t s)
+hipError_t launch_resample(const RunDev<float>& d, double T_req, double mtot, hipStream_t s)
 {
     return launch_resample_t(d, T_req, mtot, s);
 }
-hipError_t launch_resample(const RunDev<double>& d, double T_req, double mtot, int, hipStream_t s)
+hipError_t launch_resample(const RunDev<double>& d, double T_req, double mtot, hipStream_t s)
 {
     return launch_resample_t(d, T_req, mtot, s);
 }

@@ -42,8 +42,8 @@ hipError_t md_occupancy(int precision_fp32, int nslot, int diel, int n, int wave
 size_t md_lds(int precision_fp32, int nslot, int n, int waves);
 hipError_t launch_init(const RunDev<float>& d, hipStream_t s);
 hipError_t launch_init(const RunDev<double>& d, hipStream_t s);
-hipError_t launch_resample(const RunDev<float>& d, double T_req, double mtot, int gb, hipStream_t s);
-hipError_t launch_resample(const RunDev<double>& d, double T_req, double mtot, int gb, hipStream_t s);
+hipError_t launch_resample(const RunDev<float>& d, double T_req, double mtot, hipStream_t s);
+hipError_t launch_resample(const RunDev<double>& d, double T_req, double mtot, hipStream_t s);
 size_t part_doubles(int64_t R_cap);
 size_t cpart_count(int64_t R_cap);
 hipError_t launch_md_begin(const RunDev<float>& d, hipStream_t s);
@@ -119,7 +119,7 @@ struct pamd_ctx {
     std::vector<Run> runs;
     std::string err;
     int failed = 0;
-    int n_cu = 0, gather_blocks = 0;
+    int n_cu = 0;
     int have_energy = 0;     // some pamd_md_steps (or a state with energies) since init
     pamd_nn* nn = nullptr;   // learned surrogate of the r-RESPA inner force (null: plain MD)
     int mts_ratio = 0;       // inner steps per outer step
@@ -1205,7 +1205,6 @@ pamd_status pamd_init(const pamd_system* sys, int32_t n_runs, const pamd_params*
         c->tile_waves = waves;
         c->tile_blocks = c->n_cu * bpc;
     }
-    c->gather_blocks = c->n_cu * 8;
     for (int r = 0; r < n_runs; ++r) {
         const int w = c->fp32 && c->runs[r].f.wide;
         c->runs[r].f.waves_per_block = w ? c->wide_waves : c->tile_waves;
@@ -1334,11 +1333,11 @@ pamd_status pamd_resample(pamd_ctx* c, const double* T_next, const double* d_uni
         if (c->fp32) {
             RunDev<float> d = run.f;
             d.unif = d_uniforms ? d_uniforms + (size_t)r * d.R_cap : nullptr;
-            HIPCHK(c, launch_resample(d, Treq, run.mtot, c->gather_blocks, s));
+            HIPCHK(c, launch_resample(d, Treq, run.mtot, s));
         } else {
             RunDev<double> d = run.d;
             d.unif = d_uniforms ? d_uniforms + (size_t)r * d.R_cap : nullptr;
-            HIPCHK(c, launch_resample(d, Treq, run.mtot, c->gather_blocks, s));
+            HIPCHK(c, launch_resample(d, Treq, run.mtot, s));
         }
     }
     return PAMD_OK;
