@@ -91,26 +91,14 @@ def cpu_baseline_one_core(seconds_target: float = 8.0):
                                          f"one thread, {el:.1f} s)")
 
 
-def cpu_baseline(sysd, seconds_target: float = 15.0):
+def cpu_baseline(seconds_target: float = 15.0):
     """The FP64 oracle (plain C, OpenMP over replicas) on the host cores, on a
     bounded sample of the same workload: R_s replicas x theta_s steps of the
-    same peptide at 700 K, and the same on one core.  Returns replica-steps/s."""
-    import numpy as np
-    from oracle import oracle as O
-    osys = O.OracleSystem(sysd)
+    75-atom peptide at 700 K, and the same on one core.  Returns replica-steps/s."""
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     R = max(64, 8 * threads)
-    x = np.ascontiguousarray(np.broadcast_to(sysd.x_init, (R, sysd.n_atoms, 3)).astype(np.float64))
-    v = O.init_velocities(osys, R, 700.0, seed=1806)
-    # calibrate
-    t0 = time.perf_counter()
-    O.md_steps(osys, x, v, 20, 700.0, 0.001, 1.0, 1806, 0)
-    dt1 = time.perf_counter() - t0
-    steps = max(20, int(seconds_target / max(dt1, 1e-6) * 20))
-    t0 = time.perf_counter()
-    O.md_steps(osys, x, v, steps, 700.0, 0.001, 1.0, 1806, 20)
-    el = time.perf_counter() - t0
-    return dict(value=R * steps / el, unit="replica-MD steps/s", cores=threads, kind="oracle",
+    r, steps, el = _oracle_sample(R, seconds_target)
+    return dict(value=r, unit="replica-MD steps/s", cores=threads, kind="oracle",
                 sample=f"{R} replicas x {steps} steps of the 75-atom peptide at 700 K (FP64 oracle, "
                        f"{el:.1f} s)", one_core=cpu_baseline_one_core())
 
@@ -401,7 +389,7 @@ def main():
     p.close()
     _attainable(result)
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(sysd, args.cpu_seconds)
+        result["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(result))
 
 

@@ -59,3 +59,12 @@ def test_committed_traffic_summaries_are_current(name):
     """The committed counter summaries belong to the committed kernel source
     (otherwise the bench would report traffic null)."""
     assert bench.measured_traffic(name) is not None
+
+
+def test_cpu_baseline_fields():
+    """The oracle baseline on the host: the bench line's cpu_baseline object
+    (all host threads, and one core in a child process) on a short sample."""
+    one = bench.cpu_baseline_one_core(0.3)
+    assert one["cores"] == 1 and one["value"] > 0 and "one thread" in one["sample"]
+    r, steps, el = bench._oracle_sample(16, 0.3)
+    assert r > 0 and steps >= 20 and el > 0
