@@ -3,7 +3,8 @@ the grouping (six-coordinated hubs: 15 angles per centre, more than four
 outer atoms; 25 torsions around one bond, more than three outer atoms per
 side; a second torsion term stacked on five quadruples), against the FP64
 oracle through the C ABI, in the register-tile layout (FP64 and FP32) and in
-the wide layout (batched with a 120-atom peptide).
+the wide layout (batched with a 120-atom peptide); and the same molecule with
+torsion multiplicities 1..6 (the derivative's recurrence path for n > 3).
 
 Tolerances as for the other molecules: forces within 1e-9 (FP64) / 1e-4
 (FP32) of (|F_a| + F_rms) per atom, energies within 1e-10 / 1e-5 of the sum of
@@ -88,4 +89,39 @@ def test_branched_trajectory(B, prec, tol):
     print("max |dx|", err)
     assert err < tol
     assert np.abs(g["E_pot"] - Ep).max() <= (1e-3 if prec else 1e-9) * max(1.0, np.abs(Ep).mean())
+    p.close()
+
+
+def _high_multiplicity(sysd):
+    """The branched pair with torsion multiplicities cycling through 1..6 (the
+    derivative's recurrence path for n > 3, the quadratic for n <= 3, in one
+    molecule), phases alternating 0 / pi."""
+    nd = len(sysd.dih_n)
+    n = (np.arange(nd) % 6 + 1).astype(np.int32)
+    delta = np.where(np.arange(nd) % 2 == 0, 0.0, np.pi)
+    return dataclasses.replace(sysd, dih_n=n, dih_delta=delta)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_high_multiplicity_torsions_register_tiles(B, prec):
+    sysd = _high_multiplicity(S.branched_pair())
+    assert sysd.dih_n.max() == 6
+    R = 13
+    p = B.Pamd([sysd], R_target=R, T0=1.0, dt=0.002, nu=1.0, seed=4, precision=prec)
+    x = _perturbed(sysd, R, 0.05, 21)
+    p.set_state(0, x, np.zeros_like(x), T=1.0)
+    F, E = p.get_forces(0)
+    _check_forces(F, E, sysd, as_stored(x, prec), prec)
+    p.close()
+
+
+def test_high_multiplicity_torsions_wide_layout(B):
+    syss = [dataclasses.replace(_high_multiplicity(S.branched_pair()), dielectric=S.DIELECTRIC_4R),
+            S.make_peptide(1806 + 3, 120)]
+    R = 11
+    p = B.Pamd(syss, R_target=R, T0=1.0, dt=0.002, nu=1.0, seed=4, precision=B.PAMD_FP32)
+    x = _perturbed(syss[0], R, 0.05, 22)
+    p.set_state(0, x, np.zeros_like(x), T=1.0)
+    F, E = p.get_forces(0)
+    _check_forces(F, E, syss[0], as_stored(x, True), 1)
     p.close()
