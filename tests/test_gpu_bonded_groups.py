@@ -125,3 +125,29 @@ def test_high_multiplicity_torsions_wide_layout(B):
     F, E = p.get_forces(0)
     _check_forces(F, E, syss[0], as_stored(x, True), 1)
     p.close()
+
+
+def test_branched_vacuum_wide_layout_trajectory(B):
+    """The branched pair (vacuum 1/r Coulomb) forced into the wide layout:
+    forces, then 100 NVT steps with identical streams against the oracle (the
+    wide kernel's vacuum instantiation)."""
+    sysd = S.branched_pair()
+    assert sysd.dielectric == S.DIELECTRIC_VACUUM
+    R, T, nu, dt, n_steps = 17, 0.8, 2.0, 0.002, 100
+    osys = O.OracleSystem(sysd)
+    p = B.Pamd([sysd], R_target=R, T0=T, dt=dt, nu=nu, seed=12, precision=B.PAMD_FP32, layout="wide")
+    assert p.run_launch(0)["layout"] == "wide"
+    x = _perturbed(sysd, R, 0.03, 31)
+    v = O.init_velocities(osys, R, T, seed=6)
+    p.set_state(0, x, v, T=T, step=7)
+    xo, vo = as_stored(x, True), as_stored(v, True)
+    F, E = p.get_forces(0)
+    _check_forces(F, E, sysd, xo, 1)
+    p.md_steps(n_steps)
+    Ep, Ek = O.md_steps(osys, xo, vo, n_steps, T, dt, nu, 12, step0=7)
+    g = p.get_state(0)
+    err = np.abs(g["x"] - xo).max()
+    print("max |dx|", err)
+    assert err < 1e-4
+    assert np.abs(g["E_pot"] - Ep).max() <= 1e-3 * max(1.0, np.abs(Ep).mean())
+    p.close()
