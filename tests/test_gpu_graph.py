@@ -24,15 +24,20 @@ def _state(p):
     return st["x"], st["v"], st["E_pot"], st["ancestor"], st["T"], st["sum_lnQ"]
 
 
-@pytest.mark.parametrize("mode", ["adaptive", "schedule"])
-def test_graph_replay_matches_eager(B, mode):
+@pytest.mark.parametrize("mode,thermostat,resampling", [("adaptive", "andersen", "nearest"),
+                                                        ("schedule", "andersen", "nearest"),
+                                                        ("adaptive", "langevin", "multinomial"),
+                                                        ("schedule", "langevin", "none")])
+def test_graph_replay_matches_eager(B, mode, thermostat, resampling):
     """One capture replayed for several temperatures equals the eager call
     sequence bit for bit, with eager work (observables, state reads) between
-    replays."""
+    replays; both baths and every resampling rule (the multinomial draws and
+    the Langevin noise come from device-side counters inside the graph)."""
     sysd = S.c2_system()
     R, theta = 1000, 40
     sched = S.geometric_schedule(700.0, 250.0, 40)
-    kw = dict(R_target=R, T0=700.0, dt=0.001, nu=1.0, seed=11, T_final=250.0, V_target=0.1)
+    kw = dict(R_target=R, T0=700.0, dt=0.001, nu=1.0, seed=11, T_final=250.0, V_target=0.1,
+              thermostat=thermostat, resampling=resampling)
     pe = B.Pamd([sysd], **kw)
     pg = B.Pamd([sysd], **kw)
     for p in (pe, pg):
