@@ -35,7 +35,9 @@
  *    context (sizes from pamd_query_sizes), the surrogate's parameters and
  *    workspace (pamd_nn_query_sizes) and the r-RESPA buffers
  *    (pamd_mts_query_sizes), each 256-byte aligned and kept alive until the
- *    object that uses it is destroyed.  The library allocates no device memory.
+ *    object that uses it is destroyed.  The library allocates no device memory
+ *    at run time; the only device memory it owns is the fixed staging array of
+ *    pamd_nn_forces_static, part of the loaded code object.
  */
 #ifndef PAMD_H
 #define PAMD_H
@@ -187,11 +189,14 @@ pamd_status pamd_init(const pamd_system* sys, int32_t n_runs, const pamd_params*
                       void* d_state, size_t state_bytes, void* d_work, size_t work_bytes,
                       void* stream, pamd_ctx** out);
 
-/* PAMD step 3.  n_steps >= 0 NVT velocity-Verlet steps (Andersen collisions
- * after each step) of every copy of every run at the run's current T; leaves
- * E_pot and E_kin of the final configurations (n_steps = 0 only evaluates
- * them).  With a surrogate attached (pamd_set_mts) the same time span is
- * covered by r-RESPA outer steps.  Asynchronous. */
+/* PAMD step 3.  n_steps >= 0 NVT steps of every copy of every run at the
+ * run's current T with the context's bath (velocity Verlet with Andersen
+ * collisions after each step, or the Langevin B-A-O-A-B step); leaves E_pot
+ * and E_kin of the final configurations (n_steps = 0 only evaluates them).
+ * With a surrogate attached (pamd_set_mts) the same time span is covered by
+ * r-RESPA outer steps.  A run whose sticky device error is set when the call's
+ * work starts keeps its state (positions, velocities, energies, step counter).
+ * Asynchronous. */
 pamd_status pamd_md_steps(pamd_ctx* ctx, int32_t n_steps, void* stream);
 
 /* PAMD step 2.  T_next: host [n_runs]; T_next[r] > 0 is the next temperature
