@@ -133,6 +133,13 @@ struct pamd_ctx {
     RunDev<float>* d_runs = nullptr;   // device copies of the runs' descriptors
     int32_t* d_order = nullptr;        // runs in decreasing pair work
     int32_t* d_counter = nullptr;      // work-queue counter
+    // the register-tile runs of a context with more than one MD launch run on
+    // side streams (forked from and joined back to the caller's stream), so
+    // their persistent launches overlap each other and the wide launch
+    static constexpr int kSide = 3;
+    int n_side = 0;
+    hipStream_t side[kSide] = {};
+    hipEvent_t ev_fork = nullptr, ev_join[kSide] = {};
 };
 
 namespace {
@@ -1211,6 +1218,15 @@ pamd_status pamd_init(const pamd_system* sys, int32_t n_runs, const pamd_params*
         c->runs[r].d.waves_per_block = c->tile_waves;
         c->runs[r].nu = p[r].nu;
     }
+    // side streams (default priority) when register-tile launches can overlap
+    if (n_tile >= 1 && n_tile + (c->wide ? 1 : 0) >= 2) {
+        HIPCHK(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+        for (int k = 0; k < std::min(n_tile, pamd_ctx::kSide); ++k) {
+            HIPCHK(c, hipStreamCreateWithFlags(&c->side[k], hipStreamNonBlocking));
+            HIPCHK(c, hipEventCreateWithFlags(&c->ev_join[k], hipEventDisableTiming));
+            c->n_side = k + 1;
+        }
+    }
     return c->fp32 ? init_runs<float>(c, sys, s) : init_runs<double>(c, sys, s);
 }
 
@@ -1273,6 +1289,17 @@ static pamd_status respa_steps(pamd_ctx* c, Run& run, int n_steps, hipStream_t s
     return PAMD_OK;
 }
 
+// PAMD step 3 of one register-tile run on stream t
+template <typename real>
+static pamd_status enqueue_tile_md(pamd_ctx* c, const RunDev<real>& d, int n_steps, hipStream_t t)
+{
+    HIPCHK(c, launch_md_begin(d, t));
+    HIPCHK(c, launch_md(d, n_steps, c->tile_blocks, c->tile_waves, t));
+    HIPCHK(c, launch_energy(d, c->tile_blocks, c->tile_waves, t));
+    HIPCHK(c, launch_md_finalize(d, n_steps, t));
+    return PAMD_OK;
+}
+
 pamd_status pamd_md_steps(pamd_ctx* c, int32_t n_steps, void* stream)
 {
     TraceRange trace_range("pamd_md_steps");
@@ -1283,6 +1310,34 @@ pamd_status pamd_md_steps(pamd_ctx* c, int32_t n_steps, void* stream)
         return fail(c, PAMD_ERR_ARG, "n_steps < 0");
     c->have_energy = 1;
     hipStream_t s = as_stream(stream);
+    if (c->n_side > 0 && !(c->nn && n_steps > 0)) {
+        // fork: the register-tile runs first, round robin over the side
+        // streams, then the wide launch on `s`; join every side stream back
+        HIPCHK(c, hipEventRecord(c->ev_fork, s));
+        int used = 0, k = 0;
+        for (auto& run : c->runs) {
+            if (c->fp32 && run.f.wide)
+                continue;
+            hipStream_t t = c->side[k];
+            if (k >= used) {
+                HIPCHK(c, hipStreamWaitEvent(t, c->ev_fork, 0));
+                used = k + 1;
+            }
+            st = c->fp32 ? enqueue_tile_md(c, run.f, n_steps, t) : enqueue_tile_md(c, run.d, n_steps, t);
+            if (st != PAMD_OK)
+                return st;
+            k = (k + 1) % c->n_side;
+        }
+        if (c->wide)
+            HIPCHK(c, launch_md_wide(c->d_runs, c->d_order, c->n_wide, c->d_counter, c->nmax, n_steps, c->diel,
+                                     c->runs[0].f.thermostat == PAMD_THERMOSTAT_LANGEVIN, c->wide_blocks,
+                                     c->wide_waves, s));
+        for (int q = 0; q < used; ++q) {
+            HIPCHK(c, hipEventRecord(c->ev_join[q], c->side[q]));
+            HIPCHK(c, hipStreamWaitEvent(s, c->ev_join[q], 0));
+        }
+        return PAMD_OK;
+    }
     if (c->wide)
         HIPCHK(c, launch_md_wide(c->d_runs, c->d_order, c->n_wide, c->d_counter, c->nmax, n_steps, c->diel,
                                  c->runs[0].f.thermostat == PAMD_THERMOSTAT_LANGEVIN, c->wide_blocks, c->wide_waves,
@@ -1300,17 +1355,9 @@ pamd_status pamd_md_steps(pamd_ctx* c, int32_t n_steps, void* stream)
     for (auto& run : c->runs) {
         if (c->fp32 && run.f.wide)
             continue;   // advanced by the batched launch above
-        if (c->fp32) {
-            HIPCHK(c, launch_md_begin(run.f, s));
-            HIPCHK(c, launch_md(run.f, n_steps, c->tile_blocks, c->tile_waves, s));
-            HIPCHK(c, launch_energy(run.f, c->tile_blocks, c->tile_waves, s));
-            HIPCHK(c, launch_md_finalize(run.f, n_steps, s));
-        } else {
-            HIPCHK(c, launch_md_begin(run.d, s));
-            HIPCHK(c, launch_md(run.d, n_steps, c->tile_blocks, c->tile_waves, s));
-            HIPCHK(c, launch_energy(run.d, c->tile_blocks, c->tile_waves, s));
-            HIPCHK(c, launch_md_finalize(run.d, n_steps, s));
-        }
+        st = c->fp32 ? enqueue_tile_md(c, run.f, n_steps, s) : enqueue_tile_md(c, run.d, n_steps, s);
+        if (st != PAMD_OK)
+            return st;
     }
     return PAMD_OK;
 }
@@ -1772,6 +1819,16 @@ void pamd_destroy(pamd_ctx* c)
         return;
     for (int g = 0; g < kGraphSlots; ++g)
         drop_graph(c, g);
+    for (int k = 0; k < pamd_ctx::kSide; ++k) {
+        if (c->side[k])
+            (void)hipStreamSynchronize(c->side[k]);
+        if (c->side[k])
+            (void)hipStreamDestroy(c->side[k]);
+        if (c->ev_join[k])
+            (void)hipEventDestroy(c->ev_join[k]);
+    }
+    if (c->ev_fork)
+        (void)hipEventDestroy(c->ev_fork);
     delete c;
 }
 
