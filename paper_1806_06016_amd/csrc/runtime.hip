@@ -133,9 +133,11 @@ struct pamd_ctx {
     RunDev<float>* d_runs = nullptr;   // device copies of the runs' descriptors
     int32_t* d_order = nullptr;        // runs in decreasing pair work
     int32_t* d_counter = nullptr;      // work-queue counter
-    // the register-tile runs of a context with more than one MD launch run on
-    // side streams (forked from and joined back to the caller's stream), so
-    // their persistent launches overlap each other and the wide launch
+    // the register-tile runs of a context with several of them run on side
+    // streams forked from and joined back to the caller's stream, so their
+    // persistent launches (each latency-bound on a fraction of the CUs for a
+    // small population) overlap; the wide launch follows the join, since a
+    // persistent wide launch that reaches the CUs first would hold them
     static constexpr int kSide = 3;
     int n_side = 0;
     hipStream_t side[kSide] = {};
@@ -1219,7 +1221,7 @@ pamd_status pamd_init(const pamd_system* sys, int32_t n_runs, const pamd_params*
         c->runs[r].nu = p[r].nu;
     }
     // side streams (default priority) when register-tile launches can overlap
-    if (n_tile >= 1 && n_tile + (c->wide ? 1 : 0) >= 2) {
+    if (n_tile >= 2) {
         HIPCHK(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
         for (int k = 0; k < std::min(n_tile, pamd_ctx::kSide); ++k) {
             HIPCHK(c, hipStreamCreateWithFlags(&c->side[k], hipStreamNonBlocking));
@@ -1311,8 +1313,8 @@ pamd_status pamd_md_steps(pamd_ctx* c, int32_t n_steps, void* stream)
     c->have_energy = 1;
     hipStream_t s = as_stream(stream);
     if (c->n_side > 0 && !(c->nn && n_steps > 0)) {
-        // fork: the register-tile runs first, round robin over the side
-        // streams, then the wide launch on `s`; join every side stream back
+        // fork: the register-tile runs round robin over the side streams; join
+        // every side stream back, then the wide launch on `s`
         HIPCHK(c, hipEventRecord(c->ev_fork, s));
         int used = 0, k = 0;
         for (auto& run : c->runs) {
@@ -1328,14 +1330,14 @@ pamd_status pamd_md_steps(pamd_ctx* c, int32_t n_steps, void* stream)
                 return st;
             k = (k + 1) % c->n_side;
         }
-        if (c->wide)
-            HIPCHK(c, launch_md_wide(c->d_runs, c->d_order, c->n_wide, c->d_counter, c->nmax, n_steps, c->diel,
-                                     c->runs[0].f.thermostat == PAMD_THERMOSTAT_LANGEVIN, c->wide_blocks,
-                                     c->wide_waves, s));
         for (int q = 0; q < used; ++q) {
             HIPCHK(c, hipEventRecord(c->ev_join[q], c->side[q]));
             HIPCHK(c, hipStreamWaitEvent(s, c->ev_join[q], 0));
         }
+        if (c->wide)
+            HIPCHK(c, launch_md_wide(c->d_runs, c->d_order, c->n_wide, c->d_counter, c->nmax, n_steps, c->diel,
+                                     c->runs[0].f.thermostat == PAMD_THERMOSTAT_LANGEVIN, c->wide_blocks,
+                                     c->wide_waves, s));
         return PAMD_OK;
     }
     if (c->wide)
