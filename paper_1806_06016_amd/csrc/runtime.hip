@@ -1291,13 +1291,18 @@ static pamd_status respa_steps(pamd_ctx* c, Run& run, int n_steps, hipStream_t s
     return PAMD_OK;
 }
 
-// PAMD step 3 of one register-tile run on stream t
+// PAMD step 3 of one register-tile run on stream t.  The persistent launch
+// takes no more workgroups than its R_cap / 4 work items can occupy, so the
+// launches of small populations on side streams share the chip instead of
+// each holding every CU.
 template <typename real>
 static pamd_status enqueue_tile_md(pamd_ctx* c, const RunDev<real>& d, int n_steps, hipStream_t t)
 {
+    const int64_t per_block = (int64_t)kRowsPerWave * c->tile_waves;
+    const int blocks = (int)std::min<int64_t>(c->tile_blocks, (d.R_cap + per_block - 1) / per_block);
     HIPCHK(c, launch_md_begin(d, t));
-    HIPCHK(c, launch_md(d, n_steps, c->tile_blocks, c->tile_waves, t));
-    HIPCHK(c, launch_energy(d, c->tile_blocks, c->tile_waves, t));
+    HIPCHK(c, launch_md(d, n_steps, blocks, c->tile_waves, t));
+    HIPCHK(c, launch_energy(d, blocks, c->tile_waves, t));
     HIPCHK(c, launch_md_finalize(d, n_steps, t));
     return PAMD_OK;
 }
@@ -1650,8 +1655,13 @@ pamd_status pamd_run_launch(const pamd_ctx* c, int32_t run, int32_t* layout, int
         *layout = w ? PAMD_LAYOUT_WIDE : PAMD_LAYOUT_TILE;
     if (waves_per_block)
         *waves_per_block = w ? c->wide_waves : c->tile_waves;
-    if (blocks)
-        *blocks = w ? c->wide_blocks : c->tile_blocks;
+    if (blocks) {
+        // a register-tile launch takes at most the workgroups its R_cap / 4 items fill
+        const int64_t per_block = (int64_t)kRowsPerWave * c->tile_waves;
+        const int64_t R_cap = c->fp32 ? c->runs[run].f.R_cap : c->runs[run].d.R_cap;
+        *blocks = w ? c->wide_blocks
+                    : (int32_t)std::min<int64_t>(c->tile_blocks, (R_cap + per_block - 1) / per_block);
+    }
     if (lds_bytes)
         *lds_bytes = (int32_t)(w ? c->wide_lds : c->tile_lds);
     return PAMD_OK;
