@@ -1291,15 +1291,25 @@ static pamd_status respa_steps(pamd_ctx* c, Run& run, int n_steps, hipStream_t s
     return PAMD_OK;
 }
 
-// PAMD step 3 of one register-tile run on stream t.  The persistent launch
-// takes no more workgroups than its R_cap / 4 work items can occupy, so the
-// launches of small populations on side streams share the chip instead of
-// each holding every CU.
+// workgroups of a register-tile launch of `run`.  Alone, the persistent launch
+// takes the whole chip's grid: a small population's work items then land on
+// waves of every CU, about one per SIMD, the fastest spread for a
+// latency-bound launch.  Next to other register-tile launches on side streams
+// it takes no more workgroups than its R_cap / 4 items fill, so the launches
+// share the chip instead of each holding every CU.
+static int tile_launch_blocks(const pamd_ctx* c, int64_t R_cap)
+{
+    if (c->n_side == 0)
+        return c->tile_blocks;
+    const int64_t per_block = (int64_t)kRowsPerWave * c->tile_waves;
+    return (int)std::min<int64_t>(c->tile_blocks, (R_cap + per_block - 1) / per_block);
+}
+
+// PAMD step 3 of one register-tile run on stream t
 template <typename real>
 static pamd_status enqueue_tile_md(pamd_ctx* c, const RunDev<real>& d, int n_steps, hipStream_t t)
 {
-    const int64_t per_block = (int64_t)kRowsPerWave * c->tile_waves;
-    const int blocks = (int)std::min<int64_t>(c->tile_blocks, (d.R_cap + per_block - 1) / per_block);
+    const int blocks = tile_launch_blocks(c, d.R_cap);
     HIPCHK(c, launch_md_begin(d, t));
     HIPCHK(c, launch_md(d, n_steps, blocks, c->tile_waves, t));
     HIPCHK(c, launch_energy(d, blocks, c->tile_waves, t));
@@ -1655,13 +1665,9 @@ pamd_status pamd_run_launch(const pamd_ctx* c, int32_t run, int32_t* layout, int
         *layout = w ? PAMD_LAYOUT_WIDE : PAMD_LAYOUT_TILE;
     if (waves_per_block)
         *waves_per_block = w ? c->wide_waves : c->tile_waves;
-    if (blocks) {
-        // a register-tile launch takes at most the workgroups its R_cap / 4 items fill
-        const int64_t per_block = (int64_t)kRowsPerWave * c->tile_waves;
-        const int64_t R_cap = c->fp32 ? c->runs[run].f.R_cap : c->runs[run].d.R_cap;
+    if (blocks)
         *blocks = w ? c->wide_blocks
-                    : (int32_t)std::min<int64_t>(c->tile_blocks, (R_cap + per_block - 1) / per_block);
-    }
+                    : tile_launch_blocks(c, c->fp32 ? c->runs[run].f.R_cap : c->runs[run].d.R_cap);
     if (lds_bytes)
         *lds_bytes = (int32_t)(w ? c->wide_lds : c->tile_lds);
     return PAMD_OK;
