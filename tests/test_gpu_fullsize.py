@@ -204,3 +204,58 @@ def test_batched_workload_sampled(B):
         assert np.abs(g["E_pot"][slots] - Ep).max() <= 1e-3 * np.abs(Ep).mean()
         assert np.allclose(g["E_kin"][slots], Ek, rtol=1e-3)
     p.close()
+
+
+def test_million_replica_population(B, sysd):
+    """R = 2^20 + 7 (ten times the headline population, ragged): the
+    multi-block reductions loop over more blocks than a pass launches and the
+    slab offsets pass 2^31 bytes.  Sampled initial velocities and 20 NVT steps
+    against the oracle; then resampling of host-built energies: the adaptive
+    temperature against the oracle's bisection, and at the oracle's
+    temperature every copy number bit-exact, the gathered ancestors and
+    energies exact."""
+    Rm = (1 << 20) + 7
+    kB = sysd.kB
+    p = B.Pamd([sysd], R_target=Rm, T0=T0, dt=DT, nu=NU, seed=SEED, precision=B.PAMD_FP32, waves_per_block=16,
+               T_final=250.0, V_target=0.1)
+    slots = np.unique(np.r_[0, 1, 4095, 4096, (1 << 19) + 3, Rm - 8, Rm - 1,
+                            np.random.default_rng(3).choice(Rm, 9, replace=False)]).astype(np.int64)
+    st = p.get_state(0)
+    osys = O.OracleSystem(sysd)
+    vo = O.init_velocities(osys, len(slots), T0, seed=SEED, slots=slots)
+    assert np.abs(st["v"][slots] - vo).max() <= 1e-6 * np.abs(vo).max()
+    x0 = np.ascontiguousarray(np.broadcast_to(sysd.x_init, (len(slots),) + sysd.x_init.shape))
+    xs, vs = as_stored(x0, True), as_stored(vo, True)
+    del st
+    print("MD at R = 2^20 + 7", flush=True)
+    p.md_steps(20)
+    g = p.get_state(0)
+    assert g["R"] == Rm and g["step"] == 20 and np.isfinite(g["x"]).all() and np.isfinite(g["E_pot"]).all()
+    O.md_steps(osys, xs, vs, 20, T0, DT, NU, SEED, step0=0, slots=slots)
+    err = np.abs(g["x"][slots] - xs).max()
+    print("sampled max |dx|", err, flush=True)
+    assert err < 1e-4
+    # resampling of host-built energies (the thermal spread of the peptide at T0):
+    # the adaptive temperature, then (population restored) the copy numbers at
+    # the oracle's temperature requested explicitly
+    E = np.random.default_rng(8).gamma(219 / 2, kB * T0, Rm) - 800.0
+    db = O.adaptive_dbeta(E, 1 / (kB * 250.0) - 1 / (kB * T0), 0.1)
+    To = 1 / (kB * (db + 1 / (kB * T0)))
+    p.set_state(0, g["x"], g["v"], T=T0, E_pot=E, ancestor=np.arange(Rm))
+    p.resample(None)
+    h = p.get_state(0, want_xv=False)
+    print("adaptive T", h["T"], "oracle", To, flush=True)
+    assert abs(h["T"] - To) <= 1e-9 * To
+    p.set_state(0, g["x"], g["v"], T=T0, E_pot=E, ancestor=np.arange(Rm))
+    del g
+    p.resample([To])
+    h = p.get_state(0, want_xv=False)
+    db = 1 / (kB * To) - 1 / (kB * T0)
+    c = p.get_counts(0)
+    co, _ = O.copy_counts(E, db, Rm, O.resample_uniforms(Rm, 1, seed=SEED))
+    mism = np.nonzero(c != co)[0]
+    assert len(mism) == 0, (len(mism), mism[:5])
+    src, Eo = O.gather(co, [np.arange(Rm), E])
+    assert h["R"] == co.sum() and (h["ancestor"] == src).all() and (h["E_pot"] == Eo).all()
+    print("R after resampling", h["R"], "families", p.observables()[0]["families"])
+    p.close()
