@@ -370,3 +370,76 @@ def test_copies_decorrelate(gpu):
     st = p.get_state(0)
     assert np.abs(st["x"][0] - st["x"][1]).max() > 1e-3
     p.close()
+
+
+def _check_degenerate(p, sysd, st, T_from, T_to, n_copies, u):
+    """Every replica copied n_copies times (all tau_j equal), by the oracle's
+    rule too; canonical gather; ln Q = -dbeta E_min (S = R exactly)."""
+    g = p.get_state(0)
+    R = len(st["E_pot"])
+    dbeta = 1 / (sysd.kB * T_to) - 1 / (sysd.kB * T_from)
+    co, tau = O.copy_counts(st["E_pot"], dbeta, p.R_target, u)
+    assert (co == n_copies).all() and (tau == n_copies).all()
+    assert (p.get_counts(0)[:R] == n_copies).all() and g["R"] == n_copies * R
+    assert abs(g["T"] - T_to) <= 1e-12 * T_to
+    lq = -dbeta * st["E_pot"].min()
+    assert abs(g["lnQ_last"] - lq) <= 1e-12 * max(1.0, abs(lq)), (g["lnQ_last"], lq)
+    xo, vo, Eo, ao = O.gather(co, [st["x"], st["v"], st["E_pot"], st["ancestor"]])
+    assert (g["ancestor"] == ao).all() and (g["E_pot"] == Eo).all()
+    assert np.abs(g["x"] - O.recentre(xo, sysd.mass)).max() < (1e-12 if not p.fp32 else 2e-6)
+    if T_to == T_from:
+        assert np.array_equal(g["v"], vo)              # scale sqrt(T / T) = 1
+    else:
+        assert np.abs(g["v"] - vo * math.sqrt(T_to / T_from)).max() <= 1e-6 * np.abs(vo).max()
+    return g
+
+
+@pytest.mark.parametrize("which,prec", [("chain", 0), ("peptide", 1)])
+def test_degenerate_resampling_cases(gpu, which, prec):
+    """Resampling steps whose result is fixed in closed form (PAMD step 2):
+    at the current temperature (dbeta = 0) every weight is 1, so each replica
+    is kept once, in place, with ln Q = 0 and unscaled velocities; equal
+    energies at a lower temperature give the same copy numbers and
+    ln Q = -dbeta E; equal energies at half the target size give two copies
+    each; the adaptive step with equal energies (weight variance 0 at any
+    dbeta) jumps straight to T_final, and at T_final it stays there."""
+    sysd = S.c1_system() if which == "chain" else S.c2_system()
+    kB = sysd.kB
+    R = 389
+    T0, T1, Tf = (2.0, 1.8, 0.5) if which == "chain" else (700.0, 650.0, 250.0)
+    rng = np.random.default_rng(31 + prec)
+    E = rng.normal(10.0, 3.0, R) if which == "chain" else rng.normal(-400.0, 30.0, R)
+    flat = np.full(R, -412.625)
+    print(f"degenerate resampling {which} prec={prec}", flush=True)
+
+    p = _ctx(gpu, sysd, R, prec, T0=T0, seed=505, T_final=Tf, V_target=0.1)
+    # same temperature, Philox uniforms (irrelevant: every frac(tau) is 0)
+    st = _synthetic_population(p, sysd, R, E, T0, seed=1)
+    p.resample([T0])
+    u = O.resample_uniforms(p.R_cap, 1, seed=505)
+    g = _check_degenerate(p, sysd, st, T0, T0, 1, u)
+    assert g["lnQ_last"] == 0.0 and g["sum_lnQ"] == 0.0
+    # equal energies, explicit lower temperature
+    st = _synthetic_population(p, sysd, R, flat, T0, seed=2)
+    p.resample([T1])
+    _check_degenerate(p, sysd, st, T0, T1, 1, u)
+    # equal energies, adaptive: V(dbeta_max) = 0 <= V_target, so T_final at once
+    st = _synthetic_population(p, sysd, R, flat, T0, seed=3)
+    p.resample(None)
+    _check_degenerate(p, sysd, st, T0, Tf, 1, u)
+    assert p.observables()[0]["V_last"] == 0.0
+    # adaptive at T_final: no step left, the population is kept at T_final
+    st = _synthetic_population(p, sysd, R, E, Tf, seed=4)
+    p.resample(None)
+    g = _check_degenerate(p, sysd, st, Tf, Tf, 1, u)
+    assert g["lnQ_last"] == 0.0
+    p.close()
+
+    # equal energies with half the target population: tau_j = 2 for every j
+    p = _ctx(gpu, sysd, 2 * R, prec, T0=T0, seed=505)
+    st = _synthetic_population(p, sysd, R, flat, T0, seed=5)
+    p.resample([T1])
+    u = O.resample_uniforms(p.R_cap, 1, seed=505)
+    _check_degenerate(p, sysd, st, T0, T1, 2, u)
+    assert 1 / (kB * T1) > 1 / (kB * T0)
+    p.close()
