@@ -88,13 +88,16 @@ enum { PAMD_DIELECTRIC_VACUUM = 0, PAMD_DIELECTRIC_4R = 1 };
  *   TILE  register tile: one replica per 16-lane row, four per wavefront, one
  *         persistent launch per run (molecules up to PAMD_TILE_ATOMS atoms);
  *   WIDE  one replica per wavefront; every wide run of a context shares one
- *         persistent launch (FP32 only).
+ *         persistent launch (FP32 only).  Its LJ coefficients come from a
+ *         table over the molecule's distinct (sigma, epsilon) pairs, at most
+ *         PAMD_WIDE_LJ_CLASSES of them per molecule.
  * A context may mix both (an autotuner picks per run). */
 enum { PAMD_LAYOUT_AUTO = 0, PAMD_LAYOUT_TILE = 1, PAMD_LAYOUT_WIDE = 2 };
 
 #define PAMD_MAX_ATOMS 320   /* FP32; FP64 runs take at most 32 atoms */
 #define PAMD_TILE_ATOMS 80   /* the largest molecule of the register-tile layout (PAMD_LAYOUT_*) */
 #define PAMD_FORCE_CHUNK 256 /* replicas per pamd_get_forces call */
+#define PAMD_WIDE_LJ_CLASSES 25  /* distinct per-atom (sigma, epsilon) pairs of a wide-layout molecule */
 
 /*
  * One molecule (host pointers; all arrays row-major).  Functional form:
@@ -176,7 +179,10 @@ typedef struct pamd_obs {
 typedef struct pamd_ctx pamd_ctx;
 
 /* Device bytes needed for `n_runs` independent runs (sys[n_runs], p[n_runs]).
- * Pure host function. */
+ * Pure host function.  PAMD_ERR_ARG for a descriptor out of range, runs of
+ * different precision or bath, or a molecule of the wide layout with more
+ * than PAMD_WIDE_LJ_CLASSES distinct (sigma, epsilon) pairs (pamd_init
+ * returns the same). */
 pamd_status pamd_query_sizes(const pamd_system* sys, int32_t n_runs, const pamd_params* p,
                              size_t* state_bytes, size_t* work_bytes);
 

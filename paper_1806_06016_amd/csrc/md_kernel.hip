@@ -1130,9 +1130,9 @@ __global__ __launch_bounds__(1024) void k_export(RunDev<float> d, int64_t r0, in
 // wide layout: one replica per wavefront (molecules up to 320 atoms, and every
 // run of a context that holds one).  Atom a lives on lane a % 64, slot a / 64.
 // All-pairs nonbonded forces with Newton's third law: copies of a slot's atoms
-// rotate around the wavefront (see wide_evaluate); pair parameters are combined
-// on the fly from per-atom factors, exclusion / 1-4 bits come 64 partners at a
-// time.
+// rotate around the wavefront (see wide_evaluate); LJ pair coefficients come
+// from the molecule's class table (a copy per wave in LDS), exclusion / 1-4
+// bits 64 partners at a time.
 // ---------------------------------------------------------------------------
 // lane i receives lane (i + 1) mod 64 (DPP wave_rol:1)
 __device__ __forceinline__ int wave_rol1(int v) { return __builtin_amdgcn_mov_dpp(v, 0x134, 0xF, 0xF, false); }
@@ -1145,12 +1145,23 @@ struct WideRegs {
     float x[kWideSlots], y[kWideSlots], z[kWideSlots];
     float vx[kWideSlots], vy[kWideSlots], vz[kWideSlots];
     float fx[kWideSlots], fy[kWideSlots], fz[kWideSlots];
-    float sg[kWideSlots], se[kWideSlots], qs[kWideSlots];   // own atoms' pair parameters
+    float qs[kWideSlots];   // own atoms' Coulomb factors
+    int ci[kWideSlots];     // byte offset of the own atom's row of the LJ class table
 };
 
+// a wave's copy of its run's LJ class table
+__device__ __forceinline__ void wide_load_ljtab(const RunDev<float>& d, float2* lj, int lane)
+{
+    for (int i = lane; i < kLjClasses * kLjStride; i += kWide)
+        lj[i] = d.ljtab[i];
+    wave_sync();
+}
+
+// LJ coefficients (12 c12, -6 c6) of a pair from the class table `lj` (this
+// wave's LDS copy), its Coulomb factor qs_i qs_j
 template <int DIEL, bool ENERGY>
-__device__ __forceinline__ void wide_evaluate(WideRegs& r, const RunDev<float>& d, float* pos, float* frc, int lane,
-                                              int nsl, double& eacc)
+__device__ __forceinline__ void wide_evaluate(WideRegs& r, const RunDev<float>& d, float* pos, float* frc,
+                                              const float2* lj, int lane, int nsl, double& eacc)
 {
     const int n = d.n;
     if constexpr (!ENERGY) {
@@ -1173,121 +1184,136 @@ __device__ __forceinline__ void wide_evaluate(WideRegs& r, const RunDev<float>& 
     wave_sync();
     bonded_terms<float, ENERGY, kWide>(d, pos, frc, lane, eacc);
     // Nonbonded pairs, each unordered pair once: for every partner slot t a
-    // copy of slot t's atoms (position, pair factors, reaction-force sum and
-    // atom index) travels around the wavefront one lane per step (DPP wave
-    // rotation); at step k lane l holds partner atom 64 t + (l + k) mod 64 and
-    // pairs it with its own atoms of slots s <= t (same slot: k = 1..32, the
-    // k = 32 pair kept on one of its two lanes).  The travelling reaction sums
-    // are added to the LDS force stage at the end (distinct atoms per lane).
+    // copy of slot t's atoms (position, Coulomb factor, LJ class column and
+    // reaction-force sum) travels around the wavefront one lane per step (DPP
+    // wave rotation); at step k lane l holds partner atom 64 t + (l + k) mod 64
+    // and pairs it with its own atoms of slots s <= t (same slot: k = 1..32,
+    // the k = 32 pair kept on one of its two lanes).  The travelling reaction
+    // sums are added to the LDS force stage at the end (distinct atoms per lane).
     const float s14lj = d.s14lj, s14c = d.s14c;
+    const char* ljb = reinterpret_cast<const char*>(lj);
 #pragma unroll
     for (int t = 0; t < kWideSlots; ++t) {
         if (t < nsl) {
-            float px = r.x[t], py = r.y[t], pz = r.z[t];
-            float psg = r.sg[t], pse = r.se[t], pqs = r.qs[t];
+            float px = r.x[t], py = r.y[t], pz = r.z[t], pqs = r.qs[t];
+            int pcl = r.ci[t] / kLjStride;   // byte offset of the partner's column
             float pfx = 0.f, pfy = 0.f, pfz = 0.f;
-            int pid = lane;
-            // own atoms' exclusion / 1-4 bits over the 64 atoms of slot t
-            uint64_t ex[kWideSlots], s4[kWideSlots];
+            // own atoms' exclusion / 1-4 bits over the 64 atoms of slot t,
+            // rotated so that bit k is the partner met at step k, split into
+            // the words of steps k < 32 and k >= 32
+            uint32_t exw[kWideSlots][2], s4w[kWideSlots][2];
 #pragma unroll
             for (int s = 0; s <= t; ++s) {
                 const int a = kWide * s + lane;
-                ex[s] = ~0ull;
-                s4[s] = 0ull;
+                uint64_t ex = ~0ull, s4 = 0ull;
                 if (a < n) {
                     uint2 m0 = make_uint2(0u, 0u), m1 = make_uint2(0u, 0u);
                     if (2 * t < d.nchunk)
                         m0 = d.pmask[(size_t)a * d.nchunk + 2 * t];
                     if (2 * t + 1 < d.nchunk)
                         m1 = d.pmask[(size_t)a * d.nchunk + 2 * t + 1];
-                    ex[s] = ((uint64_t)m1.x << 32) | m0.x;
-                    s4[s] = ((uint64_t)m1.y << 32) | m0.y;
+                    ex = ((uint64_t)m1.x << 32) | m0.x;
+                    s4 = ((uint64_t)m1.y << 32) | m0.y;
                 }
+                ex = (ex >> lane) | (ex << ((kWide - lane) & (kWide - 1)));
+                s4 = (s4 >> lane) | (s4 << ((kWide - lane) & (kWide - 1)));
+                exw[s][0] = (uint32_t)ex;
+                exw[s][1] = (uint32_t)(ex >> 32);
+                s4w[s][0] = (uint32_t)s4;
+                s4w[s][1] = (uint32_t)(s4 >> 32);
             }
             // steps k at which some lane of own slot s meets an excluded or 1-4
-            // partner of slot t (bit k of stepmask[t][s], wave-uniform); every
-            // other step takes the pair code without masks and scale factors
+            // partner of slot t (bit k of stepmask[t][s], wave-uniform: held in
+            // scalar registers); every other step takes the pair code without
+            // masks and scale factors
             uint64_t smask[kWideSlots];
 #pragma unroll
-            for (int s = 0; s <= t; ++s)
-                smask[s] = d.stepmask[t * kWideSlots + s];
+            for (int s = 0; s <= t; ++s) {
+                const uint64_t m = d.stepmask[t * kWideSlots + s];
+                smask[s] = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(m >> 32)) << 32) |
+                           (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)m);
+            }
             const int kend = (t == 0) ? 33 : kWide;
-            for (int k = 0; k < kend; ++k) {
+            // one ring step; h = k / 32 selects the mask words
+            auto ring_step = [&](int k, int h) {
+                // the pair coefficients of every own slot, read before any of them is used
+                float2 ab[kWideSlots];
+#pragma unroll
+                for (int s = 0; s <= t; ++s)
+                    ab[s] = *reinterpret_cast<const float2*>(ljb + (r.ci[s] + pcl));
+                const uint32_t bit = 1u << (k & 31);
 #pragma unroll
                 for (int s = 0; s <= t; ++s) {
-                    if ((s < t || (k >= 1 && k <= 32)) && !((smask[s] >> k) & 1ull)) {
-                        const float dx = r.x[s] - px, dy = r.y[s] - py, dz = r.z[s] - pz;
-                        const float r2 = dx * dx + dy * dy + dz * dz;
-                        const float ir2 = rcp_(r2);
-                        const float sig = r.sg[s] + psg;
-                        const float tt = sig * sig * ir2;
-                        const float t3 = tt * tt * tt;
-                        const float e4 = r.se[s] * pse;
-                        const float C = r.qs[s] * pqs;
-                        if constexpr (ENERGY) {
-                            const float uc = (DIEL == 1) ? 0.5f * C * ir2 : C * rsq_(r2);
-                            eacc += (double)(e4 * t3 * (t3 - 1.f) + uc);
-                        } else {
-                            // g = (e4 t3 (12 t3 - 6) + C c) / r^2, c = 1 / r^2 (dielectric 4r)
-                            // or 1 / r (vacuum): the LJ and Coulomb parts share one 1 / r^2
-                            const float w = e4 * t3 * fma_(12.f, t3, -6.f);
-                            const float g = fma_(C, (DIEL == 1) ? ir2 : rsq_(r2), w) * ir2;
-                            r.fx[s] = fma_(g, dx, r.fx[s]);
-                            r.fy[s] = fma_(g, dy, r.fy[s]);
-                            r.fz[s] = fma_(g, dz, r.fz[s]);
-                            pfx = fma_(-g, dx, pfx);
-                            pfy = fma_(-g, dy, pfy);
-                            pfz = fma_(-g, dz, pfz);
-                        }
-                    } else if (s < t || (k >= 1 && k <= 32)) {
-                        bool skip = ((ex[s] >> pid) & 1ull) != 0ull;
-                        if (s == t && k == 32 && pid < lane)
-                            skip = true;
-                        const bool is14 = ((s4[s] >> pid) & 1ull) != 0ull;
-                        const float dx = r.x[s] - px, dy = r.y[s] - py, dz = r.z[s] - pz;
-                        const float r2 = dx * dx + dy * dy + dz * dz;
-                        const float ir2 = rcp_(r2);
-                        const float sig = r.sg[s] + psg;
-                        const float tt = sig * sig * ir2;
-                        const float t3 = tt * tt * tt;
-                        const float e4 = r.se[s] * pse;       // 4 eps_ij
-                        const float C = r.qs[s] * pqs;        // Coulomb factor of the pair
+                    if (!(s < t || (k >= 1 && k <= 32)))
+                        continue;
+                    const float dx = r.x[s] - px, dy = r.y[s] - py, dz = r.z[s] - pz;
+                    const float r2 = dx * dx + dy * dy + dz * dz;
+                    const float ir2 = rcp_(r2);
+                    const float ir6 = ir2 * ir2 * ir2;
+                    const float C = r.qs[s] * pqs;   // Coulomb factor of the pair
+                    const float cc = (DIEL == 1) ? ir2 : rsq_(r2);   // Coulomb r-dependence over r^2
+                    // g: force on the own atom = g (x_own - x_partner), on the partner
+                    // -g (...); u: pair energy.  Only the factors differ between the
+                    // plain and the masked step, the updates below are shared.
+                    float g = 0.f, u = 0.f;
+                    if (!((smask[s] >> k) & 1ull)) {
+                        if constexpr (ENERGY)
+                            u = ir6 * fma_(ab[s].x * (1.f / 12.f), ir6, ab[s].y * (1.f / 6.f)) +
+                                ((DIEL == 1) ? 0.5f * C * ir2 : C * cc);
+                        else
+                            // g = (12 c12 / r^12 - 6 c6 / r^6 + C c) / r^2, c = 1 / r^2
+                            // (dielectric 4r) or 1 / r (vacuum)
+                            g = fma_(C, cc, ir6 * fma_(ab[s].x, ir6, ab[s].y)) * ir2;
+                    } else {
+                        // the same-slot pair at k = 32 is met from both of its lanes:
+                        // the upper half of the wave leaves it to the lower
+                        const bool skip = (exw[s][h] & bit) != 0u || (s == t && k == 32 && lane >= 32);
+                        const bool is14 = (s4w[s][h] & bit) != 0u;
                         const float slj = is14 ? s14lj : 1.f;
                         const float sc = is14 ? s14c : 1.f;
                         if constexpr (ENERGY) {
-                            const float ulj = e4 * t3 * (t3 - 1.f);
-                            const float uc = (DIEL == 1) ? 0.5f * C * ir2 : C * rsq_(r2);
-                            const float u = slj * ulj + sc * uc;
-                            eacc += skip ? 0.0 : (double)u;
+                            const float ulj = ir6 * fma_(ab[s].x * (1.f / 12.f), ir6, ab[s].y * (1.f / 6.f));
+                            const float uc = (DIEL == 1) ? 0.5f * C * ir2 : C * cc;
+                            u = skip ? 0.f : slj * ulj + sc * uc;
                         } else {
-                            // force on the own atom = g (x_own - x_partner), on the partner -g (...)
-                            const float w = e4 * t3 * fma_(12.f, t3, -6.f);
-                            float g = fma_(sc * C, (DIEL == 1) ? ir2 : rsq_(r2), slj * w) * ir2;
-                            g = skip ? 0.f : g;
-                            r.fx[s] += g * dx;
-                            r.fy[s] += g * dy;
-                            r.fz[s] += g * dz;
-                            pfx -= g * dx;
-                            pfy -= g * dy;
-                            pfz -= g * dz;
+                            const float gg = fma_(sc * C, cc, slj * (ir6 * fma_(ab[s].x, ir6, ab[s].y))) * ir2;
+                            g = skip ? 0.f : gg;
                         }
+                    }
+                    if constexpr (ENERGY) {
+                        eacc += (double)u;
+                    } else {
+                        r.fx[s] = fma_(g, dx, r.fx[s]);
+                        r.fy[s] = fma_(g, dy, r.fy[s]);
+                        r.fz[s] = fma_(g, dz, r.fz[s]);
+                        pfx = fma_(-g, dx, pfx);
+                        pfy = fma_(-g, dy, pfy);
+                        pfz = fma_(-g, dz, pfz);
+                        // the sums are formed here (an empty asm that reads and writes
+                        // them): deferring the updates keeps every slot's displacement
+                        // and factor live and spills
+                        asm volatile("" : "+v"(r.fx[s]), "+v"(r.fy[s]), "+v"(r.fz[s]), "+v"(pfx), "+v"(pfy),
+                                     "+v"(pfz));
                     }
                 }
                 px = wave_rol1(px);
                 py = wave_rol1(py);
                 pz = wave_rol1(pz);
-                psg = wave_rol1(psg);
-                pse = wave_rol1(pse);
+                pcl = wave_rol1(pcl);
                 pqs = wave_rol1(pqs);
                 if constexpr (!ENERGY) {
                     pfx = wave_rol1(pfx);
                     pfy = wave_rol1(pfy);
                     pfz = wave_rol1(pfz);
                 }
-                pid = wave_rol1(pid);
-            }
+            };
+            for (int k = 0; k < 32; ++k)
+                ring_step(k, 0);
+            for (int k = 32; k < kend; ++k)
+                ring_step(k, 1);
             if constexpr (!ENERGY) {
-                const int j = kWide * t + pid;
+                // the travelling copy's atom after kend rotations
+                const int j = kWide * t + ((lane + kend) & (kWide - 1));
                 if (j < n) {
                     frc[3 * j] += pfx;
                     frc[3 * j + 1] += pfy;
@@ -1334,17 +1360,17 @@ __device__ __forceinline__ void wide_load(WideRegs& r, const RunDev<float>& d, c
             r.vx[s] = slab[3 * npad + a];
             r.vy[s] = slab[4 * npad + a];
             r.vz[s] = slab[5 * npad + a];
-            const float4 p = d.apar4[a];
-            r.sg[s] = p.x;
-            r.se[s] = p.y;
-            r.qs[s] = p.z;
+            const float2 p = d.apar2[a];
+            r.qs[s] = p.x;
+            r.ci[s] = (int)p.y * (kLjStride * (int)sizeof(float2));
         } else {
-            // padding atoms: fixed, far apart, every pair excluded by the masks
+            // padding atoms: fixed, far apart, zero pair parameters (zero LJ class)
             r.x[s] = (float)(1000 + 10 * a);
             r.y[s] = 1000.f;
             r.z[s] = 1000.f;
             r.vx[s] = r.vy[s] = r.vz[s] = 0.f;
-            r.sg[s] = r.se[s] = r.qs[s] = 0.f;
+            r.qs[s] = 0.f;
+            r.ci[s] = (kLjClasses - 1) * kLjStride * (int)sizeof(float2);
         }
     }
 }
@@ -1370,6 +1396,8 @@ __device__ __forceinline__ void wide_store(const WideRegs& r, const RunDev<float
 // hands out (run, replica) items, runs in decreasing order of pair work
 // (`order`), replicas of a run in slot order.  n_steps velocity-Verlet steps
 // with Andersen collisions, then E_pot (FP64 sum) and E_kin of the final state.
+// LDS: per wave the position and force stage [2][nmax][3]; after those, per
+// wave its copy of its current run's LJ class table.
 template <int DIEL, int LANG>
 __global__ __launch_bounds__(256, 3) void k_md_wide(const RunDev<float>* runs, const int32_t* order, int n_runs,
                                                   int32_t* counter, int nmax, int n_steps)
@@ -1378,8 +1406,11 @@ __global__ __launch_bounds__(256, 3) void k_md_wide(const RunDev<float>* runs, c
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     float* pos = reinterpret_cast<float*>(smem) + (size_t)wave * 6 * nmax;
     float* frc = pos + 3 * nmax;
+    float2* lj = reinterpret_cast<float2*>(reinterpret_cast<float*>(smem) + (size_t)(blockDim.x >> 6) * 6 * nmax) +
+                 wave * kLjClasses * kLjStride;
     for (int i = lane; i < 3 * nmax; i += kWide)
         frc[i] = 0.f;
+    int lj_run = -1;   // run whose class table the wave holds
     for (;;) {
         int g = 0;
         if (lane == 0)
@@ -1401,6 +1432,10 @@ __global__ __launch_bounds__(256, 3) void k_md_wide(const RunDev<float>* runs, c
         if (k < 0)
             break;
         const RunDev<float>& d = runs[k];
+        if (k != lj_run) {
+            wide_load_ljtab(d, lj, lane);
+            lj_run = k;
+        }
         const int nsl = (d.n + kWide - 1) / kWide;
         const int npad = kWide * nsl;
         const RunCtl* ctl = d.ctl;
@@ -1420,7 +1455,7 @@ __global__ __launch_bounds__(256, 3) void k_md_wide(const RunDev<float>* runs, c
         wide_load(r, d, slab, lane, nsl);
         double unused = 0.0;
         for (int st = 0; st <= n_steps; ++st) {
-            wide_evaluate<DIEL, false>(r, d, pos, frc, lane, nsl, unused);
+            wide_evaluate<DIEL, false>(r, d, pos, frc, lj, lane, nsl, unused);
             if (st > 0) {
 #pragma unroll
                 for (int s = 0; s < kWideSlots; ++s) {
@@ -1495,7 +1530,7 @@ __global__ __launch_bounds__(256, 3) void k_md_wide(const RunDev<float>* runs, c
             }
         }
         double ep = 0.0, ek = 0.0;
-        wide_evaluate<DIEL, true>(r, d, pos, frc, lane, nsl, ep);
+        wide_evaluate<DIEL, true>(r, d, pos, frc, lj, lane, nsl, ep);
 #pragma unroll
         for (int s = 0; s < kWideSlots; ++s) {
             const int a = kWide * s + lane;
@@ -1548,18 +1583,21 @@ __global__ __launch_bounds__(512) void k_forces_wide(RunDev<float> d, int64_t r0
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     float* pos = reinterpret_cast<float*>(smem) + (size_t)wave * 6 * nmax;
     float* frc = pos + 3 * nmax;
+    float2* lj = reinterpret_cast<float2*>(reinterpret_cast<float*>(smem) + (size_t)(blockDim.x >> 6) * 6 * nmax) +
+                 wave * kLjClasses * kLjStride;
     for (int i = lane; i < 3 * nmax; i += kWide)
         frc[i] = 0.f;
     const int k = blockIdx.x * (blockDim.x >> 6) + wave;
     if (k >= count)
         return;
+    wide_load_ljtab(d, lj, lane);
     const int nsl = (d.n + kWide - 1) / kWide;
     const float* slab = d.slab[d.ctl->cur] + (size_t)(r0 + k) * 6 * kWide * nsl;
     WideRegs r;
     wide_load(r, d, slab, lane, nsl);
     double unused = 0.0, ep = 0.0;
-    wide_evaluate<DIEL, false>(r, d, pos, frc, lane, nsl, unused);
-    wide_evaluate<DIEL, true>(r, d, pos, frc, lane, nsl, ep);
+    wide_evaluate<DIEL, false>(r, d, pos, frc, lj, lane, nsl, unused);
+    wide_evaluate<DIEL, true>(r, d, pos, frc, lj, lane, nsl, ep);
     ep = wave_sum(ep);
     double* o = d.dbg + (size_t)k * d.npad * 4;
 #pragma unroll
@@ -1740,7 +1778,10 @@ hipError_t launch_export(const RunDev<float>& d, int64_t r0, int64_t count, floa
     PAMD_DISPATCH(float, d.nslot, d.dielectric, CALL)
 #undef CALL
 }
-size_t wide_lds_bytes(int nmax, int waves) { return (size_t)waves * 6 * nmax * sizeof(float); }
+size_t wide_lds_bytes(int nmax, int waves)
+{
+    return (size_t)waves * (6 * nmax * sizeof(float) + kLjClasses * kLjStride * sizeof(float2));
+}
 
 hipError_t wide_setup(int diel, int nmax, int waves, int* blocks_per_cu)
 {

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "pamd.h"
+
 namespace pamd {
 
 constexpr int kRow = 16;            // lanes per replica (one DPP row)
@@ -15,6 +17,15 @@ constexpr int kMaxSched = 4096;  // temperatures a device schedule can hold
 constexpr int kWide = 64;
 constexpr int kWideSlots = 5;
 constexpr int kWideMaxAtoms = kWide * kWideSlots;
+// LJ class table of the wide layout: the pair coefficients of every pair of
+// distinct per-atom (sigma, epsilon) values (a molecule in the wide layout has
+// at most kLjClasses - 1 of them); class kLjClasses - 1 is all zero (padding
+// atoms).  Rows are kLjStride float2 apart so consecutive rows start in
+// different banks.  At 320 atoms and four waves per workgroup the position /
+// force stages and the per-wave tables of three workgroups fit one CU's LDS.
+constexpr int kLjClasses = PAMD_WIDE_LJ_CLASSES + 1;
+constexpr int kLjStride = kLjClasses + 1;
+static_assert(kLjStride % 2 == 1, "odd row stride: consecutive rows start in different banks");
 
 // Number of tile steps of the all-pairs schedule for `nslot` blocks of 16 atoms:
 // each diagonal block takes 8 row rotations (k = 1..8, k = 8 half-masked),
@@ -100,10 +111,11 @@ struct RunDev {
     int32_t resampling;     // PAMD_RESAMPLE_*
     int32_t thermostat;     // PAMD_THERMOSTAT_*
     double lc1, lc2;        // Langevin: exp(-gamma dt), sqrt(1 - exp(-2 gamma dt))
-    // wide layout only: per-atom (sigma / 2, 2 sqrt(eps), q sqrt(k_e c), 0) with
-    // c = 1/2 for eps = 4r and 1 in vacuum, and per (atom, 32-atom chunk) the
-    // bit masks (excluded pair incl. self, scaled 1-4 pair)
-    const float4* apar4;    // [n]
+    // wide layout only: per-atom (q sqrt(k_e c), LJ class) with c = 1/2 for
+    // eps = 4r and 1 in vacuum, the LJ class table, and per (atom, 32-atom
+    // chunk) the bit masks (excluded pair incl. self, scaled 1-4 pair)
+    const float2* apar2;    // [n]
+    const float2* ljtab;    // [kLjClasses][kLjStride] (12 c12, -6 c6) of class pairs (a, b)
     const uint2* pmask;     // [n][nchunk]
     const uint64_t* stepmask;   // [t][s] (5 x 5): bit k set when some lane of own slot s meets an
                                 // excluded or 1-4 partner of slot t at rotation step k

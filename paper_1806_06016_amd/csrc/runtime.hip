@@ -87,7 +87,8 @@ struct Carver {
 struct HostTables {
     int n = 0, npad = 0, nslot = 0;
     int wide = 0, nchunk = 0;
-    std::vector<double> atomp;           // wide layout: [n][4] per-atom pair parameters
+    std::vector<double> atomp;           // wide layout: [n][2] per-atom Coulomb factor and LJ class
+    std::vector<double> lj;              // wide layout: [kLjClasses][kLjStride][2] LJ class table
     std::vector<uint32_t> pmask;         // wide layout: [n][nchunk][2] exclusion / 1-4 bits
     std::vector<uint64_t> stepmask;      // wide layout: [t][s] rotation steps that need the masks
     std::vector<double> ab, c;           // [steps][16][2], [steps][16]
@@ -180,6 +181,26 @@ int run_is_wide(const pamd_system* sys, const pamd_params* p, int n_runs, int r)
         if (sys[q].n_atoms > PAMD_TILE_ATOMS)
             return 1;
     return 0;
+}
+
+// LJ classes: the distinct per-atom (sigma, epsilon) values in order of first
+// appearance; cls[a] = class of atom a.  Returns the number of classes.
+int lj_classes(const pamd_system& s, std::vector<int>* cls)
+{
+    std::vector<std::pair<double, double>> seen;
+    if (cls)
+        cls->assign(s.n_atoms, 0);
+    for (int a = 0; a < s.n_atoms; ++a) {
+        const std::pair<double, double> v(s.sigma[a], s.epsilon[a]);
+        int k = 0;
+        while (k < (int)seen.size() && seen[k] != v)
+            ++k;
+        if (k == (int)seen.size())
+            seen.push_back(v);
+        if (cls)
+            (*cls)[a] = k;
+    }
+    return (int)seen.size();
 }
 
 // graph distance (capped at 4) between every pair of atoms of the bond graph
@@ -825,16 +846,29 @@ void build_tables(const pamd_system& s, HostTables& t, int wide)
                     coef(st, l, 16 * I + l, 16 * J + ((l - k) & 15));
     }
     if (wide) {
-        // per-atom factors of the pair parameters: sigma_ij = sg_i + sg_j,
-        // 4 eps_ij = se_i se_j, Coulomb factor = qs_i qs_j
+        // per-atom Coulomb factor (Coulomb factor of a pair = qs_i qs_j) and
+        // LJ class; the class table holds 12 c12 and -6 c6 of every class
+        // pair, combined as for the per-pair tables above (the padding class
+        // stays zero; pamd_query_sizes has checked the class count)
         const double cf = (s.dielectric == PAMD_DIELECTRIC_4R) ? 0.5 : 1.0;
         t.nchunk = (n + 31) / 32;
-        t.atomp.assign((size_t)n * 4, 0.0);
+        t.atomp.assign((size_t)n * 2, 0.0);
         t.pmask.assign((size_t)n * t.nchunk * 2, 0u);
+        std::vector<int> cls;
+        lj_classes(s, &cls);
+        t.lj.assign((size_t)kLjClasses * kLjStride * 2, 0.0);
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                const double sig = 0.5 * (s.sigma[i] + s.sigma[j]);
+                const double eps = sqrt(s.epsilon[i] * s.epsilon[j]);
+                const double s6 = pow(sig, 6.0);
+                const size_t e = ((size_t)cls[i] * kLjStride + cls[j]) * 2;
+                t.lj[e] = 12.0 * 4.0 * eps * s6 * s6;
+                t.lj[e + 1] = -6.0 * 4.0 * eps * s6;
+            }
         for (int i = 0; i < n; ++i) {
-            t.atomp[4 * i] = 0.5 * s.sigma[i];
-            t.atomp[4 * i + 1] = 2.0 * sqrt(s.epsilon[i]);
-            t.atomp[4 * i + 2] = s.charge[i] * sqrt(s.coulomb_k * cf);
+            t.atomp[2 * i] = s.charge[i] * sqrt(s.coulomb_k * cf);
+            t.atomp[2 * i + 1] = cls[i];
             for (int j = 0; j < n; ++j) {
                 const int g = dist[(size_t)i * n + j];
                 const size_t w = ((size_t)i * t.nchunk + j / 32) * 2;
@@ -952,7 +986,8 @@ void carve(Carver& st, Carver& wk, const pamd_system& s, const pamd_params& p, i
     d.resampling = p.resampling;
     d.wide = wide;
     d.nchunk = wide ? nchunk : 0;
-    d.apar4 = wide ? wk.take<float4>(n) : nullptr;
+    d.apar2 = wide ? wk.take<float2>(n) : nullptr;
+    d.ljtab = wide ? wk.take<float2>((size_t)kLjClasses * kLjStride) : nullptr;
     d.pmask = wide ? wk.take<uint2>((size_t)n * nchunk) : nullptr;
     d.stepmask = wide ? wk.take<uint64_t>((size_t)kWideSlots * kWideSlots) : nullptr;
     d.s14lj = (float)s.scale14_lj;
@@ -986,7 +1021,11 @@ hipError_t upload(const RunDev<real>& d, const HostTables& t, hipStream_t s)
     if (!t.c.empty() && (e = up(d.nb_c, t.c)) != hipSuccess) return e;
     if (t.wide) {
         std::vector<float> ap(t.atomp.begin(), t.atomp.end());
-        if ((e = hipMemcpyAsync((void*)d.apar4, ap.data(), ap.size() * sizeof(float), hipMemcpyHostToDevice, s)) !=
+        if ((e = hipMemcpyAsync((void*)d.apar2, ap.data(), ap.size() * sizeof(float), hipMemcpyHostToDevice, s)) !=
+            hipSuccess)
+            return e;
+        std::vector<float> lj(t.lj.begin(), t.lj.end());
+        if ((e = hipMemcpyAsync((void*)d.ljtab, lj.data(), lj.size() * sizeof(float), hipMemcpyHostToDevice, s)) !=
             hipSuccess)
             return e;
         if ((e = hipMemcpyAsync((void*)d.pmask, t.pmask.data(), t.pmask.size() * sizeof(uint32_t),
@@ -1099,6 +1138,9 @@ pamd_status pamd_query_sizes(const pamd_system* sys, int32_t n_runs, const pamd_
         pamd_status st = validate(nullptr, sys[r], p[r], fp32);
         if (st != PAMD_OK)
             return st;
+        // the wide kernels read LJ pair coefficients from a class table
+        if (run_is_wide(sys, p, n_runs, r) && lj_classes(sys[r], nullptr) > kLjClasses - 1)
+            return PAMD_ERR_ARG;
     }
     return layout(sys, n_runs, p, nullptr, nullptr, nullptr, state_bytes, work_bytes, nullptr);
 }

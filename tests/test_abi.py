@@ -111,6 +111,15 @@ def test_query_sizes_is_host_only_and_validates():
     s4.n_atoms = B.MAX_ATOMS + 1               # beyond the wide layout
     assert lib.pamd_query_sizes(ctypes.byref(s4), 1, ctypes.byref(p), ctypes.byref(sb),
                                 ctypes.byref(wb)) == B.PAMD_ERR_ARG
+    # the wide kernels' LJ class table holds 25 distinct (sigma, epsilon) pairs;
+    # the register-tile layout (per-pair tables) takes any number
+    for n, k, want in [(120, 25, 0), (120, 26, B.PAMD_ERR_ARG), (75, 26, 0), (75, 75, 0)]:
+        m = S.make_peptide(1806, n)
+        m.sigma = 0.3 * (1.0 + 1e-3 * (np.arange(n) % k))
+        m.epsilon = np.full(n, 0.5)
+        sm = B.make_system_struct(m, keep)
+        assert lib.pamd_query_sizes(ctypes.byref(sm), 1, ctypes.byref(p), ctypes.byref(sb),
+                                    ctypes.byref(wb)) == want, (n, k)
 
 
 def test_binding_fails_loudly_without_library(tmp_path):

@@ -256,3 +256,53 @@ def test_autotuner_picks_a_layout_and_wide_launch_shape(B):
     p.md_steps(5)
     assert p.observables()[1]["step"] == 5
     p.close()
+
+
+def _with_lj_classes(sysd, k):
+    """A copy of `sysd` whose atoms carry exactly k distinct (sigma, epsilon)
+    pairs: the atoms of its most common pair are split into sub-classes by
+    relative sigma changes of 1e-4 j (the molecule's geometry stays valid)."""
+    import collections
+    import dataclasses
+    pairs = list(zip(sysd.sigma.tolist(), sysd.epsilon.tolist()))
+    n0 = len(set(pairs))
+    top = collections.Counter(pairs).most_common(1)[0][0]
+    idx = [a for a, q in enumerate(pairs) if q == top]
+    m = k - n0 + 1
+    assert 1 <= m <= len(idx)
+    sig = sysd.sigma.copy()
+    for j, a in enumerate(idx):
+        sig[a] = top[0] * (1.0 + 1e-4 * (j % m))
+    out = dataclasses.replace(sysd, sigma=sig)
+    assert len(set(zip(out.sigma.tolist(), out.epsilon.tolist()))) == k
+    return out
+
+
+def test_lj_class_table_at_its_capacity(B):
+    """A 120-atom molecule with 25 distinct LJ parameter pairs, the most the
+    wide kernels' class table holds (one more class, all zero, serves the
+    padding atoms): the launch's LDS holds the table after the position and
+    force stages, and forces and a 50-step trajectory match the oracle."""
+    sysd = _with_lj_classes(_peptide(1807, 120), 25)
+    R, T, nu, seed = 9, 700.0, 1.0, 5
+    print("LJ classes 25", flush=True)
+    p = B.Pamd([sysd], R_target=R, T0=T, dt=0.001, nu=nu, seed=seed, precision=B.PAMD_FP32)
+    info = p.run_launch(0)
+    assert info["layout"] == "wide"
+    assert info["lds_bytes"] == info["waves_per_block"] * (6 * sysd.n_atoms * 4 + 26 * 27 * 8)
+    osys = O.OracleSystem(sysd)
+    x = _perturbed(sysd, R, 0.003, 2)
+    v = O.init_velocities(osys, R, T, seed=4)
+    p.set_state(0, x, v, T=T)
+    xo, vo = as_stored(x, True), as_stored(v, True)
+    F, E = p.get_forces(0)
+    Eo, Fo, terms = O.energy_forces(osys, xo, want_terms=True)
+    frms = np.sqrt((Fo ** 2).sum(-1).mean(-1))[:, None]
+    assert (np.linalg.norm(F - Fo, axis=-1) <= 1e-4 * (np.linalg.norm(Fo, axis=-1) + frms)).all()
+    assert np.all(np.abs(E - Eo) <= 1e-5 * np.abs(terms).sum(1))
+    p.md_steps(50)
+    Ep, Ek = O.md_steps(osys, xo, vo, 50, T, 0.001, nu, seed, step0=0)
+    g = p.get_state(0)
+    assert np.abs(g["x"] - xo).max() < 1e-4
+    assert np.abs(g["E_pot"] - Ep).max() <= 1e-3 * np.abs(Ep).mean()
+    p.close()
