@@ -176,6 +176,7 @@ def batched(args):
     info = dict(p.launch_info(), runs=[dict(atoms=s.n_atoms, **p.run_launch(r)) for r, s in enumerate(systems)],
                 autotune=tuned)
     stream = torch.cuda.current_stream()
+    calibration_copy(args.copy_mb)
     p.md_steps(args.theta_eq)
     p.observables()
     p.graph_capture(0, "schedule", slot=0, parts="resample")
@@ -228,6 +229,19 @@ def batched(args):
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline_batched(systems, R, args.cpu_seconds)
     return result
+
+
+def calibration_copy(mb):
+    """One device-to-device copy of `mb` MiB: the reference kernel whose HBM
+    counters scale FETCH_SIZE / WRITE_SIZE to bytes (known size)."""
+    if mb <= 0:
+        return
+    import torch
+    src = torch.ones(mb << 20, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
 
 
 def main():
@@ -288,13 +302,7 @@ def main():
              thermostat=args.thermostat)
     info = p.launch_info()
     stream = torch.cuda.current_stream()
-    if args.copy_mb > 0:
-        nbytes = args.copy_mb << 20
-        src = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+    calibration_copy(args.copy_mb)
     # setup (untimed): equilibration at T0; one-time graph captures (slot 0:
     # adaptive resampling, slot 1: theta MD steps), replayed every temperature
     p.md_steps(args.theta_eq)

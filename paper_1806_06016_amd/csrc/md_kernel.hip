@@ -1249,7 +1249,8 @@ __device__ __forceinline__ void wide_evaluate(WideRegs& r, const RunDev<float>& 
                     const float dx = r.x[s] - px, dy = r.y[s] - py, dz = r.z[s] - pz;
                     const float r2 = dx * dx + dy * dy + dz * dz;
                     const float ir2 = rcp_(r2);
-                    const float ir6 = ir2 * ir2 * ir2;
+                    const float ir4 = ir2 * ir2;
+                    const float ir6 = ir4 * ir2;
                     const float C = r.qs[s] * pqs;   // Coulomb factor of the pair
                     const float cc = (DIEL == 1) ? ir2 : rsq_(r2);   // Coulomb r-dependence over r^2
                     // g: force on the own atom = g (x_own - x_partner), on the partner
@@ -1262,8 +1263,12 @@ __device__ __forceinline__ void wide_evaluate(WideRegs& r, const RunDev<float>& 
                                 ((DIEL == 1) ? 0.5f * C * ir2 : C * cc);
                         else
                             // g = (12 c12 / r^12 - 6 c6 / r^6 + C c) / r^2, c = 1 / r^2
-                            // (dielectric 4r) or 1 / r (vacuum)
-                            g = fma_(C, cc, ir6 * fma_(ab[s].x, ir6, ab[s].y)) * ir2;
+                            // (dielectric 4r: ((12 c12 / r^6 - 6 c6) / r^4 + C) / r^4)
+                            // or 1 / r (vacuum)
+                            if constexpr (DIEL == 1)
+                                g = fma_(fma_(ab[s].x, ir6, ab[s].y), ir4, C) * ir4;
+                            else
+                                g = fma_(C, cc, ir6 * fma_(ab[s].x, ir6, ab[s].y)) * ir2;
                     } else {
                         // the same-slot pair at k = 32 is met from both of its lanes:
                         // the upper half of the wave leaves it to the lower
@@ -1276,7 +1281,9 @@ __device__ __forceinline__ void wide_evaluate(WideRegs& r, const RunDev<float>& 
                             const float uc = (DIEL == 1) ? 0.5f * C * ir2 : C * cc;
                             u = skip ? 0.f : slj * ulj + sc * uc;
                         } else {
-                            const float gg = fma_(sc * C, cc, slj * (ir6 * fma_(ab[s].x, ir6, ab[s].y))) * ir2;
+                            const float t = fma_(ab[s].x, ir6, ab[s].y);
+                            const float gg = (DIEL == 1) ? fma_(slj * t, ir4, sc * C) * ir4
+                                                         : fma_(sc * C, cc, slj * (ir6 * t)) * ir2;
                             g = skip ? 0.f : gg;
                         }
                     }
