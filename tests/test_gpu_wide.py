@@ -306,3 +306,29 @@ def test_lj_class_table_at_its_capacity(B):
     assert np.abs(g["x"] - xo).max() < 1e-4
     assert np.abs(g["E_pot"] - Ep).max() <= 1e-3 * np.abs(Ep).mean()
     p.close()
+
+
+@pytest.mark.parametrize("n", [1, 2, 17])
+def test_forced_wide_layout_of_tiny_chains(B, n):
+    """Bead chains of 1, 2 and 17 atoms forced into the wide layout (one LJ
+    class, vacuum 1/r Coulomb, nearly every lane a padding atom): forces and a
+    100-step trajectory against the oracle, as in the register-tile layout."""
+    sysd = S.bead_chain(n, seed=n)
+    R, T, nu, seed = 7, 1.3, 5.0, 11
+    print(f"tiny wide chain n={n}", flush=True)
+    p = B.Pamd([sysd], R_target=R, T0=T, dt=0.002, nu=nu, seed=seed, precision=B.PAMD_FP32, layout="wide")
+    assert p.run_launch(0)["layout"] == "wide"
+    osys = O.OracleSystem(sysd)
+    x = _perturbed(sysd, R, 0.05, 3)
+    v = O.init_velocities(osys, R, T, seed=6)
+    p.set_state(0, x, v, T=T)
+    xo, vo = as_stored(x, True), as_stored(v, True)
+    F, E = p.get_forces(0)
+    Eo, Fo, terms = O.energy_forces(osys, xo, want_terms=True)
+    frms = np.sqrt((Fo ** 2).sum(-1).mean(-1))[:, None]
+    assert (np.linalg.norm(F - Fo, axis=-1) <= 1e-4 * (np.linalg.norm(Fo, axis=-1) + frms) + 1e-12).all()
+    assert np.all(np.abs(E - Eo) <= 1e-5 * np.abs(terms).sum(1) + 1e-12)
+    p.md_steps(100)
+    O.md_steps(osys, xo, vo, 100, T, 0.002, nu, seed, step0=0)
+    assert np.abs(p.get_state(0)["x"] - xo).max() < 1e-4
+    p.close()
