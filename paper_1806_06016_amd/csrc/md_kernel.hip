@@ -300,7 +300,8 @@ __device__ __forceinline__ void add3(real* frc, int a, real fx, real fy, real fz
 // angles of the outer pairs; NO = 3: the three pairs of outer roles 0..2):
 // each bond vector u_a = x_a - x_j is normalised once (e_a), and the force on
 // outer atom a of angle (a, j, c) is -k dth (cos theta e_a - e_c) / (|u_a| sin theta);
-// the centre takes minus the sum.
+// the bonds j - a folded into the group add -k_b (|u_a| - r0) e_a; the centre
+// takes minus the sum.
 template <typename real, bool ENERGY, int NO>
 __device__ __forceinline__ void angle_group(const RunDev<real>& d, const real* pos, real* frc, int t, double& eacc)
 {
@@ -308,20 +309,26 @@ __device__ __forceinline__ void angle_group(const RunDev<real>& d, const real* p
     if (ga.x < 0)
         return;
     const int oa[4] = {ga.y, ga.z, ga.w, NO == 4 ? d.agrp[2 * t + 1].x : -1};
-    const real* par = d.agpar + 12 * t;
+    const real* par = d.agpar + kAngPar * t;
     real pj[3];
     ld3(pos, ga.x, pj);
-    real e[NO][3], iu[NO];
+    real e[NO][3], iu[NO], hb[NO];
 #pragma unroll
     for (int a = 0; a < NO; ++a) {
         real pa[3];
         ld3(pos, oa[a] >= 0 ? oa[a] : ga.x, pa);
         const real ux = pa[0] - pj[0], uy = pa[1] - pj[1], uz = pa[2] - pj[2];
-        // absent outer atoms (their angles carry k = 0): a unit vector along x
-        iu[a] = oa[a] >= 0 ? rsq_(ux * ux + uy * uy + uz * uz) : (real)1;
+        const real u2 = ux * ux + uy * uy + uz * uz;
+        // absent outer atoms (their angles and bond carry k = 0): a unit vector along x
+        iu[a] = oa[a] >= 0 ? rsq_(u2) : (real)1;
         e[a][0] = oa[a] >= 0 ? ux * iu[a] : (real)1;
         e[a][1] = uy * iu[a];
         e[a][2] = uz * iu[a];
+        // bond j - a: U = 1/2 k_b (|u_a| - r0)^2, its force on a is -hb e_a
+        const real kb = par[12 + 2 * a], dr = u2 * iu[a] - par[13 + 2 * a];
+        if constexpr (ENERGY)
+            eacc += (double)((real)0.5 * kb * dr * dr);
+        hb[a] = kb * dr;
     }
     real S[NO][3];
 #pragma unroll
@@ -359,7 +366,9 @@ __device__ __forceinline__ void angle_group(const RunDev<real>& d, const real* p
         real fj[3] = {(real)0, (real)0, (real)0};
 #pragma unroll
         for (int a = 0; a < NO; ++a) {
-            const real fx = -S[a][0] * iu[a], fy = -S[a][1] * iu[a], fz = -S[a][2] * iu[a];
+            const real fx = -fma_(S[a][0], iu[a], hb[a] * e[a][0]);
+            const real fy = -fma_(S[a][1], iu[a], hb[a] * e[a][1]);
+            const real fz = -fma_(S[a][2], iu[a], hb[a] * e[a][2]);
             fj[0] -= fx;
             fj[1] -= fy;
             fj[2] -= fz;
@@ -375,7 +384,7 @@ __device__ __forceinline__ void angle_group(const RunDev<real>& d, const real* p
 template <typename real, bool ENERGY, int W = kRow>
 __device__ __forceinline__ void bonded_terms(const RunDev<real>& d, const real* pos, real* frc, int l16, double& eacc)
 {
-    // bonds: U = 1/2 k (r - r0)^2
+    // bonds no angle group evaluates: U = 1/2 k (r - r0)^2
     for (int t0 = 0; t0 < d.nb; t0 += W) {
         const int t = t0 + l16;
         const int4 ix = d.bidx[t];

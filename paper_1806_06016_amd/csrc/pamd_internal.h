@@ -23,6 +23,8 @@ constexpr int kWideMaxAtoms = kWide * kWideSlots;
 // atoms).  Rows are kLjStride float2 apart so consecutive rows start in
 // different banks.  At 320 atoms and four waves per workgroup the position /
 // force stages and the per-wave tables of three workgroups fit one CU's LDS.
+// parameters per angle group: six angle pairs (k, theta0), four bonds (k_b, r0)
+constexpr int kAngPar = 20;
 constexpr int kLjClasses = PAMD_WIDE_LJ_CLASSES + 1;
 constexpr int kLjStride = kLjClasses + 1;
 static_assert(kLjStride % 2 == 1, "odd row stride: consecutive rows start in different banks");
@@ -85,11 +87,13 @@ struct RunDev {
     // topology / parameters
     const real* nb_ab;      // [steps][16][2]   (12 c12 s, -6 c6 s)
     const real* nb_c;       // [steps][16]      Coulomb coefficient
-    const int4* bidx;       // [nb]   (i, j, -, -)
+    const int4* bidx;       // [nb]   (i, j, -, -) of the bonds no angle group evaluates
     const real* bpar;       // [nb][2] (k, r0)
     const int4* agrp;       // [nag][2] angle groups: (j, o0, o1, o2), (o3, -, -, -), -1 = none;
                             // slots [0, nag6) hold four outer atoms, the rest at most three (o0..o2)
-    const real* agpar;      // [nag][6][2] (k, theta0) of the outer pairs (0,1) (0,2) (0,3) (1,2) (1,3) (2,3)
+    const real* agpar;      // [nag][kAngPar]: (k, theta0) of the outer pairs (0,1) (0,2) (0,3) (1,2)
+                            // (1,3) (2,3), then (k_b, r0) of the bond centre - outer atom a, a = 0..3
+                            // (k_b = 0 where the bond is another group's or a bond pass's)
     const int4* dgrp;       // [ng][2] dihedral groups: (j, k, i0, i1), (i2, l0, l1, l2), -1 = none
     const real* dgpar;      // [ng][9][5] (k cos(delta), n, c0, c1, c2) of (i_a, l_c) at 3 a + c, with
                             // k cos(delta) n U_{n-1}(c) = c0 + c1 c + c2 c^2 when n <= 3

@@ -628,6 +628,7 @@ struct AngGroup {
     int j, no;
     int o[4];
     int term[4][4];   // angle index of outer pair (a, c), a < c, or -1
+    int bond[4];      // bond term j - o[a] evaluated with the group, or -1
 };
 
 static int pair_slot(int a, int c)
@@ -676,10 +677,49 @@ static std::vector<AngGroup> angle_groups(const pamd_system& s)
                 for (int c = 0; c < 4; ++c)
                     G.term[a][c] = -1;
             G.term[0][1] = G.term[1][0] = q;
+            G.bond[0] = G.bond[1] = G.bond[2] = G.bond[3] = -1;
             g.push_back(G);
         }
     }
+    // every bond j - a of a group's centre and one of its outer atoms is
+    // evaluated with that group (it has the bond vector and its length); each
+    // bond term once, the first group and outer role found
+    for (int q = 0; q < s.n_bonds; ++q) {
+        const int i = s.bond_idx[2 * q], k = s.bond_idx[2 * q + 1];
+        bool done = false;
+        for (AngGroup& G : g) {
+            for (int a = 0; a < G.no && !done; ++a)
+                if (G.bond[a] < 0 && ((G.j == i && G.o[a] == k) || (G.j == k && G.o[a] == i))) {
+                    G.bond[a] = q;
+                    done = true;
+                }
+            if (done)
+                break;
+        }
+    }
     return g;
+}
+
+// bond terms no angle group evaluates (the bond passes): indices and parameters
+static void orphan_bonds(const pamd_system& s, std::vector<int32_t>& idx, std::vector<double>& k,
+                         std::vector<double>& r0)
+{
+    std::vector<char> folded(s.n_bonds, 0);
+    if (s.n_angles > 0)
+        for (const AngGroup& G : angle_groups(s))
+            for (int a = 0; a < G.no; ++a)
+                if (G.bond[a] >= 0)
+                    folded[G.bond[a]] = 1;
+    idx.clear();
+    k.clear();
+    r0.clear();
+    for (int q = 0; q < s.n_bonds; ++q)
+        if (!folded[q]) {
+            idx.push_back(s.bond_idx[2 * q]);
+            idx.push_back(s.bond_idx[2 * q + 1]);
+            k.push_back(s.bond_k[q]);
+            r0.push_back(s.bond_r0[q]);
+        }
 }
 
 static std::vector<std::vector<std::pair<int, std::array<int, 4>>>> pack_angle_passes(
@@ -776,17 +816,22 @@ int pack_angle_groups(const pamd_system& s, int W, std::vector<int32_t>* rec, st
     const int slots = (int)best.size() * W;
     if (rec && par) {
         rec->assign((size_t)slots * 8, -1);
-        par->assign((size_t)slots * 12, 0.0);
+        par->assign((size_t)slots * kAngPar, 0.0);
         for (size_t b = 0; b < best.size(); ++b)
             for (size_t q = 0; q < best[b].size(); ++q) {
                 const AngGroup& G = g[best[b][q].first];
                 const std::array<int, 4>& perm = best[b][q].second;
                 const size_t sl = b * W + q;
                 int32_t* r = rec->data() + sl * 8;
-                double* pp = par->data() + sl * 12;
+                double* pp = par->data() + sl * kAngPar;
                 r[0] = G.j;
-                for (int a = 0; a < G.no; ++a)
+                for (int a = 0; a < G.no; ++a) {
                     r[1 + perm[a]] = G.o[a];
+                    if (G.bond[a] >= 0) {
+                        pp[12 + 2 * perm[a]] = s.bond_k[G.bond[a]];
+                        pp[13 + 2 * perm[a]] = s.bond_r0[G.bond[a]];
+                    }
+                }
                 for (int a = 0; a < G.no; ++a)
                     for (int c = a + 1; c < G.no; ++c) {
                         const int t = G.term[a][c];
@@ -896,7 +941,10 @@ void build_tables(const pamd_system& s, HostTables& t, int wide)
                 t.stepmask[(size_t)tt * kWideSlots + ss] = m;
             }
     }
-    pack_terms(s.n_bonds, 2, s.bond_idx, s.bond_k, s.bond_r0, t.bidx, t.bpar, W);
+    std::vector<int32_t> bi;
+    std::vector<double> bk, br;
+    orphan_bonds(s, bi, bk, br);
+    pack_terms((int)bk.size(), 2, bi.data(), bk.data(), br.data(), t.bidx, t.bpar, W);
     pack_angle_groups(s, W, &t.aidx, &t.apar, &t.n6);
     pack_dihedral_groups(s, W, &t.didx, &t.dpar);
     t.mass.assign(t.npad, 0.0);
@@ -939,7 +987,10 @@ void carve(Carver& st, Carver& wk, const pamd_system& s, const pamd_params& p, i
     std::vector<int32_t> rec;
     std::vector<double> par;
     std::vector<double> zeros(std::max({s.n_bonds, s.n_angles, s.n_dihedrals, 1}), 0.0);
-    pack_terms(s.n_bonds, 2, s.bond_idx, zeros.data(), zeros.data(), rec, par, W);
+    std::vector<int32_t> bi;
+    std::vector<double> bk, br;
+    orphan_bonds(s, bi, bk, br);
+    pack_terms((int)bk.size(), 2, bi.data(), zeros.data(), zeros.data(), rec, par, W);
     const int nb_slots = (int)(rec.size() / 4);
     int na6 = 0;
     const int na_slots = std::max(pack_angle_groups(s, W, nullptr, nullptr, &na6), 1);
@@ -947,7 +998,7 @@ void carve(Carver& st, Carver& wk, const pamd_system& s, const pamd_params& p, i
     d.bidx = wk.take<int4>(nb_slots);
     d.bpar = wk.take<real>((size_t)nb_slots * 2);
     d.agrp = wk.take<int4>((size_t)na_slots * 2);
-    d.agpar = wk.take<real>((size_t)na_slots * 12);
+    d.agpar = wk.take<real>((size_t)na_slots * kAngPar);
     d.dgrp = wk.take<int4>((size_t)nd_slots * 2);
     d.dgpar = wk.take<real>((size_t)nd_slots * 45);
     d.mass = wk.take<double>(npad);
@@ -960,7 +1011,7 @@ void carve(Carver& st, Carver& wk, const pamd_system& s, const pamd_params& p, i
     d.n = n;
     d.npad = npad;
     d.nslot = nslot;
-    d.nb = s.n_bonds > 0 ? nb_slots : 0;
+    d.nb = !bk.empty() ? nb_slots : 0;
     d.nag = s.n_angles > 0 ? na_slots : 0;
     d.nag6 = s.n_angles > 0 ? na6 : 0;
     d.dih_general = 0;
