@@ -28,6 +28,7 @@ RESAMPLING_MODES = {"nearest": PAMD_RESAMPLE_NEAREST, "multinomial": PAMD_RESAMP
 PAMD_FORCE_CHUNK = 256
 MAX_ATOMS = 320
 TILE_ATOMS = 80
+WIDE_LJ_CLASSES = 25   # distinct (sigma, epsilon) pairs of one molecule in the wide layout
 
 
 class PamdError(RuntimeError):
@@ -328,8 +329,19 @@ class Pamd:
             prm.append(p)
         self._prm = P(*prm)
         sb, wb = C.c_size_t(), C.c_size_t()
-        self._check(self.lib.pamd_query_sizes(C.byref(self._sys), self.n_runs, C.byref(self._prm),
-                                              C.byref(sb), C.byref(wb)), None)
+        st = self.lib.pamd_query_sizes(C.byref(self._sys), self.n_runs, C.byref(self._prm), C.byref(sb), C.byref(wb))
+        if st == PAMD_ERR_ARG:
+            def wide(r):   # the library's layout choice of run r
+                lay = layout if isinstance(layout, str) else layout[r]
+                if not self.fp32 or lay == "tile":
+                    return False
+                return lay == "wide" or any(n > TILE_ATOMS for n in self.n_atoms)
+            many = [r for r, sd in enumerate(self.systems) if wide(r) and len(
+                set(zip(np.asarray(sd.sigma).tolist(), np.asarray(sd.epsilon).tolist()))) > WIDE_LJ_CLASSES]
+            if many:
+                raise PamdError(st, f"runs {many}: the wide layout takes at most {WIDE_LJ_CLASSES} distinct "
+                                    "(sigma, epsilon) pairs per molecule")
+        self._check(st, None)
         self.state_bytes, self.work_bytes = sb.value, wb.value
         self.d_state = torch.empty(self.state_bytes + 256, dtype=torch.uint8, device="cuda")
         self.d_work = torch.empty(self.work_bytes + 256, dtype=torch.uint8, device="cuda")

@@ -113,7 +113,7 @@ def test_query_sizes_is_host_only_and_validates():
                                 ctypes.byref(wb)) == B.PAMD_ERR_ARG
     # the wide kernels' LJ class table holds 25 distinct (sigma, epsilon) pairs;
     # the register-tile layout (per-pair tables) takes any number
-    for n, k, want in [(120, 25, 0), (120, 26, B.PAMD_ERR_ARG), (75, 26, 0), (75, 75, 0)]:
+    for n, k, want in [(120, B.WIDE_LJ_CLASSES, 0), (120, B.WIDE_LJ_CLASSES + 1, B.PAMD_ERR_ARG), (75, 26, 0), (75, 75, 0)]:
         m = S.make_peptide(1806, n)
         m.sigma = 0.3 * (1.0 + 1e-3 * (np.arange(n) % k))
         m.epsilon = np.full(n, 0.5)
