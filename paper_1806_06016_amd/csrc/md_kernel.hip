@@ -1155,13 +1155,13 @@ struct WideRegs {
     float vx[kWideSlots], vy[kWideSlots], vz[kWideSlots];
     float fx[kWideSlots], fy[kWideSlots], fz[kWideSlots];
     float qs[kWideSlots];   // own atoms' Coulomb factors
-    int ci[kWideSlots];     // byte offset of the own atom's row of the LJ class table
+    int cl[kWideSlots];     // own atoms' LJ classes
 };
 
-// a wave's copy of its run's LJ class table
-__device__ __forceinline__ void wide_load_ljtab(const RunDev<float>& d, float2* lj, int lane)
+// a wave's copy of its run's LJ class table (ljsz float2)
+__device__ __forceinline__ void wide_load_ljtab(const RunDev<float>& d, float2* lj, int lane, int ljsz)
 {
-    for (int i = lane; i < kLjClasses * kLjStride; i += kWide)
+    for (int i = lane; i < ljsz; i += kWide)
         lj[i] = d.ljtab[i];
     wave_sync();
 }
@@ -1201,11 +1201,12 @@ __device__ __forceinline__ void wide_evaluate(WideRegs& r, const RunDev<float>& 
     // sums are added to the LDS force stage at the end (distinct atoms per lane).
     const float s14lj = d.s14lj, s14c = d.s14c;
     const char* ljb = reinterpret_cast<const char*>(lj);
+    const int row8 = d.lj_stride * (int)sizeof(float2);   // bytes per class-table row
 #pragma unroll
     for (int t = 0; t < kWideSlots; ++t) {
         if (t < nsl) {
             float px = r.x[t], py = r.y[t], pz = r.z[t], pqs = r.qs[t];
-            int pcl = r.ci[t] / kLjStride;   // byte offset of the partner's column
+            int pcl = r.cl[t] * (int)sizeof(float2);   // byte offset of the partner's column
             float pfx = 0.f, pfy = 0.f, pfz = 0.f;
             // own atoms' exclusion / 1-4 bits over the 64 atoms of slot t,
             // rotated so that bit k is the partner met at step k, split into
@@ -1249,7 +1250,7 @@ __device__ __forceinline__ void wide_evaluate(WideRegs& r, const RunDev<float>& 
                 float2 ab[kWideSlots];
 #pragma unroll
                 for (int s = 0; s <= t; ++s)
-                    ab[s] = *reinterpret_cast<const float2*>(ljb + (r.ci[s] + pcl));
+                    ab[s] = *reinterpret_cast<const float2*>(ljb + (r.cl[s] * row8 + pcl));
                 const uint32_t bit = 1u << (k & 31);
 #pragma unroll
                 for (int s = 0; s <= t; ++s) {
@@ -1378,7 +1379,7 @@ __device__ __forceinline__ void wide_load(WideRegs& r, const RunDev<float>& d, c
             r.vz[s] = slab[5 * npad + a];
             const float2 p = d.apar2[a];
             r.qs[s] = p.x;
-            r.ci[s] = (int)p.y * (kLjStride * (int)sizeof(float2));
+            r.cl[s] = (int)p.y;
         } else {
             // padding atoms: fixed, far apart, zero pair parameters (zero LJ class)
             r.x[s] = (float)(1000 + 10 * a);
@@ -1386,7 +1387,7 @@ __device__ __forceinline__ void wide_load(WideRegs& r, const RunDev<float>& d, c
             r.z[s] = 1000.f;
             r.vx[s] = r.vy[s] = r.vz[s] = 0.f;
             r.qs[s] = 0.f;
-            r.ci[s] = (kLjClasses - 1) * kLjStride * (int)sizeof(float2);
+            r.cl[s] = d.lj_pad;
         }
     }
 }
@@ -1413,17 +1414,18 @@ __device__ __forceinline__ void wide_store(const WideRegs& r, const RunDev<float
 // (`order`), replicas of a run in slot order.  n_steps velocity-Verlet steps
 // with Andersen collisions, then E_pot (FP64 sum) and E_kin of the final state.
 // LDS: per wave the position and force stage [2][nmax][3]; after those, per
-// wave its copy of its current run's LJ class table.
+// wave its copy of its current run's LJ class table (ljsz float2, the
+// context's table shape).  128 VGPRs: four waves per SIMD when the LDS allows.
 template <int DIEL, int LANG>
-__global__ __launch_bounds__(256, 3) void k_md_wide(const RunDev<float>* runs, const int32_t* order, int n_runs,
-                                                  int32_t* counter, int nmax, int n_steps)
+__global__ __launch_bounds__(256, 4) void k_md_wide(const RunDev<float>* runs, const int32_t* order, int n_runs,
+                                                  int32_t* counter, int nmax, int n_steps, int ljsz)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     float* pos = reinterpret_cast<float*>(smem) + (size_t)wave * 6 * nmax;
     float* frc = pos + 3 * nmax;
     float2* lj = reinterpret_cast<float2*>(reinterpret_cast<float*>(smem) + (size_t)(blockDim.x >> 6) * 6 * nmax) +
-                 wave * kLjClasses * kLjStride;
+                 wave * ljsz;
     for (int i = lane; i < 3 * nmax; i += kWide)
         frc[i] = 0.f;
     int lj_run = -1;   // run whose class table the wave holds
@@ -1449,7 +1451,7 @@ __global__ __launch_bounds__(256, 3) void k_md_wide(const RunDev<float>* runs, c
             break;
         const RunDev<float>& d = runs[k];
         if (k != lj_run) {
-            wide_load_ljtab(d, lj, lane);
+            wide_load_ljtab(d, lj, lane, ljsz);
             lj_run = k;
         }
         const int nsl = (d.n + kWide - 1) / kWide;
@@ -1593,20 +1595,20 @@ __global__ void k_wide_finalize(RunDev<float>* runs, const int32_t* order, int n
 
 // forces and energies of replicas [r0, r0 + count) of one wide-layout run
 template <int DIEL>
-__global__ __launch_bounds__(512) void k_forces_wide(RunDev<float> d, int64_t r0, int count, int nmax)
+__global__ __launch_bounds__(512) void k_forces_wide(RunDev<float> d, int64_t r0, int count, int nmax, int ljsz)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     float* pos = reinterpret_cast<float*>(smem) + (size_t)wave * 6 * nmax;
     float* frc = pos + 3 * nmax;
     float2* lj = reinterpret_cast<float2*>(reinterpret_cast<float*>(smem) + (size_t)(blockDim.x >> 6) * 6 * nmax) +
-                 wave * kLjClasses * kLjStride;
+                 wave * ljsz;
     for (int i = lane; i < 3 * nmax; i += kWide)
         frc[i] = 0.f;
     const int k = blockIdx.x * (blockDim.x >> 6) + wave;
     if (k >= count)
         return;
-    wide_load_ljtab(d, lj, lane);
+    wide_load_ljtab(d, lj, lane, ljsz);
     const int nsl = (d.n + kWide - 1) / kWide;
     const float* slab = d.slab[d.ctl->cur] + (size_t)(r0 + k) * 6 * kWide * nsl;
     WideRegs r;
@@ -1794,14 +1796,14 @@ hipError_t launch_export(const RunDev<float>& d, int64_t r0, int64_t count, floa
     PAMD_DISPATCH(float, d.nslot, d.dielectric, CALL)
 #undef CALL
 }
-size_t wide_lds_bytes(int nmax, int waves)
+size_t wide_lds_bytes(int nmax, int waves, int ljsz)
 {
-    return (size_t)waves * (6 * nmax * sizeof(float) + kLjClasses * kLjStride * sizeof(float2));
+    return (size_t)waves * (6 * nmax * sizeof(float) + ljsz * sizeof(float2));
 }
 
-hipError_t wide_setup(int diel, int nmax, int waves, int* blocks_per_cu)
+hipError_t wide_setup(int diel, int nmax, int waves, int ljsz, int* blocks_per_cu)
 {
-    const size_t lds = wide_lds_bytes(nmax, waves);
+    const size_t lds = wide_lds_bytes(nmax, waves, ljsz);
     const void* md = diel ? (const void*)k_md_wide<1, 0> : (const void*)k_md_wide<0, 0>;
     const void* ml = diel ? (const void*)k_md_wide<1, 1> : (const void*)k_md_wide<0, 1>;
     const void* fo = diel ? (const void*)k_forces_wide<1> : (const void*)k_forces_wide<0>;
@@ -1820,16 +1822,16 @@ hipError_t wide_setup(int diel, int nmax, int waves, int* blocks_per_cu)
 }
 
 hipError_t launch_md_wide(const RunDev<float>* runs, const int32_t* order, int n_runs, int32_t* counter, int nmax,
-                          int n_steps, int diel, int lang, int blocks, int waves, hipStream_t s)
+                          int n_steps, int diel, int lang, int ljsz, int blocks, int waves, hipStream_t s)
 {
-    const size_t lds = wide_lds_bytes(nmax, waves);
+    const size_t lds = wide_lds_bytes(nmax, waves, ljsz);
     const dim3 g(blocks), b(waves * 64);
     hipLaunchKernelGGL(k_wide_begin, dim3(1), dim3(64), 0, s, const_cast<RunDev<float>*>(runs), order, n_runs);
     switch (diel * 2 + lang) {
-    case 0: hipLaunchKernelGGL((k_md_wide<0, 0>), g, b, lds, s, runs, order, n_runs, counter, nmax, n_steps); break;
-    case 1: hipLaunchKernelGGL((k_md_wide<0, 1>), g, b, lds, s, runs, order, n_runs, counter, nmax, n_steps); break;
-    case 2: hipLaunchKernelGGL((k_md_wide<1, 0>), g, b, lds, s, runs, order, n_runs, counter, nmax, n_steps); break;
-    default: hipLaunchKernelGGL((k_md_wide<1, 1>), g, b, lds, s, runs, order, n_runs, counter, nmax, n_steps); break;
+    case 0: hipLaunchKernelGGL((k_md_wide<0, 0>), g, b, lds, s, runs, order, n_runs, counter, nmax, n_steps, ljsz); break;
+    case 1: hipLaunchKernelGGL((k_md_wide<0, 1>), g, b, lds, s, runs, order, n_runs, counter, nmax, n_steps, ljsz); break;
+    case 2: hipLaunchKernelGGL((k_md_wide<1, 0>), g, b, lds, s, runs, order, n_runs, counter, nmax, n_steps, ljsz); break;
+    default: hipLaunchKernelGGL((k_md_wide<1, 1>), g, b, lds, s, runs, order, n_runs, counter, nmax, n_steps, ljsz); break;
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
@@ -1839,14 +1841,15 @@ hipError_t launch_md_wide(const RunDev<float>* runs, const int32_t* order, int n
     return hipGetLastError();
 }
 
-hipError_t launch_forces_wide(const RunDev<float>& d, int64_t r0, int count, int nmax, int waves, hipStream_t s)
+hipError_t launch_forces_wide(const RunDev<float>& d, int64_t r0, int count, int nmax, int waves, int ljsz,
+                              hipStream_t s)
 {
-    const size_t lds = wide_lds_bytes(nmax, waves);
+    const size_t lds = wide_lds_bytes(nmax, waves, ljsz);
     const int blocks = (count + waves - 1) / waves;
     if (d.dielectric)
-        hipLaunchKernelGGL(k_forces_wide<1>, dim3(blocks), dim3(waves * 64), lds, s, d, r0, count, nmax);
+        hipLaunchKernelGGL(k_forces_wide<1>, dim3(blocks), dim3(waves * 64), lds, s, d, r0, count, nmax, ljsz);
     else
-        hipLaunchKernelGGL(k_forces_wide<0>, dim3(blocks), dim3(waves * 64), lds, s, d, r0, count, nmax);
+        hipLaunchKernelGGL(k_forces_wide<0>, dim3(blocks), dim3(waves * 64), lds, s, d, r0, count, nmax, ljsz);
     return hipGetLastError();
 }
 

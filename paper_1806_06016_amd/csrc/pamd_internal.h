@@ -17,17 +17,17 @@ constexpr int kMaxSched = 4096;  // temperatures a device schedule can hold
 constexpr int kWide = 64;
 constexpr int kWideSlots = 5;
 constexpr int kWideMaxAtoms = kWide * kWideSlots;
-// LJ class table of the wide layout: the pair coefficients of every pair of
-// distinct per-atom (sigma, epsilon) values (a molecule in the wide layout has
-// at most kLjClasses - 1 of them); class kLjClasses - 1 is all zero (padding
-// atoms).  Rows are kLjStride float2 apart so consecutive rows start in
-// different banks.  At 320 atoms and four waves per workgroup the position /
-// force stages and the per-wave tables of three workgroups fit one CU's LDS.
 // parameters per angle group: six angle pairs (k, theta0), four bonds (k_b, r0)
 constexpr int kAngPar = 20;
+// LJ class table of the wide layout: the pair coefficients of every pair of
+// distinct per-atom (sigma, epsilon) values (a molecule in the wide layout has
+// at most PAMD_WIDE_LJ_CLASSES of them).  A context sizes its tables to its
+// largest class count m: m + 1 rows (the last one all zero, for padding
+// atoms), an odd row stride so consecutive rows start in different banks;
+// every run's device table has room for the largest shape.
 constexpr int kLjClasses = PAMD_WIDE_LJ_CLASSES + 1;
 constexpr int kLjStride = kLjClasses + 1;
-static_assert(kLjStride % 2 == 1, "odd row stride: consecutive rows start in different banks");
+__host__ __device__ constexpr int lj_stride_of(int rows) { return rows | 1; }
 
 // Number of tile steps of the all-pairs schedule for `nslot` blocks of 16 atoms:
 // each diagonal block takes 8 row rotations (k = 1..8, k = 8 half-masked),
@@ -119,7 +119,9 @@ struct RunDev {
     // eps = 4r and 1 in vacuum, the LJ class table, and per (atom, 32-atom
     // chunk) the bit masks (excluded pair incl. self, scaled 1-4 pair)
     const float2* apar2;    // [n]
-    const float2* ljtab;    // [kLjClasses][kLjStride] (12 c12, -6 c6) of class pairs (a, b)
+    const float2* ljtab;    // [lj_pad + 1][lj_stride] (12 c12, -6 c6) of class pairs (a, b)
+    int32_t lj_stride;      // row stride of the class table (float2)
+    int32_t lj_pad;         // the all-zero class of padding atoms (last row)
     const uint2* pmask;     // [n][nchunk]
     const uint64_t* stepmask;   // [t][s] (5 x 5): bit k set when some lane of own slot s meets an
                                 // excluded or 1-4 partner of slot t at rotation step k

@@ -56,11 +56,12 @@ hipError_t launch_respa(const RunDev<float>& d, const float* fnn, int ops, uint3
                         uint32_t p24_outer, int blocks, int waves, hipStream_t s);
 hipError_t launch_export(const RunDev<float>& d, int64_t r0, int64_t count, float* xo, float* fo, int waves,
                          hipStream_t s);
-size_t wide_lds_bytes(int nmax, int waves);
-hipError_t wide_setup(int diel, int nmax, int waves, int* blocks_per_cu);
+size_t wide_lds_bytes(int nmax, int waves, int ljsz);
+hipError_t wide_setup(int diel, int nmax, int waves, int ljsz, int* blocks_per_cu);
 hipError_t launch_md_wide(const RunDev<float>* runs, const int32_t* order, int n_runs, int32_t* counter, int nmax,
-                          int n_steps, int diel, int lang, int blocks, int waves, hipStream_t s);
-hipError_t launch_forces_wide(const RunDev<float>& d, int64_t r0, int count, int nmax, int waves, hipStream_t s);
+                          int n_steps, int diel, int lang, int ljsz, int blocks, int waves, hipStream_t s);
+hipError_t launch_forces_wide(const RunDev<float>& d, int64_t r0, int count, int nmax, int waves, int ljsz,
+                              hipStream_t s);
 }  // namespace pamd
 
 using namespace pamd;
@@ -88,7 +89,7 @@ struct HostTables {
     int n = 0, npad = 0, nslot = 0;
     int wide = 0, nchunk = 0;
     std::vector<double> atomp;           // wide layout: [n][2] per-atom Coulomb factor and LJ class
-    std::vector<double> lj;              // wide layout: [kLjClasses][kLjStride][2] LJ class table
+    std::vector<double> lj;              // wide layout: [rows][lj_stride_of(rows)][2] LJ class table
     std::vector<uint32_t> pmask;         // wide layout: [n][nchunk][2] exclusion / 1-4 bits
     std::vector<uint64_t> stepmask;      // wide layout: [t][s] rotation steps that need the masks
     std::vector<double> ab, c;           // [steps][16][2], [steps][16]
@@ -131,6 +132,7 @@ struct pamd_ctx {
     int wide_waves = 0, wide_blocks = 0;
     size_t wide_lds = 0;
     int wide = 0, n_wide = 0, nmax = 0, diel = 0;   // wide: some run is wide; nmax: largest wide molecule
+    int lj_rows = 0;                   // LJ class-table rows of the wide runs (largest class count + 1)
     RunDev<float>* d_runs = nullptr;   // device copies of the runs' descriptors
     int32_t* d_order = nullptr;        // runs in decreasing pair work
     int32_t* d_counter = nullptr;      // work-queue counter
@@ -850,7 +852,7 @@ int pack_angle_groups(const pamd_system& s, int W, std::vector<int32_t>* rec, st
 // the diagonal block (rotations k = 1..8; k = 8 only on lanes 0..7), then for
 // k = 0..15 the blocks I < J.  Lane l of step (I, J, k) pairs atom 16 I + l
 // with atom 16 J + ((l - k) mod 16).
-void build_tables(const pamd_system& s, HostTables& t, int wide)
+void build_tables(const pamd_system& s, HostTables& t, int wide, int lj_rows)
 {
     const int n = s.n_atoms;
     t.n = n;
@@ -901,13 +903,14 @@ void build_tables(const pamd_system& s, HostTables& t, int wide)
         t.pmask.assign((size_t)n * t.nchunk * 2, 0u);
         std::vector<int> cls;
         lj_classes(s, &cls);
-        t.lj.assign((size_t)kLjClasses * kLjStride * 2, 0.0);
+        const int ljs = lj_stride_of(lj_rows);
+        t.lj.assign((size_t)lj_rows * ljs * 2, 0.0);
         for (int i = 0; i < n; ++i)
             for (int j = 0; j < n; ++j) {
                 const double sig = 0.5 * (s.sigma[i] + s.sigma[j]);
                 const double eps = sqrt(s.epsilon[i] * s.epsilon[j]);
                 const double s6 = pow(sig, 6.0);
-                const size_t e = ((size_t)cls[i] * kLjStride + cls[j]) * 2;
+                const size_t e = ((size_t)cls[i] * ljs + cls[j]) * 2;
                 t.lj[e] = 12.0 * 4.0 * eps * s6 * s6;
                 t.lj[e + 1] = -6.0 * 4.0 * eps * s6;
             }
@@ -1201,7 +1204,11 @@ static pamd_status init_runs(pamd_ctx* c, const pamd_system* sys, hipStream_t s)
 {
     for (int r = 0; r < c->n_runs; ++r) {
         Run& run = c->runs[r];
-        build_tables(sys[r], run.tab, c->fp32 ? run.f.wide : 0);
+        build_tables(sys[r], run.tab, c->fp32 ? run.f.wide : 0, c->lj_rows);
+        if (c->fp32 && run.f.wide) {
+            run.f.lj_stride = lj_stride_of(c->lj_rows);
+            run.f.lj_pad = c->lj_rows - 1;
+        }
         run.mtot = run.tab.mtot;
         HIPCHK(c, upload<real>(dev<real>(run), run.tab, s));
         HIPCHK(c, launch_init(dev<real>(run), s));
@@ -1277,18 +1284,25 @@ pamd_status pamd_init(const pamd_system* sys, int32_t n_runs, const pamd_params*
         if (c->wide && sys[r].dielectric != sys[0].dielectric)
             return fail(c, PAMD_ERR_ARG, "runs of a context with a batched launch must share the dielectric model");
     if (c->wide) {
+        // LJ class tables shaped for the largest class count of the wide runs
+        int lj_max = 1;
+        for (int r = 0; r < n_runs; ++r)
+            if (c->runs[r].f.wide)
+                lj_max = std::max(lj_max, lj_classes(sys[r], nullptr));
+        c->lj_rows = lj_max + 1;
+        const int ljsz = c->lj_rows * lj_stride_of(c->lj_rows);
         int waves = p[0].wide_waves_per_block;
         if (waves == 0)
             waves = 4;
-        while (waves > 1 && wide_lds_bytes(wn_max, waves) > (size_t)max_lds)
+        while (waves > 1 && wide_lds_bytes(wn_max, waves, ljsz) > (size_t)max_lds)
             --waves;
         int bpc = 0;
-        HIPCHK(c, wide_setup(c->diel, wn_max, waves, &bpc));
+        HIPCHK(c, wide_setup(c->diel, wn_max, waves, ljsz, &bpc));
         if (bpc < 1)
             return fail(c, PAMD_ERR_ARG, "batched MD kernel cannot be resident with this launch shape");
         c->wide_waves = waves;
         c->wide_blocks = c->n_cu * bpc;
-        c->wide_lds = wide_lds_bytes(wn_max, waves);
+        c->wide_lds = wide_lds_bytes(wn_max, waves, ljsz);
     }
     if (n_tile > 0) {
         int waves = p[0].waves_per_block;
@@ -1444,14 +1458,14 @@ pamd_status pamd_md_steps(pamd_ctx* c, int32_t n_steps, void* stream)
         }
         if (c->wide)
             HIPCHK(c, launch_md_wide(c->d_runs, c->d_order, c->n_wide, c->d_counter, c->nmax, n_steps, c->diel,
-                                     c->runs[0].f.thermostat == PAMD_THERMOSTAT_LANGEVIN, c->wide_blocks,
-                                     c->wide_waves, s));
+                                     c->runs[0].f.thermostat == PAMD_THERMOSTAT_LANGEVIN,
+                                     c->lj_rows * lj_stride_of(c->lj_rows), c->wide_blocks, c->wide_waves, s));
         return PAMD_OK;
     }
     if (c->wide)
         HIPCHK(c, launch_md_wide(c->d_runs, c->d_order, c->n_wide, c->d_counter, c->nmax, n_steps, c->diel,
-                                 c->runs[0].f.thermostat == PAMD_THERMOSTAT_LANGEVIN, c->wide_blocks, c->wide_waves,
-                                 s));
+                                 c->runs[0].f.thermostat == PAMD_THERMOSTAT_LANGEVIN,
+                                 c->lj_rows * lj_stride_of(c->lj_rows), c->wide_blocks, c->wide_waves, s));
     if (c->nn && n_steps > 0) {
         if (n_steps % c->mts_ratio != 0)
             return fail(c, PAMD_ERR_ARG, "n_steps must be a multiple of the r-RESPA outer ratio");
@@ -1540,7 +1554,8 @@ static pamd_status get_forces_t(pamd_ctx* c, Run& run, int64_t r0, int32_t count
     RunDev<real>& d = dev<real>(run);
     if constexpr (sizeof(real) == 4) {
         if (d.wide)
-            HIPCHK(c, launch_forces_wide(d, r0, count, c->nmax, c->wide_waves, s));
+            HIPCHK(c, launch_forces_wide(d, r0, count, c->nmax, c->wide_waves,
+                                         c->lj_rows * lj_stride_of(c->lj_rows), s));
         else
             HIPCHK(c, launch_forces(d, r0, count, c->tile_waves, s));
     } else {
