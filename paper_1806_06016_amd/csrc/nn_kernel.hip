@@ -218,11 +218,67 @@ __global__ __launch_bounds__(256) void k_nn_feat(Topo tp, ConfIO io, const float
 // fused MLP: per 64-row tile, energies e (FP32) and dE/dG (BF16).
 // Four waves; layer outputs are split over the waves by column, activations
 // pass through LDS (rows padded by 16 bytes against bank conflicts), weight
-// fragments come from the (L2-resident) BF16 copies.
+// fragments come from the (L2-resident) BF16 copies, kPf k-steps ahead of
+// their use: one k-step's MFMAs take a small fraction of an L2 round trip.
+// Every product is formed transposed (the weight fragment as the A operand),
+// so a lane's four accumulator values are four adjacent columns of one row:
+// bias and activation per column, one 8-byte LDS store per 16 x 16 tile, and
+// the row energy summed over the four lane groups of the row.
 // ---------------------------------------------------------------------------
 constexpr int kTM = 64;
 constexpr int kLdX = kFeat + 8;
 constexpr int kLdH = kH + 8;
+constexpr int kPf = 4;
+
+// Weight fragments of k-steps [K0, K1) of the CT column tiles starting at
+// output column c0 (WT: row = output column, ld elements, k contiguous).
+template <int KS, int CT, int K0, int K1>
+__device__ __forceinline__ void load_wfrag(uint4 (&b)[KS][CT], const uint16_t* WT, int ld, int c0, int l16, int g4)
+{
+    const uint16_t* p = WT + (size_t)(c0 + l16) * ld + 8 * g4;
+#pragma unroll
+    for (int ks = K0; ks < K1; ++ks)
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct)
+            b[ks][ct] = *reinterpret_cast<const uint4*>(p + (size_t)16 * ct * ld + 32 * ks);
+}
+
+// acc[rt][ct] = transposed tile (columns c0 + 16 ct + 4 g4 + e of row 16 rt + l16)
+// of X W, X: 64 x 32 KS from LDS (row-major, ldx); the caller has loaded the
+// fragments of the first kPf k-steps into b.
+template <int KS, int CT>
+__device__ __forceinline__ void layer_mfma(f32x4 (&acc)[4][CT], uint4 (&b)[KS][CT], const uint16_t* X, int ldx,
+                                           const uint16_t* WT, int ld, int c0, int l16, int g4)
+{
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct)
+            acc[rt][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const uint16_t* p = WT + (size_t)(c0 + l16) * ld + 8 * g4;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+        if (ks + kPf < KS) {
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct)
+                b[ks + kPf < KS ? ks + kPf : ks][ct] =
+                    *reinterpret_cast<const uint4*>(p + (size_t)16 * ct * ld + 32 * (ks + kPf));
+        }
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) {
+            const uint4 a = *reinterpret_cast<const uint4*>(X + (16 * rt + l16) * ldx + 32 * ks + 8 * g4);
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct)
+                acc[rt][ct] = mfma(b[ks][ct], a, acc[rt][ct]);
+        }
+    }
+}
+
+// four adjacent BF16 values, one 8-byte LDS store
+__device__ __forceinline__ void st4(uint16_t* p, float a, float b, float c, float d)
+{
+    *reinterpret_cast<uint2*>(p) = uint2{pack2(a, b), pack2(c, d)};
+}
 
 __global__ __launch_bounds__(256, 3) void k_nn_mlp(Weights w, const uint16_t* G, uint16_t* gG, float* e_out,
                                                 const RunCtl* ctl, int64_t rows_fixed, int n)
@@ -239,7 +295,13 @@ __global__ __launch_bounds__(256, 3) void k_nn_mlp(Weights w, const uint16_t* G,
         return;
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63, l16 = lane & 15, g4 = lane >> 4;
+    // this wave's output columns: 32 wave .. 32 wave + 31 of the hidden
+    // layers, 64 wave .. 64 wave + 63 of dE/dG; c4: a lane's first column
+    // within a 16-column tile
+    const int c1 = 32 * wave, c4 = 4 * g4;
 
+    uint4 b1f[kFeat / 32][2];
+    load_wfrag<kFeat / 32, 2, 0, kPf>(b1f, w.W1T, kFeat, c1, l16, g4);
     {
         // all eight 16-byte loads of this thread in flight before the first LDS store
         uint4 v[kTM * 32 / 256];
@@ -258,138 +320,85 @@ __global__ __launch_bounds__(256, 3) void k_nn_mlp(Weights w, const uint16_t* G,
     }
     __syncthreads();
 
-    // layer 1: h1 = G W1 + b1, this wave's columns 32 wave .. 32 wave + 31
+    // layer 1: h1 = G W1 + b1; a1 = silu(h1) to Ys, s1 = silu'(h1) kept
     float s1[4][2][4];
+    uint4 b2f[kH / 32][2];
     {
         f32x4 acc[4][2];
-#pragma unroll
-        for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-            for (int ct = 0; ct < 2; ++ct)
-                acc[rt][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int ks = 0; ks < kFeat / 32; ++ks) {
-            uint4 b[2];
-#pragma unroll
-            for (int ct = 0; ct < 2; ++ct)
-                b[ct] = *reinterpret_cast<const uint4*>(w.W1T + (size_t)(32 * wave + 16 * ct + l16) * kFeat + 32 * ks +
-                                                        8 * g4);
-#pragma unroll
-            for (int rt = 0; rt < 4; ++rt) {
-                const uint4 a = *reinterpret_cast<const uint4*>(Xs + (16 * rt + l16) * kLdX + 32 * ks + 8 * g4);
-#pragma unroll
-                for (int ct = 0; ct < 2; ++ct)
-                    acc[rt][ct] = mfma(a, b[ct], acc[rt][ct]);
-            }
-        }
+        layer_mfma<kFeat / 32, 2>(acc, b1f, Xs, kLdX, w.W1T, kFeat, c1, l16, g4);
+        load_wfrag<kH / 32, 2, 0, kPf>(b2f, w.W2T, kH, c1, l16, g4);
 #pragma unroll
         for (int ct = 0; ct < 2; ++ct) {
-            const int col = 32 * wave + 16 * ct + l16;
-            const float bias = w.b1[col];
+            const int col = c1 + 16 * ct + c4;
+            float bias[4], a1[4];
 #pragma unroll
-            for (int rt = 0; rt < 4; ++rt)
+            for (int e = 0; e < 4; ++e)
+                bias[e] = w.b1[col + e];
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int row = 16 * rt + 4 * g4 + e;
-                    float a1;
-                    silu_d(acc[rt][ct][e] + bias, a1, s1[rt][ct][e]);
-                    Ys[row * kLdH + col] = (uint16_t)bf16_bits(a1);
-                }
+            for (int rt = 0; rt < 4; ++rt) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    silu_d(acc[rt][ct][e] + bias[e], a1[e], s1[rt][ct][e]);
+                st4(Ys + (16 * rt + l16) * kLdH + col, a1[0], a1[1], a1[2], a1[3]);
+            }
         }
     }
     __syncthreads();
 
-    // layer 2: h2 = a1 W2 + b2; e partial = a2 . w3; g2 = w3 silu'(h2)
+    // layer 2: h2 = a1 W2 + b2; e partial = a2 . w3; g2 = w3 silu'(h2) to Zs
+    uint4 b3f[kH / 32][2];
     {
         f32x4 acc[4][2];
-#pragma unroll
-        for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-            for (int ct = 0; ct < 2; ++ct)
-                acc[rt][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int ks = 0; ks < kH / 32; ++ks) {
-            uint4 b[2];
-#pragma unroll
-            for (int ct = 0; ct < 2; ++ct)
-                b[ct] = *reinterpret_cast<const uint4*>(w.W2T + (size_t)(32 * wave + 16 * ct + l16) * kH + 32 * ks +
-                                                        8 * g4);
-#pragma unroll
-            for (int rt = 0; rt < 4; ++rt) {
-                const uint4 a = *reinterpret_cast<const uint4*>(Ys + (16 * rt + l16) * kLdH + 32 * ks + 8 * g4);
-#pragma unroll
-                for (int ct = 0; ct < 2; ++ct)
-                    acc[rt][ct] = mfma(a, b[ct], acc[rt][ct]);
-            }
-        }
-        float ep[4][4];
-#pragma unroll
-        for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-                ep[rt][e] = 0.f;
+        layer_mfma<kH / 32, 2>(acc, b2f, Ys, kLdH, w.W2T, kH, c1, l16, g4);
+        load_wfrag<kH / 32, 2, 0, kPf>(b3f, w.W2, kH, c1, l16, g4);
+        float ep[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int ct = 0; ct < 2; ++ct) {
-            const int col = 32 * wave + 16 * ct + l16;
-            const float bias = w.b2[col], w3c = w.w3[col];
-#pragma unroll
-            for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int row = 16 * rt + 4 * g4 + e;
-                    float a2, s2;
-                    silu_d(acc[rt][ct][e] + bias, a2, s2);
-                    ep[rt][e] += a2 * w3c;
-                    Zs[row * kLdH + col] = (uint16_t)bf16_bits(w3c * s2);
-                }
-        }
-#pragma unroll
-        for (int rt = 0; rt < 4; ++rt)
+            const int col = c1 + 16 * ct + c4;
+            float bias[4], w3c[4], g2[4];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                float v = ep[rt][e];
-#pragma unroll
-                for (int o = 8; o >= 1; o >>= 1)
-                    v += __shfl_xor(v, o, 16);
-                if (l16 == 0)
-                    es[wave][16 * rt + 4 * g4 + e] = v;
+                bias[e] = w.b2[col + e];
+                w3c[e] = w.w3[col + e];
             }
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    float a2, s2;
+                    silu_d(acc[rt][ct][e] + bias[e], a2, s2);
+                    ep[rt] = fmaf(a2, w3c[e], ep[rt]);
+                    g2[e] = w3c[e] * s2;
+                }
+                st4(Zs + (16 * rt + l16) * kLdH + col, g2[0], g2[1], g2[2], g2[3]);
+            }
+        }
+        // the row's 32 columns of this wave sit in the four lane groups
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) {
+            float v = ep[rt];
+            v += __shfl_xor(v, 16);
+            v += __shfl_xor(v, 32);
+            if (g4 == 0)
+                es[wave][16 * rt + l16] = v;
+        }
     }
     __syncthreads();
 
     // g1 = (g2 W2^T) * silu'(h1): the same columns as this wave's layer-1 output
+    const int c2 = 64 * wave;
+    uint4 b4f[kH / 32][4];
     {
         f32x4 acc[4][2];
-#pragma unroll
-        for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-            for (int ct = 0; ct < 2; ++ct)
-                acc[rt][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int ks = 0; ks < kH / 32; ++ks) {
-            uint4 b[2];
-#pragma unroll
-            for (int ct = 0; ct < 2; ++ct)
-                b[ct] = *reinterpret_cast<const uint4*>(w.W2 + (size_t)(32 * wave + 16 * ct + l16) * kH + 32 * ks +
-                                                        8 * g4);
-#pragma unroll
-            for (int rt = 0; rt < 4; ++rt) {
-                const uint4 a = *reinterpret_cast<const uint4*>(Zs + (16 * rt + l16) * kLdH + 32 * ks + 8 * g4);
-#pragma unroll
-                for (int ct = 0; ct < 2; ++ct)
-                    acc[rt][ct] = mfma(a, b[ct], acc[rt][ct]);
-            }
-        }
+        layer_mfma<kH / 32, 2>(acc, b3f, Zs, kLdH, w.W2, kH, c1, l16, g4);
+        load_wfrag<kH / 32, 4, 0, kPf>(b4f, w.W1, kH, c2, l16, g4);
 #pragma unroll
         for (int ct = 0; ct < 2; ++ct) {
-            const int col = 32 * wave + 16 * ct + l16;
+            const int col = c1 + 16 * ct + c4;
 #pragma unroll
             for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int row = 16 * rt + 4 * g4 + e;
-                    Ys[row * kLdH + col] = (uint16_t)bf16_bits(acc[rt][ct][e] * s1[rt][ct][e]);
-                }
+                st4(Ys + (16 * rt + l16) * kLdH + col, acc[rt][ct][0] * s1[rt][ct][0], acc[rt][ct][1] * s1[rt][ct][1],
+                    acc[rt][ct][2] * s1[rt][ct][2], acc[rt][ct][3] * s1[rt][ct][3]);
         }
     }
     __syncthreads();
@@ -397,34 +406,14 @@ __global__ __launch_bounds__(256, 3) void k_nn_mlp(Weights w, const uint16_t* G,
     // dE/dG = g1 W1^T: this wave's columns 64 wave .. 64 wave + 63, staged in Xs
     {
         f32x4 acc[4][4];
-#pragma unroll
-        for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-            for (int ct = 0; ct < 4; ++ct)
-                acc[rt][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int ks = 0; ks < kH / 32; ++ks) {
-            uint4 b[4];
-#pragma unroll
-            for (int ct = 0; ct < 4; ++ct)
-                b[ct] = *reinterpret_cast<const uint4*>(w.W1 + (size_t)(64 * wave + 16 * ct + l16) * kH + 32 * ks +
-                                                        8 * g4);
-#pragma unroll
-            for (int rt = 0; rt < 4; ++rt) {
-                const uint4 a = *reinterpret_cast<const uint4*>(Ys + (16 * rt + l16) * kLdH + 32 * ks + 8 * g4);
-#pragma unroll
-                for (int ct = 0; ct < 4; ++ct)
-                    acc[rt][ct] = mfma(a, b[ct], acc[rt][ct]);
-            }
-        }
+        layer_mfma<kH / 32, 4>(acc, b4f, Ys, kLdH, w.W1, kH, c2, l16, g4);
 #pragma unroll
         for (int ct = 0; ct < 4; ++ct) {
-            const int col = 64 * wave + 16 * ct + l16;
+            const int col = c2 + 16 * ct + c4;
 #pragma unroll
             for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    Xs[(16 * rt + 4 * g4 + e) * kLdX + col] = (uint16_t)bf16_bits(acc[rt][ct][e]);
+                st4(Xs + (16 * rt + l16) * kLdX + col, acc[rt][ct][0], acc[rt][ct][1], acc[rt][ct][2],
+                    acc[rt][ct][3]);
         }
     }
     __syncthreads();
