@@ -6,7 +6,7 @@ generates (a 2000-replica population annealed 700 -> 300 K, snapshots every
 250 steps).  With F_NN = 0 the outer impulse of r-RESPA carries the whole
 nonbonded force (relative residual 1); the trained network must cut the
 held-out residual |F_nb - F_NN| / |F_nb| below 0.5 and keep a 4 fs outer step
-stable over 1 ps of NVE dynamics.  Plain velocity Verlet stays the judge of
+stable over 1 ps of NVE dynamics.  Plain velocity Verlet stays the reference for
 the r-RESPA runs: annealed <E_pot>(T) with the trained surrogate (outer step
 2 fs) agrees with plain velocity Verlet (1 fs) under the covariance-aware
 rule of energy_curve_stats (8 + 8 independently seeded runs of a reduced
@@ -51,7 +51,7 @@ def test_trained_surrogate_reduces_the_outer_impulse(B):
     d = mts.nve_run(sysd, x0, v0, 0.001, nn, 4, window_ps=1.0, sample_ps=0.1)
     print("r-RESPA 4 fs with the trained surrogate:", d)
     assert not d["unstable"] and math.isfinite(d["rms_drift_kJmol"])
-    # plain MD as the judge: annealed <E_pot>(T), r-RESPA + surrogate against velocity Verlet
+    # plain MD as the reference: annealed <E_pot>(T), r-RESPA + surrogate against velocity Verlet
     sched = S.geometric_schedule(700.0, 500.0, 9)
     print("annealing: plain velocity Verlet and r-RESPA with the trained surrogate, 8 + 8 runs", flush=True)
     vv = np.array([mts.anneal_curve(sysd, 300, sched, 160, 400, seed) for seed in range(1, 9)])
