@@ -139,8 +139,10 @@ struct pamd_ctx {
     // the register-tile runs of a context with several of them run on side
     // streams forked from and joined back to the caller's stream, so their
     // persistent launches (each latency-bound on a fraction of the CUs for a
-    // small population) overlap; the wide launch follows the join, since a
-    // persistent wide launch that reaches the CUs first would hold them
+    // small population) overlap; the wide launch goes on the caller's stream
+    // after the fork and before the join: its workgroups take the CUs the
+    // tile launches leave free and, through its work queue, the rest as those
+    // finish
     static constexpr int kSide = 3;
     int n_side = 0;
     hipStream_t side[kSide] = {};
@@ -1435,8 +1437,8 @@ pamd_status pamd_md_steps(pamd_ctx* c, int32_t n_steps, void* stream)
     c->have_energy = 1;
     hipStream_t s = as_stream(stream);
     if (c->n_side > 0 && !(c->nn && n_steps > 0)) {
-        // fork: the register-tile runs round robin over the side streams; join
-        // every side stream back, then the wide launch on `s`
+        // fork: the register-tile runs round robin over the side streams, the
+        // wide launch on `s` next to them, then every side stream joined back
         HIPCHK(c, hipEventRecord(c->ev_fork, s));
         int used = 0, k = 0;
         for (auto& run : c->runs) {
@@ -1452,14 +1454,14 @@ pamd_status pamd_md_steps(pamd_ctx* c, int32_t n_steps, void* stream)
                 return st;
             k = (k + 1) % c->n_side;
         }
-        for (int q = 0; q < used; ++q) {
-            HIPCHK(c, hipEventRecord(c->ev_join[q], c->side[q]));
-            HIPCHK(c, hipStreamWaitEvent(s, c->ev_join[q], 0));
-        }
         if (c->wide)
             HIPCHK(c, launch_md_wide(c->d_runs, c->d_order, c->n_wide, c->d_counter, c->nmax, n_steps, c->diel,
                                      c->runs[0].f.thermostat == PAMD_THERMOSTAT_LANGEVIN,
                                      c->lj_rows * lj_stride_of(c->lj_rows), c->wide_blocks, c->wide_waves, s));
+        for (int q = 0; q < used; ++q) {
+            HIPCHK(c, hipEventRecord(c->ev_join[q], c->side[q]));
+            HIPCHK(c, hipStreamWaitEvent(s, c->ev_join[q], 0));
+        }
         return PAMD_OK;
     }
     if (c->wide)
