@@ -3,8 +3,9 @@
 //
 //   features   G[i, t, k] = sum over partners j of type t of
 //              phi_k(r_ij) = exp(-(r_ij - mu_k)^2 / (2 s^2))  (VALU, one lane
-//              per (configuration, atom) row, Gaussians by a two-exponential
-//              recurrence in chunks of 8)
+//              per (configuration, atom) row, Gaussians by a multiplicative
+//              recurrence in chunks of 8: one exponential per chunk and one
+//              per pair)
 //   MLP        E_i = w3 . silu(W2^T silu(W1^T G_i + b1) + b2) + b3 and its
 //              input gradient dE_i/dG_i, fused in one kernel per 64-row tile
 //              (BF16 MFMA 16x16x32, FP32 accumulate, activations in LDS)
@@ -73,28 +74,34 @@ __device__ __forceinline__ void silu_dd(float h, float& a, float& d1, float& d2)
 constexpr float kL2e = 1.44269504088896341f;   // log2(e)
 
 // phi_k(r) = exp(-u_k^2 / 2), u_k = (r - mu_k) / s = u_0 - k, in chunks of 8:
-//   phi_{k0+e} = P_e C_e,  P_0 = exp(-u_c^2 / 2),  P_{e+1} = P_e exp(u_c),
-//   C_e = exp(-e^2 / 2),  u_c = u_0 - k0.
-// body(k, e, P_e) folds C_e into its multiply-add.  Each chunk restarts from
-// two exponentials, so a chunk cannot underflow before its values matter;
-// u_c is clamped to +-40, where the chunk's values are below 1e-100 and the
-// products stay finite (P_e <= exp(e^2 / 2) <= 4.4e10).
+//   phi_{k0+e} = P_e C_e,  P_0 = exp(-u_c^2 / 2),  P_{e+1} = P_e q,
+//   q = exp(u_c),  C_e = exp(-e^2 / 2),  u_c = u_0 - k0.
+// body(k, e, P_e) folds C_e into its multiply-add.  Each chunk restarts P_0
+// from an exponential, so a chunk cannot underflow before its values matter;
+// q comes from an exponential in the first chunk and from the previous
+// chunk's q times exp(-8) after it (u_c falls by 8 per chunk).  u_0 >= -mu_0 / s
+// > -40 for every distance, and u_c is clamped to 40: where it is, the
+// chunk's values are below 1e-100, P_0 is 0 in FP32 and every q stays finite
+// (below exp(40)); elsewhere q = exp(u_c) and the products stay finite
+// (P_e <= exp(e^2 / 2) <= 4.4e10).
 constexpr float kGauss[8] = {1.0f, 0.60653066f, 0.135335283f, 0.0111089965f,
                              0.000335462628f, 3.72665317e-06f, 1.52299797e-08f, 2.28973485e-11f};
+constexpr float kExpM8 = 3.35462628e-04f;   // exp(-8)
 
 template <typename Body>
 __device__ __forceinline__ void rbf_chunks(float u0, Body&& body)
 {
+    float q = __builtin_amdgcn_exp2f(kL2e * fminf(fmaxf(u0, -40.f), 40.f));
 #pragma unroll
     for (int ch = 0; ch < kRbf / 8; ++ch) {
         const float uc = fminf(fmaxf(u0 - (float)(8 * ch), -40.f), 40.f);
         float P = __builtin_amdgcn_exp2f(-0.5f * kL2e * uc * uc);
-        const float q = __builtin_amdgcn_exp2f(kL2e * uc);
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             body(8 * ch + e, e, P);
             P *= q;
         }
+        q *= kExpM8;
     }
 }
 
