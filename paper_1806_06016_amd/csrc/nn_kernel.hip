@@ -229,7 +229,7 @@ __global__ __launch_bounds__(256) void k_nn_feat(Topo tp, ConfIO io, const float
 // their use: one k-step's MFMAs take a small fraction of an L2 round trip.
 // Every product is formed transposed (the weight fragment as the A operand),
 // so a lane's four accumulator values are four adjacent columns of one row:
-// bias and activation per column, one 8-byte LDS store per 16 x 16 tile, and
+// bias and activation per column, one 8-byte LDS store per lane and tile, and
 // the row energy summed over the four lane groups of the row.
 // ---------------------------------------------------------------------------
 constexpr int kTM = 64;
